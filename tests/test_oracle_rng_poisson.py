@@ -1,0 +1,118 @@
+"""Pins of the oracle's random stream and Poisson counts.
+
+Philox4x32-10 is pinned to the published known-answer vectors; the uniform
+mapping to its definition; the per-segment Poisson draw to scipy's Poisson
+quantile function (single chunk) and to the Poisson moments and pmf (chunked).
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+
+
+def _kat_rows():
+    rows = []
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        v = [int(x, 16) for x in line.split()]
+        rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers(oracle):
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for ctr, key, expect in rows:
+        got = oracle.philox(np.array([ctr], dtype=np.uint32), key)[0]
+        assert [int(x) for x in got] == expect
+
+
+def test_uniform_mapping_endpoints(oracle):
+    u = oracle.uniform([0, 1, 2**31, 2**32 - 1])
+    assert u[0] == 0.5 / 2**32
+    assert u[1] == 1.5 / 2**32
+    assert u[2] == 0.5 + 0.5 / 2**32
+    assert u[3] == (2**32 - 0.5) / 2**32
+    assert np.all((u > 0) & (u < 1))
+
+
+def test_philox_stream_is_uniform(oracle):
+    n = 20000
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = np.arange(n)
+    ctr[:, 1] = 7
+    ctr[:, 3] = 1
+    w = oracle.philox(ctr, [12345, 678])
+    u = (w.astype(np.float64) + 0.5) / 2**32
+    for col in range(4):
+        assert stats.kstest(u[:, col], "uniform").pvalue > 1e-4
+    # words of one block are uncorrelated
+    c = np.corrcoef(u.T)
+    assert np.max(np.abs(c - np.eye(4))) < 0.04
+
+
+def _count_uniform(oracle, seed, chunk, idx, shower):
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    w = oracle.philox(np.array([[chunk, idx, shower, 0]], np.uint32), key)[0, 0]
+    return (float(w) + 0.5) / 2**32
+
+
+@pytest.mark.parametrize("mu", [0.3, 2.5, 17.0, 64.0, 127.9, 128.0])
+def test_poisson_single_chunk_is_scipy_quantile(oracle, mu):
+    """For mu <= 128 the count is the Poisson quantile of the COUNT-stream
+    uniform: the smallest k with F(k) >= u (scipy.stats.poisson.ppf)."""
+    seed = 0x1234_5678_9ABC
+    mismatches = 0
+    for idx in range(300):
+        k, margin = oracle.poisson(mu, seed, idx, 3)
+        u = _count_uniform(oracle, seed, 0, idx, 3)
+        ref = int(stats.poisson.ppf(u, mu))
+        if k != ref:
+            assert margin < 1e-12, (mu, idx, k, ref, margin)
+            mismatches += 1
+    assert mismatches <= 1
+
+
+def test_poisson_zero_and_negative_mean(oracle):
+    assert oracle.poisson(0.0, 1, 0, 0)[0] == 0
+    assert oracle.poisson(-3.0, 1, 0, 0)[0] == 0
+
+
+@pytest.mark.parametrize("mu", [300.0, 1255.0])
+def test_poisson_chunked_moments_and_pmf(oracle, mu):
+    """Chunked draws (m = ceil(mu/128) chunks) follow Poisson(mu)."""
+    seed = 99
+    draws = np.array([oracle.poisson(mu, seed, i, 0)[0] for i in range(6000)])
+    n = len(draws)
+    # mean and variance within 5 standard errors
+    assert abs(draws.mean() - mu) < 5 * np.sqrt(mu / n)
+    var_se = mu * np.sqrt(2.0 / n)
+    assert abs(draws.var(ddof=1) - mu) < 5 * var_se
+    # chi-square against the Poisson pmf on central bins
+    lo, hi = int(mu - 3 * np.sqrt(mu)), int(mu + 3 * np.sqrt(mu))
+    edges = np.linspace(lo, hi, 13).astype(int)
+    obs = np.histogram(draws, bins=edges)[0]
+    cdf = stats.poisson.cdf(edges - 1, mu)
+    exp = n * np.diff(cdf)
+    chi2 = ((obs - exp) ** 2 / exp).sum()
+    assert stats.chi2.sf(chi2, len(obs) - 1) > 1e-4
+
+
+def test_counts_use_segment_ids_not_positions(oracle):
+    """Counts depend on (shower, index_in_shower), so any subset or order of
+    segments gives the same per-segment counts."""
+    from paper_2309_15861_amd import workloads as W
+
+    atm = oracle.Atmosphere.from_dict(W.default_atmosphere())
+    seg = W.plain_cherenkov(200, seed=11)
+    c_all = oracle.counts(seg, atm, "cherenkov", 5)[0]
+    perm = np.random.default_rng(0).permutation(200)[:77]
+    c_sub = oracle.counts(W.subsample(seg, perm), atm, "cherenkov", 5)[0]
+    assert np.array_equal(c_all[perm], c_sub)
+    c_other = oracle.counts(seg, atm, "cherenkov", 6)[0]
+    assert not np.array_equal(c_all, c_other)
