@@ -1,0 +1,261 @@
+/*
+ * photon.h -- C ABI of the MI355X optical-photon library (libphoton.so).
+ *
+ * The library computes, for charged-particle track segments, the optical
+ * photons of the method of Baack & Alameddine, "Comparison and efficiency of
+ * GPU accelerated optical light propagation in CORSIKA 8" (ICRC2023,
+ * arXiv:2309.15861):
+ *   - Cherenkov photon numbers from the Frank-Tamm formula (section 1.2) and
+ *     fluorescence photon numbers from dN/dx = Y dE/dx (section 1.1),
+ *     Poisson-sampled per segment;
+ *   - Cherenkov photons on the cone cos(theta) = 1/(beta n), generated
+ *     downward, rotated by M_Rod into the track frame and moved to their
+ *     emission point (section 1.2, Fig. 1, section 1.2.1); isotropic
+ *     fluorescence photons on emission lines (section 1.1);
+ *   - propagation to the observation level through a plane-parallel layered
+ *     exponential atmosphere, n(h) = 1 + (n0 - 1) rho(h)/rho0, with
+ *     refraction, arrival time and absorption (section 2);
+ *   - collection on telescope spheres or a ground grid.
+ *
+ * Conventions shared by every call:
+ *   - z is the altitude above sea level [m], z points up; times in ns;
+ *     wavelengths in nm; c = 0.299792458 m/ns.
+ *   - Pointers named "device" are HIP device pointers owned by the caller;
+ *     the library never frees or keeps them. Structs passed by pointer are
+ *     host memory, read during the call only.
+ *   - Every call validates its arguments on the host before any HIP call,
+ *     then enqueues its kernels on `stream` (a hipStream_t; NULL = the null
+ *     stream) and returns without synchronising.
+ *   - Return value: PHOTON_OK (0) or a negative error code; the message of
+ *     the last error of the calling thread is photon_last_error().
+ *   - Randomness: Philox4x32-10 (Salmon et al., SC'11) with key = seed and
+ *     counter (j or chunk, index_in_shower, shower, domain); results are a
+ *     pure function of (inputs, seed), independent of batching and of the
+ *     order of segments.
+ *   - The library allocates one small device work area per device (a few
+ *     bytes of counters) on its first use on that device; photon_init()
+ *     creates it up front (needed before stream capture).
+ */
+#ifndef PHOTON_H
+#define PHOTON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define PHOTON_OK 0
+#define PHOTON_EINVAL (-1)      /* invalid argument (message says which)   */
+#define PHOTON_ECAPACITY (-2)   /* output buffer too small                 */
+#define PHOTON_EHIP (-3)        /* a HIP runtime call failed               */
+#define PHOTON_ENODEV (-4)      /* no usable gfx950 device                 */
+
+/* ---- precision --------------------------------------------------------- */
+#define PHOTON_FP64 0           /* all arithmetic in double                 */
+#define PHOTON_FP32 1           /* generation and bending in float; time,
+                                   path and near-horizon pieces in double  */
+
+/* ---- emission kinds ------------------------------------------------------ */
+#define PHOTON_CHERENKOV 0
+#define PHOTON_FLUORESCENCE 1
+
+/* ---- per-photon status -------------------------------------------------- */
+#define PHOTON_LANDED 0         /* reached the observation level            */
+#define PHOTON_HIT 1            /* landed and hit a telescope sphere        */
+#define PHOTON_UP 2             /* emitted with u_z >= 0: never lands        */
+#define PHOTON_BELOW 3          /* emitted below the observation level      */
+#define PHOTON_OFFGRID 4        /* landed outside the ground grid           */
+#define PHOTON_INVALID 6        /* slot without a valid segment             */
+#define PHOTON_N_STATUS 8
+
+/* ---- sink kinds ---------------------------------------------------------- */
+#define PHOTON_SINK_STATUS 0    /* per-status photon totals only            */
+#define PHOTON_SINK_TELESCOPES 1
+#define PHOTON_SINK_GRID 2
+
+#define PHOTON_MAX_LAYERS 8
+#define PHOTON_MAX_ABS 40
+#define PHOTON_MAX_LINES 32
+#define PHOTON_MAX_TELESCOPES 32
+
+/* Plane-parallel atmosphere (host struct). Layer i covers
+   [h_base[i], h_base[i+1]); layer 0 extends below h_base[0] = 0 and the top
+   layer has no upper bound. rho/rho0 is continuous, equals 1 at h = 0 and
+   falls as exp(-h/scale_height[i]) inside layer i (scale_height = +inf:
+   constant density). n(h) = 1 + n0_minus_1 * rho(h)/rho0. Absorption
+   coefficient k(lambda) * rho/rho0 [1/m], k piecewise linear in lambda
+   between the table nodes and clamped outside; n_abs = 0: no absorption.
+   Errors: n_layers outside 1..8, h_base[0] != 0 or not strictly increasing,
+   scale_height <= 0 or NaN, n0_minus_1 < 0 or not finite, h_obs not finite,
+   n_abs outside 0..40, abs_lambda_nm not strictly increasing, abs_k < 0. */
+typedef struct {
+  int32_t n_layers;
+  double h_base[PHOTON_MAX_LAYERS];
+  double scale_height[PHOTON_MAX_LAYERS];
+  double n0_minus_1;
+  double h_obs;
+  int32_t n_abs;
+  double abs_lambda_nm[PHOTON_MAX_ABS];
+  double abs_k_per_m[PHOTON_MAX_ABS];
+} photon_atmosphere;
+
+/* Track segments, structure of arrays of length n (device pointers).
+   Start point (x0,y0,z0) [m], direction (dx,dy,dz) (normalised inside),
+   length [m], speed beta in (0,1), start time t0 [ns], energy loss dedx
+   [MeV/m] (fluorescence only), charge number (NULL: |z| = 1), shower id
+   (NULL: 0) and index of the segment in its shower (NULL: the row number);
+   the last two are Philox counter words. A segment with a non-finite field,
+   beta outside (0,1), negative length or zero direction emits no photons. */
+typedef struct {
+  int64_t n;
+  const double *x0, *y0, *z0, *dx, *dy, *dz, *length, *beta, *t0;
+  const double *dedx;
+  const int32_t *charge;
+  const uint32_t *shower;
+  const uint32_t *index_in_shower;
+} photon_segments;
+
+/* Emission model (host struct).
+   Cherenkov: wavelength band [lambda_min_nm, lambda_max_nm], 0 < min < max.
+   Fluorescence: total yield [photons/MeV] >= 0 and n_lines (1..32) lines
+   with wavelengths line_nm and relative yields line_rel_yield (>= 0, not
+   all zero); a photon takes line k with probability rel[k]/sum(rel). */
+typedef struct {
+  int32_t kind;                       /* PHOTON_CHERENKOV / PHOTON_FLUORESCENCE */
+  double lambda_min_nm, lambda_max_nm;
+  double yield_per_MeV;
+  int32_t n_lines;
+  double line_nm[PHOTON_MAX_LINES];
+  double line_rel_yield[PHOTON_MAX_LINES];
+} photon_emission;
+
+/* The common photon block (section 1: photons of both generators are
+   written to one memory block and processed downstream), structure of
+   arrays with `capacity` slots (device pointers). Slot q holds photon j of
+   segment `segment[q]`, with q = offsets[segment] + j. Position, direction,
+   wavelength and weight are double (PHOTON_FP64) or float (PHOTON_FP32);
+   time and path length are double in both. After generation: emission point,
+   time and direction, path 0, weight 1, status LANDED (or INVALID). After
+   propagation: landing point (z = h_obs), arrival time, arrival direction,
+   geometric path length, transmission weight exp(-tau) and status. */
+typedef struct {
+  int64_t capacity;
+  int64_t n_photons;                  /* slots in use = offsets[n]          */
+  int32_t precision;
+  void *x, *y, *z, *ux, *uy, *uz, *wavelength_nm, *weight;
+  double *t_ns, *path_m;
+  uint32_t *segment, *j;
+  int32_t *status;
+} photon_block;
+
+/* Telescope hit records, appended in arbitrary order (device pointers).
+   *count (device) is incremented once per hit; records beyond capacity
+   are dropped but still counted, so *count > capacity signals overflow. */
+typedef struct {
+  int64_t capacity;
+  unsigned long long *count;
+  uint32_t *segment, *j;
+  int32_t *telescope;
+  double *x, *y, *z, *t_ns;           /* entry point on the sphere and time  */
+  float *ux, *uy, *uz, *wavelength_nm, *weight;
+} photon_hits;
+
+/* Where photons are collected (host struct). Outputs accumulate: the caller
+   clears them. status_totals (device, 8 x u64, may be NULL) receives the
+   number of photons per status. TELESCOPES: spheres (x,y,z,R) [m]; a
+   landed photon hits when the straight line through its landing point
+   along its arrival direction meets a sphere; the entry point of the first
+   sphere along the ray is recorded with time t + n_obs * s / c (s the
+   signed distance from the landing point). GRID: nx * ny cells of size
+   `cell` from (x_min, y_min), half-open; grid_count[iy*nx+ix] counts landed
+   photons, grid_weight the sum of their weights in units of 2^-32. */
+typedef struct {
+  int32_t kind;
+  unsigned long long *status_totals;
+  int32_t n_tel;
+  double tel[PHOTON_MAX_TELESCOPES][4];
+  photon_hits hits;
+  double x_min, y_min, cell;
+  int32_t nx, ny;
+  uint32_t *grid_count;
+  unsigned long long *grid_weight;
+} photon_sink;
+
+/* Launch shape of the fused kernel: threads per block (64..1024, multiple
+   of 64), photons per work chunk (multiple of block), blocks per CU
+   (0 = as many as fit). NULL = defaults. */
+typedef struct {
+  int32_t block;
+  int32_t chunk;
+  int32_t blocks_per_cu;
+} photon_tuning;
+
+/* Creates the per-device work area on the current device. Optional;
+   returns PHOTON_ENODEV without a gfx950 device. */
+int photon_init(void);
+
+/* Version string and the message of the calling thread's last error. */
+const char* photon_version(void);
+const char* photon_last_error(void);
+
+/* Cherenkov generation (section 1.2). With out == NULL: per-segment mean
+   from the Frank-Tamm formula with n taken at the segment midpoint and
+   constant along it, mu = 2 pi alpha z^2 (1/lambda_min - 1/lambda_max) L
+   (1 - 1/(beta n)^2) for beta n > 1, else 0; Poisson count by sequential
+   inverse CDF in chunks of mean <= 128 on the COUNT stream -> counts[n]
+   (device u32); exclusive prefix sums -> offsets[n+1] (device u64,
+   offsets[n] = total). With out != NULL: fills slots [0, out->n_photons)
+   from the given offsets (which must come from a call with out == NULL):
+   cone angle cos = 1/(beta n), azimuth 2 pi u1, photon vector of section
+   1.2.1 rotated by M_Rod about the bisector of the track direction and
+   (0,0,-1), emission point u0 along the track, time t0 + s/(beta c),
+   wavelength from the 1/lambda^2 spectrum. Errors: EINVAL (NULL pointer,
+   n < 0, band, atmosphere, precision, n_photons > capacity). */
+int photon_gen_cherenkov(const photon_segments* seg, const photon_atmosphere* atm,
+                         double lambda_min_nm, double lambda_max_nm, uint64_t seed,
+                         int32_t precision, uint32_t* counts, uint64_t* offsets,
+                         photon_block* out, void* stream);
+
+/* Fluorescence generation (section 1.1): mean Y dE/dx L, Poisson count and
+   offsets as above (out == NULL); photons (out != NULL) isotropic,
+   cos(theta) = 1 - 2 u1, phi = 2 pi u2, emission point u0 along the track,
+   line = smallest k with u3 < cdf[k]. Errors: as photon_gen_cherenkov, plus
+   n_lines outside 1..32, negative or all-zero relative yields, yield < 0,
+   dedx == NULL. */
+int photon_gen_fluor(const photon_segments* seg, const photon_atmosphere* atm,
+                     const double* line_nm, const double* line_rel_yield, int32_t n_lines,
+                     double yield_per_MeV, uint64_t seed, int32_t precision, uint32_t* counts,
+                     uint64_t* offsets, photon_block* out, void* stream);
+
+/* Propagation (section 2), in place on slots [0, inout->n_photons): u_z >= 0
+   -> UP; emission below h_obs -> BELOW; otherwise the exact refracted ray of
+   the plane-parallel atmosphere (n sin(theta) conserved) is carried to
+   h_obs with closed-form layer integrals: landing point, arrival time
+   t + (optical path)/c, path length, arrival direction (Snell), weight
+   exp(-k(lambda) * column density along the ray). Errors: EINVAL. */
+int photon_propagate(photon_block* inout, const photon_atmosphere* atm, void* stream);
+
+/* Collection of a propagated block into `sink` (status totals, telescope
+   hits or ground grid). Errors: EINVAL (sink kind, n_tel outside 1..32,
+   R <= 0, grid shape, NULL outputs). */
+int photon_collect(const photon_block* in, const photon_atmosphere* atm, const photon_sink* sink,
+                   void* stream);
+
+/* Fused persistent form: generation, propagation and collection of every
+   photon of `seg` in registers, without a photon block, by one persistent
+   kernel that takes work chunks of the photon index space from an atomic
+   queue. `offsets` (n+1, device) comes from a generation call with
+   out == NULL for the same segments, emission and seed; n_photons must equal
+   offsets[n]. Results equal those of gen + propagate + collect. */
+int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
+                     const photon_emission* em, uint64_t seed, int32_t precision,
+                     const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
+                     const photon_tuning* tuning, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHOTON_H */

@@ -233,9 +233,10 @@ double or_mean_fluor(const or_segments* s, int64_t i, double yield_per_MeV) {
    k-1 (how close the decision was). */
 #define OR_POISSON_CHUNK 128.0
 #define OR_POISSON_KMAX 1000u
+#define OR_MAX_MEAN 1e7  /* larger means mark the segment invalid: no photons */
 uint32_t or_poisson(double mu, uint64_t seed, uint32_t idx, uint32_t shower, double* margin) {
   double best = INFINITY;
-  if (!(mu > 0.0)) {
+  if (!(mu > 0.0) || !(mu <= OR_MAX_MEAN)) {
     if (margin) *margin = best;
     return 0u;
   }

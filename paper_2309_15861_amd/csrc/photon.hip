@@ -1,0 +1,920 @@
+// libphoton: HIP kernels for gfx950 and the C ABI declared in photon.h.
+//
+// Kernels (all wave64):
+//   k_count      one lane per segment: mean (Frank-Tamm, section 1.2, or
+//                Y dE/dx, section 1.1) and Poisson count; block totals for
+//                the scan.
+//   k_scan_tops  one workgroup: inclusive scan of the block totals in place.
+//   k_scan_final one lane per segment: exclusive offsets.
+//   k_gen        one lane per photon slot: Cherenkov (section 1.2, 1.2.1) or
+//                fluorescence (section 1.1) photon into the photon block.
+//   k_propagate  one lane per photon: refracted ray to the observation level
+//                (section 2).
+//   k_collect    one lane per photon: status totals, telescope hits, grid.
+//   k_fused      persistent: work chunks of the photon index space from an
+//                atomic queue; generation + propagation + collection in
+//                registers, per-segment constants staged in LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "photon.h"
+#include "photon_device.hpp"
+
+using namespace ph;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(PHOTON_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kScanBlock = 256;
+constexpr int kWaveSize = 64;
+
+// ------------------------------------------------------------------ views --
+template <typename T>
+struct BlockView {
+  T *x, *y, *z, *ux, *uy, *uz, *lam, *w;
+  double *t, *path;
+  uint32_t *seg, *j;
+  int32_t* status;
+};
+
+struct GenParams {
+  int32_t kind;
+  int32_t n_lines;
+  double inv_l1, inv_dl;                // Cherenkov: 1/lambda_min, 1/lambda_min - 1/lambda_max
+  uint64_t thr[PHOTON_MAX_LINES];       // fluorescence line thresholds on the 32-bit word
+  double line_nm[PHOTON_MAX_LINES];
+};
+
+struct SinkDev {
+  int32_t kind;
+  int32_t n_tel;
+  unsigned long long* totals;
+  double tel[PHOTON_MAX_TELESCOPES][4];
+  photon_hits hits;
+  double x_min, y_min, cell;
+  int32_t nx, ny;
+  uint32_t* grid_count;
+  unsigned long long* grid_weight;
+};
+
+// ------------------------------------------------------ wave/block helpers --
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWaveSize; d <<= 1) {
+    const unsigned long long o = __shfl_up(v, d, kWaveSize);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int d = kWaveSize / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWaveSize);
+  return v;
+}
+
+// Largest s in [0, n] with off[s] <= key (off nondecreasing, off[0] = 0),
+// found by one wave with 64-way splits (a few dependent loads).
+__device__ int64_t wave_upper_index(const uint64_t* off, int64_t n, uint64_t key) {
+  const int lane = lane_id();
+  int64_t lo = 0, hi = n;
+  while (hi - lo >= kWaveSize) {
+    const int64_t step = (hi - lo + kWaveSize) / kWaveSize;
+    const int64_t pos = lo + (int64_t)lane * step;
+    const bool le = (pos <= hi) && (off[pos] <= key);
+    const int c = max(__popcll(__ballot(le)) - 1, 0);
+    const int64_t nlo = lo + (int64_t)c * step;
+    const int64_t nhi = min(nlo + step - 1, hi);
+    lo = nlo;
+    hi = nhi;
+  }
+  const int64_t pos = lo + lane;
+  const bool le = (pos <= hi) && (off[pos] <= key);
+  return lo + max(__popcll(__ballot(le)) - 1, 0);
+}
+
+// Largest s in [0, n) with off[s] <= key, one lane.
+__device__ __forceinline__ int64_t lane_upper_index(const uint64_t* off, int64_t n, uint64_t key) {
+  int64_t lo = 0, hi = n;  // off[lo] <= key < off[hi] for key < off[n]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= key) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------- count+scan --
+template <int KIND>
+__global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, AtmDev atm, double K, uint32_t k0,
+                                                      uint32_t k1, uint32_t* __restrict__ counts,
+                                                      uint64_t* __restrict__ offsets) {
+  __shared__ unsigned long long part[kScanBlock / kWaveSize];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  uint32_t c = 0;
+  if (i < n) {
+    const double mu = (KIND == PHOTON_CHERENKOV) ? mean_cherenkov(seg, i, atm, K) : mean_fluor(seg, i, K);
+    c = poisson_count(mu, k0, k1, seg_idx(seg, i), seg_shower(seg, i));
+    counts[i] = c;
+  }
+  const unsigned long long s = wave_sum((unsigned long long)c);
+  if (lane_id() == 0) part[threadIdx.x / kWaveSize] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kScanBlock / kWaveSize; ++w) t += part[w];
+    const int64_t pos = min((int64_t)(blockIdx.x + 1) * kScanBlock, n);
+    offsets[pos] = t;
+  }
+}
+
+// In-place inclusive scan of the block totals at positions min((b+1)B, n).
+__global__ __launch_bounds__(1024) void k_scan_tops(uint64_t* __restrict__ offsets, int64_t n, int64_t nb) {
+  __shared__ unsigned long long part[1024 / kWaveSize];
+  __shared__ unsigned long long carry;
+  if (threadIdx.x == 0) {
+    carry = 0;
+    offsets[0] = 0;
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t b = base + threadIdx.x;
+    const int64_t pos = min((b + 1) * kScanBlock, n);
+    unsigned long long v = (b < nb) ? offsets[pos] : 0ull;
+    v = wave_incl_scan(v);
+    const int w = threadIdx.x / kWaveSize;
+    if (lane_id() == kWaveSize - 1) part[w] = v;
+    __syncthreads();
+    unsigned long long add = carry;
+    for (int k = 0; k < w; ++k) add += part[k];
+    if (b < nb) offsets[pos] = v + add;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = v + add;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_final(const uint32_t* __restrict__ counts,
+                                                           uint64_t* __restrict__ offsets, int64_t n) {
+  __shared__ unsigned long long part[kScanBlock / kWaveSize];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  const int64_t i = base + threadIdx.x;
+  const unsigned long long prefix = offsets[base];
+  const unsigned long long c = (i < n) ? counts[i] : 0u;
+  const unsigned long long incl = wave_incl_scan(c);
+  const int w = threadIdx.x / kWaveSize;
+  if (lane_id() == kWaveSize - 1) part[w] = incl;
+  __syncthreads();
+  unsigned long long add = prefix;
+  for (int k = 0; k < w; ++k) add += part[k];
+  if (i < n) offsets[i] = add + incl - c;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// -------------------------------------------------------------- generation --
+template <typename T>
+__device__ __forceinline__ void generate(const SegConst<T>& c, uint32_t j, const GenParams& g, uint32_t k0,
+                                         uint32_t k1, const uint64_t* thr, const T* lines, Photon<T>& p) {
+  if (g.kind == PHOTON_CHERENKOV)
+    gen_cherenkov<T>(c, j, k0, k1, (T)g.inv_l1, (T)g.inv_dl, p);
+  else
+    gen_fluor<T>(c, j, k0, k1, thr, lines, g.n_lines, p);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gen(SegView seg, int64_t n_seg, AtmDev atm, GenParams g, uint32_t k0,
+                                             uint32_t k1, const uint64_t* __restrict__ offsets, int64_t n_ph,
+                                             BlockView<T> out) {
+  __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
+  __shared__ T s_lines[PHOTON_MAX_LINES];
+  if (threadIdx.x < PHOTON_MAX_LINES) {
+    s_thr[threadIdx.x] = g.thr[threadIdx.x];
+    s_lines[threadIdx.x] = (T)g.line_nm[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_ph) return;
+  Photon<T> p;
+  uint32_t s32 = 0xffffffffu, j = 0;
+  if ((uint64_t)q < offsets[n_seg]) {
+    const int64_t s = lane_upper_index(offsets, n_seg, (uint64_t)q);
+    SegConst<T> c;
+    seg_const<T>(seg, s, atm, g.kind == PHOTON_CHERENKOV, c);
+    j = (uint32_t)((uint64_t)q - offsets[s]);
+    generate<T>(c, j, g, k0, k1, s_thr, s_lines, p);
+    s32 = (uint32_t)s;
+  } else {
+    p = Photon<T>{};
+    p.status = PHOTON_INVALID;
+  }
+  out.x[q] = p.x;
+  out.y[q] = p.y;
+  out.z[q] = p.z;
+  out.ux[q] = p.ux;
+  out.uy[q] = p.uy;
+  out.uz[q] = p.uz;
+  out.lam[q] = p.lambda;
+  out.w[q] = p.w;
+  out.t[q] = p.t;
+  out.path[q] = p.path;
+  out.seg[q] = s32;
+  out.j[q] = j;
+  out.status[q] = p.status;
+}
+
+// ------------------------------------------------------------- propagation --
+template <typename T>
+__global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, int64_t n_ph) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_ph) return;
+  Photon<T> p;
+  p.x = b.x[q];
+  p.y = b.y[q];
+  p.z = b.z[q];
+  p.ux = b.ux[q];
+  p.uy = b.uy[q];
+  p.uz = b.uz[q];
+  p.lambda = b.lam[q];
+  p.w = b.w[q];
+  p.t = b.t[q];
+  p.path = b.path[q];
+  p.status = b.status[q];
+  propagate<T>(atm, p);
+  b.x[q] = p.x;
+  b.y[q] = p.y;
+  b.z[q] = p.z;
+  b.ux[q] = p.ux;
+  b.uy[q] = p.uy;
+  b.uz[q] = p.uz;
+  b.w[q] = p.w;
+  b.t[q] = p.t;
+  b.path[q] = p.path;
+  b.status[q] = p.status;
+}
+
+// -------------------------------------------------------------- collection --
+struct StatusCounter {
+  uint32_t c[PHOTON_N_STATUS];
+  __device__ void clear() {
+#pragma unroll
+    for (int k = 0; k < PHOTON_N_STATUS; ++k) c[k] = 0;
+  }
+  __device__ void add(int st) {
+#pragma unroll
+    for (int k = 0; k < PHOTON_N_STATUS; ++k) c[k] += (st == k) ? 1u : 0u;
+  }
+};
+
+// Block-wide reduction of per-lane status counters into global totals.
+__device__ void flush_status(StatusCounter& sc, unsigned long long* totals) {
+  __shared__ unsigned long long s_tot[PHOTON_N_STATUS];
+  if (threadIdx.x < PHOTON_N_STATUS) s_tot[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PHOTON_N_STATUS; ++k) {
+    const unsigned long long v = wave_sum((unsigned long long)sc.c[k]);
+    if (lane_id() == 0 && v) atomicAdd(&s_tot[k], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < PHOTON_N_STATUS && s_tot[threadIdx.x]) atomicAdd(&totals[threadIdx.x], s_tot[threadIdx.x]);
+}
+
+// Applies the sink to one propagated photon (in the lanes that hold one);
+// returns the final status. Hit records are compacted per wave: one atomic
+// per wave reserves the slots, lanes write at their rank among the hits.
+template <typename T>
+__device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], double n_obs, Photon<T>& p,
+                                           uint32_t seg_row, uint32_t j, bool active) {
+  int st = active ? p.status : -1;
+  if (sk.kind == PHOTON_SINK_TELESCOPES) {
+    int k = -1;
+    T s_hit = (T)0;
+    if (active && st == PHOTON_LANDED) k = telescope_hit<T>(p, tel, sk.n_tel, s_hit);
+    const bool hit = k >= 0;
+    const unsigned long long m = __ballot(hit);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long base = 0;
+      if (lane_id() == leader) base = atomicAdd(sk.hits.count, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader, kWaveSize);
+      if (hit) {
+        const unsigned long long rank = __popcll(m & ((1ull << lane_id()) - 1ull));
+        const unsigned long long slot = base + rank;
+        if (slot < (unsigned long long)sk.hits.capacity) {
+          sk.hits.segment[slot] = seg_row;
+          sk.hits.j[slot] = j;
+          sk.hits.telescope[slot] = k;
+          sk.hits.x[slot] = (double)p.x + (double)s_hit * (double)p.ux;
+          sk.hits.y[slot] = (double)p.y + (double)s_hit * (double)p.uy;
+          sk.hits.z[slot] = (double)p.z + (double)s_hit * (double)p.uz;
+          sk.hits.t_ns[slot] = p.t + n_obs * (double)s_hit / kC;
+          sk.hits.ux[slot] = (float)p.ux;
+          sk.hits.uy[slot] = (float)p.uy;
+          sk.hits.uz[slot] = (float)p.uz;
+          sk.hits.wavelength_nm[slot] = (float)p.lambda;
+          sk.hits.weight[slot] = (float)p.w;
+        }
+        st = PHOTON_HIT;
+      }
+    }
+  } else if (sk.kind == PHOTON_SINK_GRID) {
+    if (active && st == PHOTON_LANDED) {
+      const double fx = floor(((double)p.x - sk.x_min) / sk.cell);
+      const double fy = floor(((double)p.y - sk.y_min) / sk.cell);
+      if (fx >= 0.0 && fy >= 0.0 && fx < (double)sk.nx && fy < (double)sk.ny) {
+        const int cell = (int)fy * sk.nx + (int)fx;
+        atomicAdd(&sk.grid_count[cell], 1u);
+        atomicAdd(&sk.grid_weight[cell], (unsigned long long)((double)p.w * 4294967296.0 + 0.5));
+      } else {
+        st = PHOTON_OFFGRID;
+      }
+    }
+  }
+  return st;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, SinkDev sk, double n_obs) {
+  __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  if (threadIdx.x < PHOTON_MAX_TELESCOPES * 4) (&s_tel[0][0])[threadIdx.x] = (&sk.tel[0][0])[threadIdx.x];
+  __syncthreads();
+  StatusCounter sc;
+  sc.clear();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = q < n_ph;
+  Photon<T> p{};
+  uint32_t s = 0, j = 0;
+  if (active) {
+    p.x = b.x[q];
+    p.y = b.y[q];
+    p.z = b.z[q];
+    p.ux = b.ux[q];
+    p.uy = b.uy[q];
+    p.uz = b.uz[q];
+    p.lambda = b.lam[q];
+    p.w = b.w[q];
+    p.t = b.t[q];
+    p.status = b.status[q];
+    s = b.seg[q];
+    j = b.j[q];
+  }
+  const int st = sink_photon<T>(sk, s_tel, n_obs, p, s, j, active);
+  if (active) sc.add(st);
+  if (sk.totals) flush_status(sc, sk.totals);
+}
+
+// ------------------------------------------------------------ fused kernel --
+constexpr int kWindow = 256;  // segments staged in LDS per work chunk
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_fused(SegView seg, int64_t n_seg, AtmDev atm, GenParams g, uint32_t k0,
+                                              uint32_t k1, const uint64_t* __restrict__ offsets, int64_t n_ph,
+                                              int64_t chunk, SinkDev sk, unsigned long long* cursor) {
+  __shared__ SegConst<T> s_seg[kWindow];
+  __shared__ uint64_t s_off[kWindow + 1];
+  __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
+  __shared__ T s_lines[PHOTON_MAX_LINES];
+  __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  __shared__ unsigned long long s_c0;
+  __shared__ int64_t s_lo, s_hi;
+
+  const int tid = threadIdx.x;
+  if (tid < PHOTON_MAX_LINES) {
+    s_thr[tid] = g.thr[tid];
+    s_lines[tid] = (T)g.line_nm[tid];
+  }
+  for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&sk.tel[0][0])[k];
+  const bool cher = g.kind == PHOTON_CHERENKOV;
+  StatusCounter sc;
+  sc.clear();
+  // slots at or beyond offsets[n_seg] belong to no segment: counted INVALID
+  const uint64_t lim = min((uint64_t)n_ph, offsets[n_seg]);
+
+  for (;;) {
+    if (tid == 0) s_c0 = atomicAdd(cursor, (unsigned long long)chunk);
+    __syncthreads();
+    const uint64_t c0 = s_c0;
+    if (c0 >= (uint64_t)n_ph) break;
+    const uint64_t c1 = min(c0 + (uint64_t)chunk, (uint64_t)n_ph);
+    const uint64_t v1 = min(c1, lim);  // valid slots of this chunk: [c0, v1)
+    for (uint64_t q = max(c0, v1) + tid; q < c1; q += BS) sc.add(PHOTON_INVALID);
+    if (c0 >= v1) {
+      __syncthreads();
+      continue;
+    }
+    const int wave = tid / kWaveSize;
+    if (wave == 0) {
+      const int64_t s = wave_upper_index(offsets, n_seg, c0);
+      if (lane_id() == 0) s_lo = s;
+    }
+    if (wave == (BS > kWaveSize ? 1 : 0)) {
+      const int64_t s = wave_upper_index(offsets, n_seg, v1 - 1);
+      if (lane_id() == 0) s_hi = s;
+    }
+    __syncthreads();
+    // both ends lie in [0, n_seg) for offsets from the count call; the
+    // clamps keep every index in bounds for any offsets array
+    const int64_t lo = min(s_lo, n_seg - 1);
+    const int64_t W = min(s_hi, n_seg - 1) - lo + 1;
+    const bool win = W >= 1 && W <= kWindow;
+    if (win) {
+      for (int t = tid; t < W; t += BS) {
+        seg_const<T>(seg, lo + t, atm, cher, s_seg[t]);
+        s_off[t] = offsets[lo + t];
+      }
+      if (tid == 0) s_off[W] = offsets[lo + W];
+    }
+    __syncthreads();
+    for (uint64_t q = c0 + tid; q < v1; q += BS) {
+      SegConst<T> c;
+      uint64_t off_s;
+      int64_t s;
+      if (win) {
+        int a = 0, b = (int)W;  // s_off[a] <= q < s_off[b]
+        while (b - a > 1) {
+          const int mid = (a + b) >> 1;
+          if (s_off[mid] <= q) a = mid; else b = mid;
+        }
+        c = s_seg[a];
+        off_s = s_off[a];
+        s = lo + a;
+      } else {
+        s = lane_upper_index(offsets, n_seg, q);
+        seg_const<T>(seg, s, atm, cher, c);
+        off_s = offsets[s];
+      }
+      const uint32_t j = (uint32_t)(q - off_s);
+      Photon<T> p;
+      generate<T>(c, j, g, k0, k1, s_thr, s_lines, p);
+      propagate<T>(atm, p);
+      const int st = sink_photon<T>(sk, s_tel, atm.n_obs, p, (uint32_t)s, j, true);
+      sc.add(st);
+    }
+    __syncthreads();
+  }
+  if (sk.totals) flush_status(sc, sk.totals);
+}
+
+// ------------------------------------------------------------ host helpers --
+bool finite(double v) { return std::isfinite(v); }
+
+int prep_atm(const photon_atmosphere* a, AtmDev* d) {
+  if (!a) return fail(PHOTON_EINVAL, "atmosphere is NULL");
+  if (a->n_layers < 1 || a->n_layers > PHOTON_MAX_LAYERS)
+    return fail(PHOTON_EINVAL, "n_layers = %d outside 1..%d", a->n_layers, PHOTON_MAX_LAYERS);
+  if (a->h_base[0] != 0.0) return fail(PHOTON_EINVAL, "h_base[0] must be 0");
+  for (int i = 0; i < a->n_layers; ++i) {
+    if (!finite(a->h_base[i])) return fail(PHOTON_EINVAL, "h_base[%d] not finite", i);
+    if (i > 0 && !(a->h_base[i] > a->h_base[i - 1])) return fail(PHOTON_EINVAL, "h_base not strictly increasing at %d", i);
+    if (!(a->scale_height[i] > 0.0)) return fail(PHOTON_EINVAL, "scale_height[%d] must be > 0", i);
+  }
+  if (!(a->n0_minus_1 >= 0.0) || !finite(a->n0_minus_1)) return fail(PHOTON_EINVAL, "n0_minus_1 must be finite and >= 0");
+  if (!finite(a->h_obs)) return fail(PHOTON_EINVAL, "h_obs not finite");
+  if (a->n_abs < 0 || a->n_abs > PHOTON_MAX_ABS) return fail(PHOTON_EINVAL, "n_abs = %d outside 0..%d", a->n_abs, PHOTON_MAX_ABS);
+  for (int i = 0; i < a->n_abs; ++i) {
+    if (!finite(a->abs_lambda_nm[i]) || !(a->abs_k_per_m[i] >= 0.0) || !finite(a->abs_k_per_m[i]))
+      return fail(PHOTON_EINVAL, "absorption table entry %d invalid", i);
+    if (i > 0 && !(a->abs_lambda_nm[i] > a->abs_lambda_nm[i - 1]))
+      return fail(PHOTON_EINVAL, "abs_lambda_nm not strictly increasing at %d", i);
+  }
+  std::memset(d, 0, sizeof *d);
+  d->nl = a->n_layers;
+  d->n_abs = a->n_abs;
+  for (int i = 0; i < PHOTON_MAX_LAYERS; ++i) {
+    const int k = i < a->n_layers ? i : a->n_layers - 1;
+    d->hb[i] = a->h_base[k];
+    d->H[i] = a->scale_height[k];
+    if (std::isinf(a->scale_height[k]) && i < a->n_layers) d->homog_mask |= 1 << i;
+  }
+  d->rb[0] = 1.0;
+  for (int i = 0; i + 1 < a->n_layers; ++i) d->rb[i + 1] = d->rb[i] * std::exp(-(a->h_base[i + 1] - a->h_base[i]) / a->scale_height[i]);
+  for (int i = a->n_layers; i < PHOTON_MAX_LAYERS; ++i) d->rb[i] = d->rb[a->n_layers - 1];
+  d->eta0 = a->n0_minus_1;
+  d->hobs = a->h_obs;
+  int lo = 0;
+  for (int k = 0; k < a->n_layers; ++k)
+    if (a->h_base[k] <= a->h_obs) lo = k;
+  d->l_obs = lo;
+  d->rho_obs = d->rb[lo] * std::exp(-(a->h_obs - a->h_base[lo]) / a->scale_height[lo]);
+  d->n_obs = 1.0 + a->n0_minus_1 * d->rho_obs;
+  for (int i = 0; i < a->n_abs; ++i) {
+    d->abs_l[i] = a->abs_lambda_nm[i];
+    d->abs_k[i] = a->abs_k_per_m[i];
+  }
+  return PHOTON_OK;
+}
+
+int prep_seg(const photon_segments* s, SegView* v, bool need_dedx) {
+  if (!s) return fail(PHOTON_EINVAL, "segments is NULL");
+  if (s->n < 0) return fail(PHOTON_EINVAL, "segment count n = %lld < 0", (long long)s->n);
+  if (s->n > 0xffffffffll) return fail(PHOTON_EINVAL, "more than 2^32 - 1 segments");
+  if (s->n > 0) {
+    const void* req[] = {s->x0, s->y0, s->z0, s->dx, s->dy, s->dz, s->length, s->beta, s->t0};
+    const char* nm[] = {"x0", "y0", "z0", "dx", "dy", "dz", "length", "beta", "t0"};
+    for (int k = 0; k < 9; ++k)
+      if (!req[k]) return fail(PHOTON_EINVAL, "segment field %s is NULL", nm[k]);
+    if (need_dedx && !s->dedx) return fail(PHOTON_EINVAL, "segment field dedx is NULL (fluorescence)");
+  }
+  *v = SegView{s->x0, s->y0, s->z0, s->dx, s->dy, s->dz, s->length, s->beta, s->t0, s->dedx,
+               s->charge, s->shower, s->index_in_shower};
+  return PHOTON_OK;
+}
+
+int prep_emission(const photon_emission* em, GenParams* g) {
+  if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
+  std::memset(g, 0, sizeof *g);
+  g->kind = em->kind;
+  if (em->kind == PHOTON_CHERENKOV) {
+    if (!(em->lambda_min_nm > 0.0) || !(em->lambda_max_nm > em->lambda_min_nm) || !finite(em->lambda_max_nm))
+      return fail(PHOTON_EINVAL, "wavelength band must satisfy 0 < lambda_min < lambda_max");
+    g->inv_l1 = 1.0 / em->lambda_min_nm;
+    g->inv_dl = 1.0 / em->lambda_min_nm - 1.0 / em->lambda_max_nm;
+    g->n_lines = 1;
+    return PHOTON_OK;
+  }
+  if (em->kind != PHOTON_FLUORESCENCE) return fail(PHOTON_EINVAL, "unknown emission kind %d", em->kind);
+  if (!(em->yield_per_MeV >= 0.0) || !finite(em->yield_per_MeV)) return fail(PHOTON_EINVAL, "yield_per_MeV must be >= 0");
+  if (em->n_lines < 1 || em->n_lines > PHOTON_MAX_LINES)
+    return fail(PHOTON_EINVAL, "n_lines = %d outside 1..%d", em->n_lines, PHOTON_MAX_LINES);
+  double acc = 0.0, cdf[PHOTON_MAX_LINES];
+  for (int k = 0; k < em->n_lines; ++k) {
+    if (!(em->line_rel_yield[k] >= 0.0) || !finite(em->line_rel_yield[k]))
+      return fail(PHOTON_EINVAL, "line_rel_yield[%d] must be >= 0", k);
+    if (!(em->line_nm[k] > 0.0) || !finite(em->line_nm[k])) return fail(PHOTON_EINVAL, "line_nm[%d] must be > 0", k);
+    acc = acc + em->line_rel_yield[k];
+    cdf[k] = acc;
+  }
+  if (!(acc > 0.0)) return fail(PHOTON_EINVAL, "relative line yields are all zero");
+  for (int k = 0; k < em->n_lines; ++k) cdf[k] = cdf[k] / acc;
+  cdf[em->n_lines - 1] = 1.0;
+  g->n_lines = em->n_lines;
+  for (int k = 0; k < PHOTON_MAX_LINES; ++k) {
+    const int kk = k < em->n_lines ? k : em->n_lines - 1;
+    // u3 < cdf[k]  <=>  (w + 1/2) 2^-32 < cdf[k]  <=>  w < ceil(cdf[k] 2^32 - 1/2)
+    g->thr[k] = (uint64_t)std::ceil(std::ldexp(cdf[kk], 32) - 0.5);
+    g->line_nm[k] = em->line_nm[kk];
+  }
+  return PHOTON_OK;
+}
+
+int prep_precision(int32_t p) {
+  if (p != PHOTON_FP64 && p != PHOTON_FP32) return fail(PHOTON_EINVAL, "precision must be PHOTON_FP64 or PHOTON_FP32");
+  return PHOTON_OK;
+}
+
+template <typename T>
+int prep_block(const photon_block* b, BlockView<T>* v, bool need_cap) {
+  if (!b) return fail(PHOTON_EINVAL, "photon block is NULL");
+  if (b->n_photons < 0 || b->capacity < 0) return fail(PHOTON_EINVAL, "negative photon count or capacity");
+  if (need_cap && b->n_photons > b->capacity)
+    return fail(PHOTON_ECAPACITY, "n_photons = %lld exceeds capacity %lld", (long long)b->n_photons, (long long)b->capacity);
+  if (b->n_photons > 0) {
+    const void* req[] = {b->x, b->y, b->z, b->ux, b->uy, b->uz, b->wavelength_nm, b->weight, b->t_ns, b->path_m,
+                         b->segment, b->j, b->status};
+    for (int k = 0; k < 13; ++k)
+      if (!req[k]) return fail(PHOTON_EINVAL, "photon block array %d is NULL", k);
+  }
+  *v = BlockView<T>{(T*)b->x, (T*)b->y, (T*)b->z, (T*)b->ux, (T*)b->uy, (T*)b->uz, (T*)b->wavelength_nm,
+                    (T*)b->weight, b->t_ns, b->path_m, b->segment, b->j, b->status};
+  return PHOTON_OK;
+}
+
+int check_block(const photon_block* b, int32_t precision) {
+  if (precision == PHOTON_FP64) {
+    BlockView<double> v;
+    return prep_block<double>(b, &v, true);
+  }
+  BlockView<float> v;
+  return prep_block<float>(b, &v, true);
+}
+
+int prep_sink(const photon_sink* s, SinkDev* d) {
+  if (!s) return fail(PHOTON_EINVAL, "sink is NULL");
+  std::memset(d, 0, sizeof *d);
+  d->kind = s->kind;
+  d->totals = s->status_totals;
+  if (s->kind == PHOTON_SINK_TELESCOPES) {
+    if (s->n_tel < 1 || s->n_tel > PHOTON_MAX_TELESCOPES)
+      return fail(PHOTON_EINVAL, "n_tel = %d outside 1..%d", s->n_tel, PHOTON_MAX_TELESCOPES);
+    for (int k = 0; k < s->n_tel; ++k) {
+      for (int c = 0; c < 4; ++c)
+        if (!finite(s->tel[k][c])) return fail(PHOTON_EINVAL, "telescope %d not finite", k);
+      if (!(s->tel[k][3] > 0.0)) return fail(PHOTON_EINVAL, "telescope %d radius must be > 0", k);
+    }
+    const photon_hits& h = s->hits;
+    if (h.capacity < 0 || !h.count) return fail(PHOTON_EINVAL, "hits.count is NULL or capacity < 0");
+    if (h.capacity > 0) {
+      const void* req[] = {h.segment, h.j, h.telescope, h.x, h.y, h.z, h.t_ns, h.ux, h.uy, h.uz, h.wavelength_nm, h.weight};
+      for (int k = 0; k < 12; ++k)
+        if (!req[k]) return fail(PHOTON_EINVAL, "hit array %d is NULL", k);
+    }
+    d->n_tel = s->n_tel;
+    std::memcpy(d->tel, s->tel, sizeof d->tel);
+    d->hits = h;
+  } else if (s->kind == PHOTON_SINK_GRID) {
+    if (s->nx < 1 || s->ny < 1 || (int64_t)s->nx * s->ny > (1 << 24))
+      return fail(PHOTON_EINVAL, "grid shape %d x %d invalid", s->nx, s->ny);
+    if (!(s->cell > 0.0) || !finite(s->x_min) || !finite(s->y_min) || !finite(s->cell))
+      return fail(PHOTON_EINVAL, "grid origin/cell invalid");
+    if (!s->grid_count || !s->grid_weight) return fail(PHOTON_EINVAL, "grid outputs are NULL");
+    d->x_min = s->x_min;
+    d->y_min = s->y_min;
+    d->cell = s->cell;
+    d->nx = s->nx;
+    d->ny = s->ny;
+    d->grid_count = s->grid_count;
+    d->grid_weight = s->grid_weight;
+  } else if (s->kind != PHOTON_SINK_STATUS) {
+    return fail(PHOTON_EINVAL, "unknown sink kind %d", s->kind);
+  }
+  return PHOTON_OK;
+}
+
+// ---------------------------------------------------------------- devices --
+struct DeviceState {
+  bool checked = false;
+  bool ok = false;
+  int cu = 0;
+  unsigned long long* work = nullptr;  // [0] = fused work cursor
+};
+std::mutex g_mu;
+DeviceState g_dev[64];
+
+int current_device(DeviceState** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PHOTON_ENODEV, "no HIP device");
+  if (dev < 0 || dev >= 64) return fail(PHOTON_ENODEV, "device index %d unsupported", dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceState& d = g_dev[dev];
+  if (!d.checked) {
+    d.checked = true;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(PHOTON_ENODEV, "hipGetDeviceProperties failed");
+    d.ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    d.cu = prop.multiProcessorCount;
+    if (d.ok && hipMalloc(&d.work, 4096) != hipSuccess) {
+      d.ok = false;
+      d.work = nullptr;
+      return fail(PHOTON_EHIP, "work area allocation failed");
+    }
+    if (d.ok && hipMemset(d.work, 0, 4096) != hipSuccess) return fail(PHOTON_EHIP, "work area clear failed");
+  }
+  if (!d.ok) return fail(PHOTON_ENODEV, "current device is not gfx950");
+  *out = &d;
+  return PHOTON_OK;
+}
+
+int check_launch() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PHOTON_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return PHOTON_OK;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int count_and_scan(const SegView& sv, int64_t n, const AtmDev& atm, int kind, double K, uint64_t seed,
+                   uint32_t* counts, uint64_t* offsets, hipStream_t st) {
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)offsets, 1);
+    return check_launch();
+  }
+  const int64_t nb = ceil_div(n, kScanBlock);
+  if (kind == PHOTON_CHERENKOV)
+    hipLaunchKernelGGL(k_count<PHOTON_CHERENKOV>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0, k1,
+                       counts, offsets);
+  else
+    hipLaunchKernelGGL(k_count<PHOTON_FLUORESCENCE>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0,
+                       k1, counts, offsets);
+  hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(1024), 0, st, offsets, n, nb);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanBlock), 0, st, (const uint32_t*)counts, offsets, n);
+  return check_launch();
+}
+
+template <typename T>
+int launch_gen(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
+               const uint64_t* offsets, const photon_block* out, hipStream_t st) {
+  BlockView<T> bv;
+  int rc = prep_block<T>(out, &bv, true);
+  if (rc) return rc;
+  if (out->n_photons == 0) return PHOTON_OK;
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  hipLaunchKernelGGL(k_gen<T>, dim3((unsigned)ceil_div(out->n_photons, 256)), dim3(256), 0, st, sv, n, atm, g, k0, k1,
+                     offsets, out->n_photons, bv);
+  return check_launch();
+}
+
+int generate_common(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                    uint64_t seed, int32_t precision, uint32_t* counts, uint64_t* offsets, photon_block* out,
+                    void* stream) {
+  SegView sv;
+  AtmDev ad;
+  GenParams g;
+  int rc;
+  if ((rc = prep_seg(seg, &sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
+  if ((rc = prep_atm(atm, &ad))) return rc;
+  if ((rc = prep_emission(em, &g))) return rc;
+  if ((rc = prep_precision(precision))) return rc;
+  if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
+  if (!out && !counts) return fail(PHOTON_EINVAL, "counts is NULL");
+  if (out && out->precision != precision) return fail(PHOTON_EINVAL, "photon block precision differs from the call's");
+  if (out && (rc = check_block(out, precision))) return rc;
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (!out) {
+    const double K = (em->kind == PHOTON_CHERENKOV)
+                         ? (2.0 * kPi * kAlpha) * ((1e9 / em->lambda_min_nm) - (1e9 / em->lambda_max_nm))
+                         : em->yield_per_MeV;
+    return count_and_scan(sv, seg->n, ad, em->kind, K, seed, counts, offsets, st);
+  }
+  return precision == PHOTON_FP64 ? launch_gen<double>(sv, seg->n, ad, g, seed, offsets, out, st)
+                                  : launch_gen<float>(sv, seg->n, ad, g, seed, offsets, out, st);
+}
+
+template <typename T>
+int launch_propagate(photon_block* b, const AtmDev& atm, hipStream_t st) {
+  BlockView<T> bv;
+  int rc = prep_block<T>(b, &bv, true);
+  if (rc) return rc;
+  if (b->n_photons == 0) return PHOTON_OK;
+  hipLaunchKernelGGL(k_propagate<T>, dim3((unsigned)ceil_div(b->n_photons, 256)), dim3(256), 0, st, atm, bv,
+                     b->n_photons);
+  return check_launch();
+}
+
+template <typename T>
+int launch_collect(const photon_block* b, const AtmDev& atm, const SinkDev& sk, hipStream_t st) {
+  BlockView<T> bv;
+  int rc = prep_block<T>(b, &bv, true);
+  if (rc) return rc;
+  if (b->n_photons == 0) return PHOTON_OK;
+  hipLaunchKernelGGL(k_collect<T>, dim3((unsigned)ceil_div(b->n_photons, 256)), dim3(256), 0, st, bv, b->n_photons,
+                     sk, atm.n_obs);
+  return check_launch();
+}
+
+template <typename T, int BS>
+int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
+                    const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
+                    DeviceState* dev, hipStream_t st) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<T, BS>, BS, 0) != hipSuccess || occ < 1) occ = 1;
+  if (bpc > 0 && bpc < occ) occ = bpc;
+  int64_t grid = (int64_t)dev->cu * occ;
+  const int64_t chunks = ceil_div(n_ph, chunk);
+  if (grid > chunks) grid = chunks;
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
+  hipLaunchKernelGGL((k_fused<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, sv, n, atm, g, k0, k1, offsets, n_ph,
+                     chunk, sk, dev->work);
+  return check_launch();
+}
+
+template <typename T>
+int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
+                 const uint64_t* offsets, int64_t n_ph, const photon_tuning* tun, const SinkDev& sk,
+                 DeviceState* dev, hipStream_t st) {
+  int bs = tun ? tun->block : 256;
+  int64_t chunk = tun ? tun->chunk : 4096;
+  int bpc = tun ? tun->blocks_per_cu : 0;
+  if (bs != 128 && bs != 256 && bs != 512) return fail(PHOTON_EINVAL, "tuning.block must be 128, 256 or 512");
+  if (chunk < bs || chunk % bs) return fail(PHOTON_EINVAL, "tuning.chunk must be a positive multiple of block");
+  if (bpc < 0) return fail(PHOTON_EINVAL, "tuning.blocks_per_cu must be >= 0");
+  switch (bs) {
+    case 128: return launch_fused_bs<T, 128>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st);
+    case 512: return launch_fused_bs<T, 512>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st);
+    default: return launch_fused_bs<T, 256>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st);
+  }
+}
+
+}  // namespace
+
+// ================================================================= C ABI ==
+extern "C" {
+
+const char* photon_version(void) { return "libphoton 0.1 (gfx950)"; }
+
+const char* photon_last_error(void) { return g_err.c_str(); }
+
+int photon_init(void) {
+  DeviceState* d;
+  return current_device(&d);
+}
+
+int photon_gen_cherenkov(const photon_segments* seg, const photon_atmosphere* atm, double lambda_min_nm,
+                         double lambda_max_nm, uint64_t seed, int32_t precision, uint32_t* counts, uint64_t* offsets,
+                         photon_block* out, void* stream) {
+  photon_emission em;
+  std::memset(&em, 0, sizeof em);
+  em.kind = PHOTON_CHERENKOV;
+  em.lambda_min_nm = lambda_min_nm;
+  em.lambda_max_nm = lambda_max_nm;
+  return generate_common(seg, atm, &em, seed, precision, counts, offsets, out, stream);
+}
+
+int photon_gen_fluor(const photon_segments* seg, const photon_atmosphere* atm, const double* line_nm,
+                     const double* line_rel_yield, int32_t n_lines, double yield_per_MeV, uint64_t seed,
+                     int32_t precision, uint32_t* counts, uint64_t* offsets, photon_block* out, void* stream) {
+  if (!line_nm || !line_rel_yield) return fail(PHOTON_EINVAL, "line tables are NULL");
+  if (n_lines < 1 || n_lines > PHOTON_MAX_LINES)
+    return fail(PHOTON_EINVAL, "n_lines = %d outside 1..%d", n_lines, PHOTON_MAX_LINES);
+  photon_emission em;
+  std::memset(&em, 0, sizeof em);
+  em.kind = PHOTON_FLUORESCENCE;
+  em.yield_per_MeV = yield_per_MeV;
+  em.n_lines = n_lines;
+  for (int k = 0; k < n_lines; ++k) {
+    em.line_nm[k] = line_nm[k];
+    em.line_rel_yield[k] = line_rel_yield[k];
+  }
+  return generate_common(seg, atm, &em, seed, precision, counts, offsets, out, stream);
+}
+
+int photon_propagate(photon_block* inout, const photon_atmosphere* atm, void* stream) {
+  AtmDev ad;
+  int rc;
+  if (!inout) return fail(PHOTON_EINVAL, "photon block is NULL");
+  if ((rc = prep_atm(atm, &ad))) return rc;
+  if ((rc = prep_precision(inout->precision))) return rc;
+  if ((rc = check_block(inout, inout->precision))) return rc;
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  return inout->precision == PHOTON_FP64 ? launch_propagate<double>(inout, ad, st) : launch_propagate<float>(inout, ad, st);
+}
+
+int photon_collect(const photon_block* in, const photon_atmosphere* atm, const photon_sink* sink, void* stream) {
+  AtmDev ad;
+  SinkDev sk;
+  int rc;
+  if (!in) return fail(PHOTON_EINVAL, "photon block is NULL");
+  if ((rc = prep_atm(atm, &ad))) return rc;
+  if ((rc = prep_sink(sink, &sk))) return rc;
+  if ((rc = prep_precision(in->precision))) return rc;
+  if ((rc = check_block(in, in->precision))) return rc;
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  return in->precision == PHOTON_FP64 ? launch_collect<double>(in, ad, sk, st) : launch_collect<float>(in, ad, sk, st);
+}
+
+int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em, uint64_t seed,
+                     int32_t precision, const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
+                     const photon_tuning* tuning, void* stream) {
+  SegView sv;
+  AtmDev ad;
+  GenParams g;
+  SinkDev sk;
+  int rc;
+  if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
+  if ((rc = prep_seg(seg, &sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
+  if ((rc = prep_atm(atm, &ad))) return rc;
+  if ((rc = prep_emission(em, &g))) return rc;
+  if ((rc = prep_precision(precision))) return rc;
+  if ((rc = prep_sink(sink, &sk))) return rc;
+  if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
+  if (n_photons < 0) return fail(PHOTON_EINVAL, "n_photons < 0");
+  if (tuning && (tuning->block != 128 && tuning->block != 256 && tuning->block != 512))
+    return fail(PHOTON_EINVAL, "tuning.block must be 128, 256 or 512");
+  if (tuning && (tuning->chunk < tuning->block || tuning->chunk % tuning->block))
+    return fail(PHOTON_EINVAL, "tuning.chunk must be a positive multiple of block");
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  if (n_photons == 0 || seg->n == 0) return PHOTON_OK;
+  hipStream_t st = (hipStream_t)stream;
+  return precision == PHOTON_FP64
+             ? launch_fused<double>(sv, seg->n, ad, g, seed, offsets, n_photons, tuning, sk, dev, st)
+             : launch_fused<float>(sv, seg->n, ad, g, seed, offsets, n_photons, tuning, sk, dev, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,485 @@
+// Device-side building blocks of the photon pipeline (gfx950, wave64).
+//
+// Paper: Baack & Alameddine, arXiv:2309.15861 (ICRC2023). Section 1.1
+// (fluorescence yield), section 1.2 (Frank-Tamm count, cone generation),
+// section 1.2.1 (photon vector p, rotation M_Rod), section 2 (propagation).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "photon.h"
+
+namespace ph {
+
+constexpr double kPi = 3.141592653589793;
+constexpr double kAlpha = 7.2973525693e-3;   // fine-structure constant (CODATA 2018)
+constexpr double kC = 0.299792458;           // m/ns
+constexpr uint32_t kDomCount = 0u, kDomCher = 1u, kDomFluo = 2u;
+constexpr double kPoissonChunk = 128.0;
+constexpr uint32_t kPoissonKmax = 1000u;
+constexpr double kMaxMean = 1e7;   // a segment with a larger mean is invalid
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32
+// S-box; each round multiplies words 0 and 2 by the published constants,
+// crosses the high halves with words 1 and 3 and the key, and the key gets
+// the Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+  return U4{{c0, c1, c2, c3}};
+}
+
+// (x + 1/2) 2^-32: exact in double, strictly inside (0,1).
+__device__ __forceinline__ double u01d(uint32_t x) { return (double)x * 0x1p-32 + 0x1p-33; }
+// 24-bit form for the float path: ((x >> 8) + 1/2) 2^-24, exact in float.
+__device__ __forceinline__ float u01f(uint32_t x) { return (float)(x >> 8) * 0x1p-24f + 0x1p-25f; }
+
+template <typename T>
+__device__ __forceinline__ T u01(uint32_t x);
+template <>
+__device__ __forceinline__ double u01<double>(uint32_t x) { return u01d(x); }
+template <>
+__device__ __forceinline__ float u01<float>(uint32_t x) { return u01f(x); }
+
+// ---------------------------------------------------------------------------
+// Atmosphere as passed to kernels (by value). rb = rho/rho0 at each layer
+// base, computed on the host by the recurrence rb[i+1] = rb[i]
+// exp(-(h[i+1]-h[i])/H[i]); rho_obs and n_obs at the observation level.
+// ---------------------------------------------------------------------------
+struct AtmDev {
+  int32_t nl;
+  int32_t n_abs;
+  double hb[PHOTON_MAX_LAYERS];
+  double H[PHOTON_MAX_LAYERS];
+  double rb[PHOTON_MAX_LAYERS];
+  double eta0, hobs, rho_obs, n_obs;
+  int32_t l_obs;          // layer of h_obs
+  int32_t homog_mask;     // bit i set: layer i has infinite scale height
+  double abs_l[PHOTON_MAX_ABS];
+  double abs_k[PHOTON_MAX_ABS];
+};
+
+__device__ __forceinline__ int layer_of(const AtmDev& a, double h) {
+  int l = 0;
+#pragma unroll
+  for (int k = 1; k < PHOTON_MAX_LAYERS; ++k)
+    if (k < a.nl && a.hb[k] <= h) l = k;
+  return l;
+}
+
+// ---------------------------------------------------------------------------
+// Per-segment mean and Poisson count (section 1.2 Frank-Tamm, section 1.1
+// yield). Evaluated in double without contraction in a fixed order so that
+// counts are reproducible bit for bit by any IEEE implementation of the
+// same steps.
+// ---------------------------------------------------------------------------
+struct SegView {
+  const double *x0, *y0, *z0, *dx, *dy, *dz, *len, *beta, *t0, *dedx;
+  const int32_t* charge;
+  const uint32_t *shower, *idx;
+};
+
+__device__ __forceinline__ uint32_t seg_idx(const SegView& s, int64_t i) {
+  return s.idx ? s.idx[i] : (uint32_t)i;
+}
+__device__ __forceinline__ uint32_t seg_shower(const SegView& s, int64_t i) {
+  return s.shower ? s.shower[i] : 0u;
+}
+
+__device__ __forceinline__ bool seg_ok(const SegView& s, int64_t i) {
+#pragma clang fp contract(off)
+  const double v[9] = {s.x0[i], s.y0[i], s.z0[i], s.dx[i], s.dy[i], s.dz[i], s.len[i], s.beta[i], s.t0[i]};
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) ok = ok && isfinite(v[k]);
+  ok = ok && (s.beta[i] > 0.0) && (s.beta[i] < 1.0) && (s.len[i] >= 0.0);
+  const double dn2 = (s.dx[i] * s.dx[i] + s.dy[i] * s.dy[i]) + s.dz[i] * s.dz[i];
+  return ok && (dn2 > 0.0);
+}
+
+// n at the segment midpoint (the medium is homogeneous along a short step).
+__device__ __forceinline__ double seg_index(const SegView& s, int64_t i, const AtmDev& a) {
+#pragma clang fp contract(off)
+  const double dx = s.dx[i], dy = s.dy[i], dz = s.dz[i];
+  const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
+  const double dzh = dz / dn;
+  const double zc = s.z0[i] + (0.5 * s.len[i]) * dzh;
+  const int l = layer_of(a, zc);
+  const double rho = a.rb[l] * exp(-(zc - a.hb[l]) / a.H[l]);
+  return 1.0 + a.eta0 * rho;
+}
+
+__device__ __forceinline__ double mean_cherenkov(const SegView& s, int64_t i, const AtmDev& a, double K) {
+#pragma clang fp contract(off)
+  if (!seg_ok(s, i)) return 0.0;
+  const double n = seg_index(s, i, a);
+  const double bn = s.beta[i] * n;
+  const double f = 1.0 - 1.0 / (bn * bn);
+  double zz = 1.0;
+  if (s.charge) zz = (double)(s.charge[i] * s.charge[i]);
+  return (f > 0.0) ? ((K * zz) * s.len[i]) * f : 0.0;
+}
+
+__device__ __forceinline__ double mean_fluor(const SegView& s, int64_t i, double Y) {
+#pragma clang fp contract(off)
+  if (!seg_ok(s, i)) return 0.0;
+  const double e = s.dedx[i];
+  if (!(isfinite(e) && e >= 0.0)) return 0.0;
+  return (Y * e) * s.len[i];
+}
+
+// Poisson(mu): m = ceil(mu/128) chunks of mean mc = mu/m, each the smallest
+// k with F(k) >= u, F summed term by term p_k = p_{k-1} mc / k.
+__device__ __forceinline__ uint32_t poisson_count(double mu, uint32_t k0, uint32_t k1, uint32_t idx,
+                                                  uint32_t shower) {
+#pragma clang fp contract(off)
+  if (!(mu > 0.0) || !(mu <= kMaxMean)) return 0u;
+  const uint32_t m = (mu <= kPoissonChunk) ? 1u : (uint32_t)ceil(mu / kPoissonChunk);
+  const double mc = mu / (double)m;
+  const double p0 = exp(-mc);
+  uint32_t total = 0;
+  for (uint32_t c = 0; c < m; ++c) {
+    const double u = u01d(philox(c, idx, shower, kDomCount, k0, k1).w[0]);
+    uint32_t k = 0;
+    double p = p0, F = p0;
+    while (u > F && k < kPoissonKmax) {
+      k += 1;
+      p = (p * mc) / (double)k;
+      F = F + p;
+    }
+    total += k;
+  }
+  return total;
+}
+
+// ---------------------------------------------------------------------------
+// Per-segment constants of photon generation, computed once per segment
+// (one lane per segment) and shared by all of its photons.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SegConst {
+  double x0, y0, z0, t0, inv_bc;   // start point, start time, 1/(beta c)
+  T dx, dy, dz, len;               // unit direction, length
+  T cos_c, sin_c;                  // Cherenkov cone (section 1.2)
+  T ax, ay, az;                    // unit bisector of direction and (0,0,-1)
+  uint32_t idx, shower;
+};
+
+// Unit bisector A of the track direction d and the downward normal: M_Rod
+// (section 1.2.1) is the half turn 2 A A^T - 1 about it, which maps the
+// downward axis onto d. For d straight up the bisector vanishes and the
+// half turn about x is used.
+template <typename T>
+__device__ __forceinline__ void seg_const(const SegView& s, int64_t i, const AtmDev& a, bool cherenkov,
+                                          SegConst<T>& c) {
+  const double dx = s.dx[i], dy = s.dy[i], dz = s.dz[i];
+  const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
+  const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+  c.x0 = s.x0[i];
+  c.y0 = s.y0[i];
+  c.z0 = s.z0[i];
+  c.t0 = s.t0[i];
+  c.inv_bc = 1.0 / (s.beta[i] * kC);
+  c.dx = (T)ux;
+  c.dy = (T)uy;
+  c.dz = (T)uz;
+  c.len = (T)s.len[i];
+  c.idx = seg_idx(s, i);
+  c.shower = seg_shower(s, i);
+  if (cherenkov) {
+    const double n = seg_index(s, i, a);
+    const double cc = 1.0 / (s.beta[i] * n);
+    c.cos_c = (T)cc;
+    c.sin_c = (T)sqrt((1.0 - cc) * (1.0 + cc));
+    double bx = ux, by = uy, bz = uz - 1.0;
+    const double bn = sqrt((bx * bx + by * by) + bz * bz);
+    if (bn > 0.0) {
+      bx /= bn;
+      by /= bn;
+      bz /= bn;
+    } else {
+      bx = 1.0;
+      by = 0.0;
+      bz = 0.0;
+    }
+    c.ax = (T)bx;
+    c.ay = (T)by;
+    c.az = (T)bz;
+  } else {
+    c.cos_c = c.sin_c = c.ax = c.ay = c.az = (T)0;
+  }
+}
+
+template <typename T>
+struct Photon {
+  T x, y, z, ux, uy, uz, lambda, w;
+  double t, path;
+  int32_t status;
+};
+
+__device__ __forceinline__ void sincos2pi(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
+__device__ __forceinline__ void sincos2pi(float u, float* s, float* c) { sincospif(2.0f * u, s, c); }
+
+// Photon j of a Cherenkov segment (section 1.2, Fig. 1): cone vector
+// p = (cos c sin Tc, sin c sin Tc, -cos Tc) at azimuth c = 2 pi u1
+// (section 1.2.1), rotated by M_Rod p = 2 (A.p) A - p, moved to the emission
+// point u0 along the track; wavelength from the 1/lambda^2 spectrum.
+template <typename T>
+__device__ __forceinline__ void gen_cherenkov(const SegConst<T>& c, uint32_t j, uint32_t k0, uint32_t k1,
+                                              T inv_l1, T inv_dl, Photon<T>& p) {
+  const U4 r = philox(j, c.idx, c.shower, kDomCher, k0, k1);
+  const T u0 = u01<T>(r.w[0]), u1 = u01<T>(r.w[1]), u2 = u01<T>(r.w[2]);
+  const T s = u0 * c.len;
+  p.x = (T)c.x0 + s * c.dx;
+  p.y = (T)c.y0 + s * c.dy;
+  p.z = (T)c.z0 + s * c.dz;
+  p.t = c.t0 + (double)s * c.inv_bc;
+  T sp, cp;
+  sincos2pi(u1, &sp, &cp);
+  const T px = cp * c.sin_c, py = sp * c.sin_c, pz = -c.cos_c;
+  const T ap2 = (T)2 * (c.ax * px + c.ay * py + c.az * pz);
+  p.ux = ap2 * c.ax - px;
+  p.uy = ap2 * c.ay - py;
+  p.uz = ap2 * c.az - pz;
+  p.lambda = (T)1 / (inv_l1 - u2 * inv_dl);
+  p.w = (T)1;
+  p.path = 0.0;
+  p.status = PHOTON_LANDED;
+}
+
+// Photon j of a fluorescence segment (section 1.1): isotropic direction,
+// emission point u0 along the track, line k = smallest k with u3 < cdf[k],
+// decided exactly on the 32-bit word against integer thresholds
+// thr[k] = ceil(cdf[k] 2^32 - 1/2).
+template <typename T>
+__device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint32_t k0, uint32_t k1,
+                                          const uint64_t* thr, const T* line_nm, int n_lines, Photon<T>& p) {
+  const U4 r = philox(j, c.idx, c.shower, kDomFluo, k0, k1);
+  const T u0 = u01<T>(r.w[0]), u1 = u01<T>(r.w[1]), u2 = u01<T>(r.w[2]);
+  const T s = u0 * c.len;
+  p.x = (T)c.x0 + s * c.dx;
+  p.y = (T)c.y0 + s * c.dy;
+  p.z = (T)c.z0 + s * c.dz;
+  p.t = c.t0 + (double)s * c.inv_bc;
+  const T ct = (T)1 - (T)2 * u1;
+  const T st = (T)2 * sqrt(u1 * ((T)1 - u1));
+  T sp, cp;
+  sincos2pi(u2, &sp, &cp);
+  p.ux = st * cp;
+  p.uy = st * sp;
+  p.uz = ct;
+  int k = 0;
+  const uint64_t w3 = r.w[3];
+  while (k < n_lines - 1 && !(w3 < thr[k])) ++k;
+  p.lambda = line_nm[k];
+  p.w = (T)1;
+  p.path = 0.0;
+  p.status = PHOTON_LANDED;
+}
+
+// ---------------------------------------------------------------------------
+// Propagation (section 2). With n sin(theta) = S conserved, the layer
+// integrals of dh/r, n dh/r, n^2 dh/r and rho n dh/r (r = sqrt(n^2 - S^2))
+// have closed forms in eps = n - 1 = eta0 rho, which falls exponentially
+// with scale height H inside a layer. For a piece [a, b] (a below b):
+//   C^2 = 1 - S^2 > 0:  int dh/r = (b-a)/C + (H/C) log((C r_b + C^2 + eps_b)
+//                                                   / (C r_a + C^2 + eps_a))
+//   C^2 < 0, K^2 = -C^2: int dh/r = (H/K) [asin((eps_a - K^2)/(eps_a S))
+//                                        - asin((eps_b - K^2)/(eps_b S))]
+//   C^2 = 0:           int dh/r = H (r_b/eps_b - r_a/eps_a)
+//   int n dh/r   = int dh/r + H log((n_a + r_a)/(n_b + r_b))
+//   int n^2 dh/r = int n dh/r + H (r_a - r_b)
+//   int rho n dh/r = H (rho_a - rho_b) (2 + eps_a + eps_b)/(r_a + r_b)
+// Differences are formed from eps_a expm1(-(b-a)/H) so that thin pieces and
+// nearly vertical rays keep full relative precision.
+// ---------------------------------------------------------------------------
+struct Piece4 {
+  double g0, p, o, t;  // int dh/r, path, optical path, density-weighted path
+};
+
+template <typename T>
+__device__ __forceinline__ void piece_integrals(T rho_a, T dh, T H, bool homog, T eta0, T C2, T S,
+                                                T& g0, T& pth, T& opt, T& col) {
+  const T eps_a = eta0 * rho_a;
+  const T na = (T)1 + eps_a;
+  if (homog) {
+    const T r = sqrt(C2 + eps_a * ((T)2 + eps_a));
+    g0 = dh / r;
+    pth = na * g0;
+    opt = na * pth;
+    col = rho_a * pth;
+    return;
+  }
+  const T em = expm1(-dh / H);          // rho_b/rho_a - 1 (<= 0)
+  const T drho = rho_a * em;            // rho_b - rho_a
+  const T d = eta0 * drho;              // eps_b - eps_a
+  const T eps_b = eps_a + d;
+  const T nb = (T)1 + eps_b;
+  const T ra = sqrt(C2 + eps_a * ((T)2 + eps_a));
+  const T rb = sqrt(C2 + eps_b * ((T)2 + eps_b));
+  const T rs = ra + rb;
+  const T two_e = (T)2 + eps_a + eps_b;
+  const T rd = -d * two_e / rs;         // r_a - r_b
+  if (C2 > (T)0) {
+    const T Cc = sqrt(C2);
+    const T den = Cc * ra + C2 + eps_a;
+    const T delta = d * ((T)1 + Cc * two_e / rs);
+    g0 = dh / Cc + (H / Cc) * log1p(delta / den);
+  } else if (C2 < (T)0) {
+    const T K2 = -C2;
+    const T Kk = sqrt(K2);
+    g0 = (H / Kk) * (asin((eps_a - K2) / (eps_a * S)) - asin((eps_b - K2) / (eps_b * S)));
+  } else {
+    g0 = H * (rb / eps_b - ra / eps_a);
+  }
+  const T lg = log1p((-d + rd) / (nb + rb));
+  pth = g0 + H * lg;
+  opt = pth + H * rd;
+  col = -H * drho * two_e / rs;
+}
+
+template <typename T>
+__device__ __forceinline__ T abs_coeff(const AtmDev& a, T lambda) {
+  if (a.n_abs <= 0) return (T)0;
+  const double l = (double)lambda;
+  if (l <= a.abs_l[0]) return (T)a.abs_k[0];
+  if (l >= a.abs_l[a.n_abs - 1]) return (T)a.abs_k[a.n_abs - 1];
+  int lo = 0, hi = a.n_abs - 1;  // abs_l[lo] <= l < abs_l[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.abs_l[mid] <= l) lo = mid; else hi = mid;
+  }
+  const double f = (l - a.abs_l[lo]) / (a.abs_l[hi] - a.abs_l[lo]);
+  return (T)(a.abs_k[lo] + f * (a.abs_k[hi] - a.abs_k[lo]));
+}
+
+// Threshold on |C^2| below which the float path evaluates a piece in double
+// (rays within about 13 degrees of the horizontal, where the float closed
+// forms lose digits to cancellation).
+constexpr float kNearHorizonC2 = 0.05f;
+
+template <typename T>
+__device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
+  if (p.status != PHOTON_LANDED) return;
+  if (!(p.uz < (T)0)) {
+    p.status = PHOTON_UP;
+    return;
+  }
+  if ((double)p.z < a.hobs) {
+    p.status = PHOTON_BELOW;
+    return;
+  }
+  const T un = sqrt(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz);
+  const T ux = p.ux / un, uy = p.uy / un, ce = -p.uz / un;
+  const T se = sqrt(ux * ux + uy * uy);
+
+  const double ze = (double)p.z;
+  const int le = layer_of(a, ze);
+  const double rho_e_d = a.rb[le] * exp(-(ze - a.hb[le]) / a.H[le]);
+  const T rho_e = (T)rho_e_d;
+  const T eta0 = (T)a.eta0;
+  const T eps_e = eta0 * rho_e;
+  const T ne = (T)1 + eps_e;
+  const T S = ne * se;
+  // 1 - S = ce^2/(1 + se) - eps_e se, without cancellation for S well below 1
+  const T one_m_S = ce * ce / ((T)1 + se) - eps_e * se;
+  const T C2 = one_m_S * ((T)1 + S);
+  const bool dbl = (sizeof(T) == 4) && !(fabs((float)C2) > kNearHorizonC2);
+  const double C2d = dbl ? ((double)ce * (double)ce / (1.0 + (double)se) - (double)eps_e * (double)se) *
+                               (1.0 + (double)ne * (double)se)
+                         : 0.0;
+
+  T g0 = (T)0, col = (T)0;
+  double pth = 0.0, opt = 0.0;
+  double top = ze;
+  T rho_top = rho_e;
+  for (int l = le; l >= a.l_obs; --l) {
+    const double bot = (l == a.l_obs) ? a.hobs : a.hb[l];
+    const double dh = top - bot;
+    // density at the bottom of the piece (known exactly at layer bases)
+    const double rho_bot = (l == a.l_obs) ? a.rho_obs : a.rb[l];
+    if (dh > 0.0) {
+      const bool homog = (a.homog_mask >> l) & 1;
+      if (sizeof(T) == 8 || dbl) {
+        double q0, q1, q2, q3;
+        const double Sd = (double)ne * (double)se;
+        piece_integrals<double>(rho_bot, dh, a.H[l], homog, a.eta0, sizeof(T) == 8 ? (double)C2 : C2d, Sd,
+                                q0, q1, q2, q3);
+        g0 += (T)q0;
+        pth += q1;
+        opt += q2;
+        col += (T)q3;
+      } else {
+        T q0, q1, q2, q3;
+        piece_integrals<T>((T)rho_bot, (T)dh, (T)a.H[l], homog, eta0, C2, S, q0, q1, q2, q3);
+        g0 += q0;
+        pth += (double)q1;
+        opt += (double)q2;
+        col += q3;
+      }
+    }
+    top = bot;
+    rho_top = (T)rho_bot;
+  }
+  (void)rho_top;
+  p.x = p.x + ux * ne * g0;
+  p.y = p.y + uy * ne * g0;
+  p.z = (T)a.hobs;
+  p.t = p.t + opt / kC;
+  p.path = pth;
+  const T tau = abs_coeff<T>(a, p.lambda) * col;
+  p.w = exp(-tau);
+  const T q = ne / (T)a.n_obs;
+  p.ux = ux * q;
+  p.uy = uy * q;
+  const T sl = se * q;
+  p.uz = -sqrt(((T)1 - sl) * ((T)1 + sl));
+  p.status = PHOTON_LANDED;
+}
+
+// ---------------------------------------------------------------------------
+// Telescope test: first sphere along the straight arrival line.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int telescope_hit(const Photon<T>& p, const double (*tel)[4], int n_tel, T& s_hit) {
+  int best = -1;
+  T best_s = (T)INFINITY;
+  for (int k = 0; k < n_tel; ++k) {
+    const T ox = p.x - (T)tel[k][0], oy = p.y - (T)tel[k][1], oz = p.z - (T)tel[k][2];
+    const T R = (T)tel[k][3];
+    const T b = p.ux * ox + p.uy * oy + p.uz * oz;
+    const T cc = (ox * ox + oy * oy + oz * oz) - R * R;
+    const T disc = b * b - cc;
+    if (disc < (T)0) continue;
+    const T s = -b - sqrt(disc);
+    if (s < best_s) {
+      best_s = s;
+      best = k;
+    }
+  }
+  s_hit = best_s;
+  return best;
+}
+
+}  // namespace ph

@@ -1,0 +1,358 @@
+"""Python binding of libphoton (C ABI in include/photon.h).
+
+Argument marshalling only: every step of the photon path runs in the HIP
+kernels of libphoton.so. PyTorch supplies device memory (tensor data
+pointers) and the stream (the current torch stream). There is no CPU
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphoton.so")
+
+OK, EINVAL, ECAPACITY, EHIP, ENODEV = 0, -1, -2, -3, -4
+FP64, FP32 = 0, 1
+CHERENKOV, FLUORESCENCE = 0, 1
+LANDED, HIT, UP, BELOW, OFFGRID, ABSORBED, INVALID = 0, 1, 2, 3, 4, 5, 6
+N_STATUS = 8
+SINK_STATUS, SINK_TELESCOPES, SINK_GRID = 0, 1, 2
+MAX_LAYERS, MAX_ABS, MAX_LINES, MAX_TELESCOPES = 8, 40, 32, 32
+
+P = C.c_void_p
+
+
+class Atmosphere(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("h_base", C.c_double * MAX_LAYERS),
+                ("scale_height", C.c_double * MAX_LAYERS), ("n0_minus_1", C.c_double),
+                ("h_obs", C.c_double), ("n_abs", C.c_int32), ("abs_lambda_nm", C.c_double * MAX_ABS),
+                ("abs_k_per_m", C.c_double * MAX_ABS)]
+
+
+class Segments(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, P) for f in (
+        "x0", "y0", "z0", "dx", "dy", "dz", "length", "beta", "t0", "dedx", "charge", "shower",
+        "index_in_shower")]
+
+
+class Emission(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("lambda_min_nm", C.c_double), ("lambda_max_nm", C.c_double),
+                ("yield_per_MeV", C.c_double), ("n_lines", C.c_int32),
+                ("line_nm", C.c_double * MAX_LINES), ("line_rel_yield", C.c_double * MAX_LINES)]
+
+
+class Block(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("n_photons", C.c_int64), ("precision", C.c_int32)] + [
+        (f, P) for f in ("x", "y", "z", "ux", "uy", "uz", "wavelength_nm", "weight", "t_ns", "path_m",
+                         "segment", "j", "status")]
+
+
+class Hits(C.Structure):
+    _fields_ = [("capacity", C.c_int64)] + [(f, P) for f in (
+        "count", "segment", "j", "telescope", "x", "y", "z", "t_ns", "ux", "uy", "uz", "wavelength_nm",
+        "weight")]
+
+
+class Sink(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("status_totals", P), ("n_tel", C.c_int32),
+                ("tel", (C.c_double * 4) * MAX_TELESCOPES), ("hits", Hits), ("x_min", C.c_double),
+                ("y_min", C.c_double), ("cell", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("grid_count", P), ("grid_weight", P)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("chunk", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
+class PhotonError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libphoton error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libphoton.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.photon_version.restype = C.c_char_p
+        L.photon_last_error.restype = C.c_char_p
+        L.photon_init.restype = C.c_int
+        L.photon_gen_cherenkov.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P]
+        L.photon_gen_fluor.argtypes = [P, P, P, P, C.c_int32, C.c_double, C.c_uint64, C.c_int32, P, P, P, P]
+        L.photon_propagate.argtypes = [P, P, P]
+        L.photon_collect.argtypes = [P, P, P, P]
+        L.photon_run_fused.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, C.c_int64, P, P, P]
+        for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
+                  "photon_run_fused"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise PhotonError(rc, lib().photon_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def version():
+    return lib().photon_version().decode()
+
+
+def init():
+    _check(lib().photon_init())
+
+
+# ------------------------------------------------------------------ inputs --
+def atmosphere(d: dict) -> Atmosphere:
+    a = Atmosphere()
+    hb, H = d["h_base"], d["scale_height"]
+    a.n_layers = len(hb)
+    for i in range(min(len(hb), MAX_LAYERS)):
+        a.h_base[i] = float(hb[i])
+        a.scale_height[i] = float(H[i])
+    a.n0_minus_1 = float(d["n0_minus_1"])
+    a.h_obs = float(d["h_obs"])
+    lam, k = d.get("abs_lambda_nm"), d.get("abs_k_per_m")
+    if lam is not None and len(lam):
+        a.n_abs = len(lam)
+        for i in range(min(len(lam), MAX_ABS)):
+            a.abs_lambda_nm[i] = float(lam[i])
+            a.abs_k_per_m[i] = float(k[i])
+    return a
+
+
+class DeviceSegments:
+    """Segment arrays resident on the GPU (float64 / int32 / uint32)."""
+
+    F64 = ("x0", "y0", "z0", "dx", "dy", "dz", "length", "beta", "t0")
+
+    def __init__(self, seg: dict, device="cuda"):
+        self.t = {}
+        for f in self.F64:
+            self.t[f] = torch.as_tensor(np.ascontiguousarray(seg[f], np.float64), device=device)
+        if seg.get("dedx") is not None:
+            self.t["dedx"] = torch.as_tensor(np.ascontiguousarray(seg["dedx"], np.float64), device=device)
+        if seg.get("charge") is not None:
+            self.t["charge"] = torch.as_tensor(np.ascontiguousarray(seg["charge"], np.int32), device=device)
+        for f in ("shower", "index_in_shower"):
+            if seg.get(f) is not None:
+                a = np.ascontiguousarray(seg[f], np.uint32).view(np.int32)
+                self.t[f] = torch.as_tensor(a, device=device)
+        self.n = int(self.t["x0"].numel())
+
+    def struct(self) -> Segments:
+        s = Segments()
+        s.n = self.n
+        for f in self.F64 + ("dedx", "charge", "shower", "index_in_shower"):
+            if f in self.t:
+                setattr(s, f, self.t[f].data_ptr())
+        return s
+
+
+class PhotonBlock:
+    """The common photon block (structure of arrays) on the GPU."""
+
+    REAL = ("x", "y", "z", "ux", "uy", "uz", "wavelength_nm", "weight")
+
+    def __init__(self, capacity: int, precision: int, device="cuda"):
+        dt = torch.float64 if precision == FP64 else torch.float32
+        self.precision = precision
+        self.capacity = int(capacity)
+        self.n_photons = 0
+        n = max(self.capacity, 1)
+        self.t = {f: torch.empty(n, dtype=dt, device=device) for f in self.REAL}
+        self.t["t_ns"] = torch.empty(n, dtype=torch.float64, device=device)
+        self.t["path_m"] = torch.empty(n, dtype=torch.float64, device=device)
+        self.t["segment"] = torch.empty(n, dtype=torch.int32, device=device)
+        self.t["j"] = torch.empty(n, dtype=torch.int32, device=device)
+        self.t["status"] = torch.empty(n, dtype=torch.int32, device=device)
+
+    def struct(self) -> Block:
+        b = Block()
+        b.capacity = self.capacity
+        b.n_photons = self.n_photons
+        b.precision = self.precision
+        for f, v in self.t.items():
+            setattr(b, f, v.data_ptr())
+        return b
+
+    def numpy(self) -> dict:
+        n = self.n_photons
+        out = {f: v[:n].cpu().numpy() for f, v in self.t.items()}
+        out["segment"] = out["segment"].view(np.uint32)
+        out["j"] = out["j"].view(np.uint32)
+        return out
+
+
+class HitBuffer:
+    """Telescope hit records on the GPU."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        self.capacity = int(capacity)
+        n = max(self.capacity, 1)
+        self.t = dict(count=torch.zeros(1, dtype=torch.int64, device=device),
+                      segment=torch.empty(n, dtype=torch.int32, device=device),
+                      j=torch.empty(n, dtype=torch.int32, device=device),
+                      telescope=torch.empty(n, dtype=torch.int32, device=device))
+        for f in ("x", "y", "z", "t_ns"):
+            self.t[f] = torch.empty(n, dtype=torch.float64, device=device)
+        for f in ("ux", "uy", "uz", "wavelength_nm", "weight"):
+            self.t[f] = torch.empty(n, dtype=torch.float32, device=device)
+
+    def clear(self):
+        self.t["count"].zero_()
+
+    def struct(self) -> Hits:
+        h = Hits()
+        h.capacity = self.capacity
+        for f, v in self.t.items():
+            setattr(h, f, v.data_ptr())
+        return h
+
+    def count(self) -> int:
+        return int(self.t["count"].item())
+
+    def numpy(self) -> dict:
+        n = min(self.count(), self.capacity)
+        out = {f: v[:n].cpu().numpy() for f, v in self.t.items() if f != "count"}
+        out["segment"] = out["segment"].view(np.uint32)
+        out["j"] = out["j"].view(np.uint32)
+        return out
+
+
+def status_totals(device="cuda"):
+    return torch.zeros(N_STATUS, dtype=torch.int64, device=device)
+
+
+def sink_status(totals) -> Sink:
+    s = Sink()
+    s.kind = SINK_STATUS
+    s.status_totals = _ptr(totals).value
+    return s
+
+
+def sink_telescopes(tel: np.ndarray, hits: HitBuffer, totals=None) -> Sink:
+    s = Sink()
+    s.kind = SINK_TELESCOPES
+    s.status_totals = None if totals is None else totals.data_ptr()
+    tel = np.asarray(tel, np.float64).reshape(-1, 4)
+    s.n_tel = tel.shape[0]
+    for k in range(min(tel.shape[0], MAX_TELESCOPES)):
+        for c in range(4):
+            s.tel[k][c] = float(tel[k, c])
+    s.hits = hits.struct()
+    return s
+
+
+def sink_grid(x_min, y_min, cell, nx, ny, grid_count, grid_weight, totals=None) -> Sink:
+    s = Sink()
+    s.kind = SINK_GRID
+    s.status_totals = None if totals is None else totals.data_ptr()
+    s.x_min, s.y_min, s.cell, s.nx, s.ny = float(x_min), float(y_min), float(cell), int(nx), int(ny)
+    s.grid_count = grid_count.data_ptr()
+    s.grid_weight = grid_weight.data_ptr()
+    return s
+
+
+def emission_cherenkov(lmin=300.0, lmax=600.0) -> Emission:
+    e = Emission()
+    e.kind = CHERENKOV
+    e.lambda_min_nm, e.lambda_max_nm = float(lmin), float(lmax)
+    return e
+
+
+def emission_fluor(line_nm, line_rel, yield_per_MeV) -> Emission:
+    e = Emission()
+    e.kind = FLUORESCENCE
+    e.yield_per_MeV = float(yield_per_MeV)
+    e.n_lines = len(line_nm)
+    for k in range(min(len(line_nm), MAX_LINES)):
+        e.line_nm[k] = float(line_nm[k])
+        e.line_rel_yield[k] = float(line_rel[k])
+    return e
+
+
+# --------------------------------------------------------------- entry points --
+def gen_cherenkov(seg: DeviceSegments, atm: Atmosphere, lmin, lmax, seed, precision, counts, offsets,
+                  block: PhotonBlock | None = None):
+    s = seg.struct()
+    b = None if block is None else block.struct()
+    _check(lib().photon_gen_cherenkov(C.byref(s), C.byref(atm), float(lmin), float(lmax), int(seed),
+                                      int(precision), _ptr(counts), _ptr(offsets),
+                                      None if b is None else C.byref(b), _stream()))
+
+
+def gen_fluor(seg: DeviceSegments, atm: Atmosphere, line_nm, line_rel, yield_per_MeV, seed, precision,
+              counts, offsets, block: PhotonBlock | None = None):
+    s = seg.struct()
+    b = None if block is None else block.struct()
+    ln = np.ascontiguousarray(line_nm, np.float64)
+    lr = np.ascontiguousarray(line_rel, np.float64)
+    _check(lib().photon_gen_fluor(C.byref(s), C.byref(atm), ln.ctypes.data, lr.ctypes.data, len(ln),
+                                  float(yield_per_MeV), int(seed), int(precision), _ptr(counts),
+                                  _ptr(offsets), None if b is None else C.byref(b), _stream()))
+
+
+def count(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, device="cuda"):
+    """Counts (u32 as int32 tensor) and offsets (u64 as int64 tensor)."""
+    counts = torch.empty(max(seg.n, 1), dtype=torch.int32, device=device)
+    offsets = torch.empty(seg.n + 1, dtype=torch.int64, device=device)
+    if em.kind == CHERENKOV:
+        gen_cherenkov(seg, atm, em.lambda_min_nm, em.lambda_max_nm, seed, FP64, counts, offsets)
+    else:
+        gen_fluor(seg, atm, list(em.line_nm)[:em.n_lines], list(em.line_rel_yield)[:em.n_lines],
+                  em.yield_per_MeV, seed, FP64, counts, offsets)
+    return counts[:seg.n], offsets
+
+
+def generate(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precision, offsets,
+             block: PhotonBlock):
+    dummy = offsets  # counts are not written when a block is given
+    if em.kind == CHERENKOV:
+        gen_cherenkov(seg, atm, em.lambda_min_nm, em.lambda_max_nm, seed, precision, dummy, offsets, block)
+    else:
+        gen_fluor(seg, atm, list(em.line_nm)[:em.n_lines], list(em.line_rel_yield)[:em.n_lines],
+                  em.yield_per_MeV, seed, precision, dummy, offsets, block)
+
+
+def propagate(block: PhotonBlock, atm: Atmosphere):
+    b = block.struct()
+    _check(lib().photon_propagate(C.byref(b), C.byref(atm), _stream()))
+
+
+def collect(block: PhotonBlock, atm: Atmosphere, sink: Sink):
+    b = block.struct()
+    _check(lib().photon_collect(C.byref(b), C.byref(atm), C.byref(sink), _stream()))
+
+
+def run_fused(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precision, offsets, n_photons,
+              sink: Sink, tuning: Tuning | None = None):
+    s = seg.struct()
+    _check(lib().photon_run_fused(C.byref(s), C.byref(atm), C.byref(em), int(seed), int(precision),
+                                  _ptr(offsets), int(n_photons), C.byref(sink),
+                                  None if tuning is None else C.byref(tuning), _stream()))
+
+
+def tuning(block=256, chunk=4096, blocks_per_cu=0) -> Tuning:
+    t = Tuning()
+    t.block, t.chunk, t.blocks_per_cu = int(block), int(chunk), int(blocks_per_cu)
+    return t

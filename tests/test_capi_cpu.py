@@ -1,0 +1,149 @@
+"""The C ABI on the host: the library loads, exports every declared entry
+point, and validates arguments before touching a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "photon.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(photon_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def ph():
+    from paper_2309_15861_amd import photon
+    photon.lib()
+    return photon
+
+
+def test_every_declared_symbol_is_exported(ph):
+    names = declared_functions()
+    assert {"photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
+            "photon_run_fused", "photon_init", "photon_last_error", "photon_version"} <= set(names)
+    L = ph.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version(ph):
+    assert "gfx950" in ph.version()
+
+
+def _valid_atm(ph):
+    from paper_2309_15861_amd import workloads as W
+    return ph.atmosphere(W.default_atmosphere(absorption=True))
+
+
+def _fake_segments(ph, n=10):
+    s = ph.Segments()
+    s.n = n
+    for f in ("x0", "y0", "z0", "dx", "dy", "dz", "length", "beta", "t0"):
+        setattr(s, f, 0x1000)
+    return s
+
+
+def _gen(ph, seg, atm, lmin=300.0, lmax=600.0, prec=0, counts=0x2000, offsets=0x3000, block=None):
+    L = ph.lib()
+    return L.photon_gen_cherenkov(None if seg is None else C.byref(seg), None if atm is None else C.byref(atm),
+                                  lmin, lmax, 1, prec, counts, offsets,
+                                  None if block is None else C.byref(block), None)
+
+
+def test_validation_errors(ph):
+    atm = _valid_atm(ph)
+    seg = _fake_segments(ph)
+    assert _gen(ph, None, atm) == ph.EINVAL
+    assert _gen(ph, seg, None) == ph.EINVAL
+    assert _gen(ph, seg, atm, lmin=600.0, lmax=300.0) == ph.EINVAL
+    assert "lambda" in ph.lib().photon_last_error().decode()
+    assert _gen(ph, seg, atm, lmin=0.0) == ph.EINVAL
+    assert _gen(ph, seg, atm, prec=7) == ph.EINVAL
+    assert _gen(ph, seg, atm, offsets=None) == ph.EINVAL
+    bad = _fake_segments(ph)
+    bad.n = -1
+    assert _gen(ph, bad, atm) == ph.EINVAL
+    nul = _fake_segments(ph)
+    nul.beta = None
+    assert _gen(ph, nul, atm) == ph.EINVAL
+    assert "beta" in ph.lib().photon_last_error().decode()
+    for mutate in (lambda a: setattr(a, "n_layers", 0), lambda a: setattr(a, "n_layers", 9),
+                   lambda a: a.scale_height.__setitem__(2, 0.0),
+                   lambda a: a.h_base.__setitem__(2, 3000.0), lambda a: a.h_base.__setitem__(0, 5.0),
+                   lambda a: setattr(a, "n0_minus_1", -1e-4), lambda a: setattr(a, "n_abs", 41),
+                   lambda a: a.abs_lambda_nm.__setitem__(3, 100.0),
+                   lambda a: a.abs_k_per_m.__setitem__(0, -1.0),
+                   lambda a: setattr(a, "h_obs", float("nan"))):
+        a = _valid_atm(ph)
+        mutate(a)
+        assert _gen(ph, seg, a) == ph.EINVAL
+
+
+def test_fluorescence_and_block_validation(ph):
+    import numpy as np
+    L = ph.lib()
+    atm = _valid_atm(ph)
+    seg = _fake_segments(ph)
+    lines = np.array([337.0, 357.0])
+    rel = np.array([1.0, 0.5])
+    # dedx missing for fluorescence
+    rc = L.photon_gen_fluor(C.byref(seg), C.byref(atm), lines.ctypes.data, rel.ctypes.data, 2, 10.0, 1, 0,
+                            0x2000, 0x3000, None, None)
+    assert rc == ph.EINVAL and "dedx" in L.photon_last_error().decode()
+    seg.dedx = 0x1000
+    zero = np.zeros(2)
+    rc = L.photon_gen_fluor(C.byref(seg), C.byref(atm), lines.ctypes.data, zero.ctypes.data, 2, 10.0, 1, 0,
+                            0x2000, 0x3000, None, None)
+    assert rc == ph.EINVAL
+    rc = L.photon_gen_fluor(C.byref(seg), C.byref(atm), lines.ctypes.data, rel.ctypes.data, 0, 10.0, 1, 0,
+                            0x2000, 0x3000, None, None)
+    assert rc == ph.EINVAL
+    rc = L.photon_gen_fluor(C.byref(seg), C.byref(atm), lines.ctypes.data, rel.ctypes.data, 2, -1.0, 1, 0,
+                            0x2000, 0x3000, None, None)
+    assert rc == ph.EINVAL
+    # photon block over capacity
+    blk = ph.Block()
+    blk.capacity, blk.n_photons, blk.precision = 10, 11, 0
+    assert _gen(ph, _fake_segments(ph), atm, block=blk) == ph.ECAPACITY
+    blk.n_photons, blk.precision = 5, 1
+    assert _gen(ph, _fake_segments(ph), atm, block=blk) == ph.EINVAL   # precision mismatch
+
+
+def test_sink_validation(ph):
+    L = ph.lib()
+    atm = _valid_atm(ph)
+    blk = ph.Block()
+    blk.capacity, blk.n_photons, blk.precision = 0, 0, 0
+    s = ph.Sink()
+    s.kind = 9
+    assert L.photon_collect(C.byref(blk), C.byref(atm), C.byref(s), None) == ph.EINVAL
+    s.kind = ph.SINK_TELESCOPES
+    s.n_tel = 0
+    assert L.photon_collect(C.byref(blk), C.byref(atm), C.byref(s), None) == ph.EINVAL
+    s.n_tel = 1
+    s.tel[0][3] = -1.0
+    assert L.photon_collect(C.byref(blk), C.byref(atm), C.byref(s), None) == ph.EINVAL
+    s.kind = ph.SINK_GRID
+    s.nx, s.ny, s.cell = 0, 4, 1.0
+    assert L.photon_collect(C.byref(blk), C.byref(atm), C.byref(s), None) == ph.EINVAL
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device path")
+def test_valid_arguments_without_device_report_enodev(ph):
+    atm = _valid_atm(ph)
+    assert _gen(ph, _fake_segments(ph), atm) == ph.ENODEV
+    assert ph.lib().photon_init() == ph.ENODEV
+
+
+def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
+    from paper_2309_15861_amd import photon
+    monkeypatch.setattr(photon, "_lib", None)
+    monkeypatch.setattr(photon, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        photon.lib()
