@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Photons propagated per second on one MI355X.
+
+Workload: shower-shaped Cherenkov input (2e5 electron segments following a
+1 TeV gamma longitudinal profile, E^-2 energies from 20 MeV, lateral
+sigma 50 m, zenith 20 deg), five-layer exponential atmosphere with
+wavelength-dependent absorption, 16 telescope spheres (R = 6 m, 100 m grid)
+at 2.2 km. One step = the whole hot path on resident inputs: per-segment
+counts and offsets, clearing the outputs, and the fused persistent kernel
+(generation, propagation, telescope collection). The headline value is the
+FP32-bulk form (float generation and bending, double time and path); the
+plain FP64 form is timed beside it. The FP64 CPU oracle is timed on the
+host's cores over the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9          # VALU lane-slots/s: CUs x SIMDs x lanes x clock
+# Algorithmic VALU issue slots per photon (quarter-rate operations count 4):
+# Philox4x32-10 (10 rounds of two 32x32->64 multiplies and two 3-way xors,
+# ~100-120), uniforms (~8), cone/rotation/translation/wavelength (~30),
+# propagation over ~2 layer pieces (~90), absorption (~15), telescope
+# selection and hit test (~30).
+SLOTS_PER_PHOTON = {"fp32": 300.0, "fp64": 750.0}
+PMC_FILE = os.path.join(ROOT, "profiles", "fused_shower_fp32_traffic.json")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("photon.hip", "photon_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2309_15861_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per fused launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source."""
+    try:
+        with open(PMC_FILE) as fh:
+            d = json.load(fh)
+    except OSError:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(seg, atm_dict, tel, seed, max_threads=16):
+    """The FP64 oracle on the host: counts, photon generation + propagation
+    and telescope test for every segment, in batches of 20000 segments."""
+    import numpy as np
+
+    import oracle.oracle as O
+    from paper_2309_15861_amd import workloads as W
+
+    threads = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+    O.set_threads(threads)
+    oatm = O.Atmosphere.from_dict(atm_dict)
+    n_obs = oatm.index(atm_dict["h_obs"])
+    n = len(seg["x0"])
+    photons = 0
+    t0 = time.perf_counter()
+    for b0 in range(0, n, 20000):
+        sub = W.subsample(seg, np.arange(b0, min(n, b0 + 20000)))
+        cnt = O.counts(sub, oatm, "cherenkov", seed)[0]
+        off = O.offsets_of(cnt)
+        ph = O.photons_all(sub, oatm, "cherenkov", seed, off)
+        O.telescopes(ph, tel, n_obs)
+        photons += int(off[-1])
+    dt = time.perf_counter() - t0
+    return dict(value=photons / dt, unit="photons/s", cores=O.num_threads(), kind="oracle",
+                sample=f"all {n} segments ({photons} photons) in batches of 20000 segments; "
+                       f"counts + generation + quadrature propagation + telescope test; {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the photon path would shard by whole showers or by photon-prefix ranges, "
+              "with one all-reduce of the small grids); use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    seed = 2
+    seg = W.shower_cherenkov()
+    a = W.default_atmosphere(absorption=True)
+    tel = W.telescopes_16()
+    d = ph.DeviceSegments(seg)
+    atm = ph.atmosphere(a)
+    em = ph.emission_cherenkov(300.0, 600.0)
+    n = d.n
+    counts = torch.empty(n, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    ph.gen_cherenkov(d, atm, 300.0, 600.0, seed, ph.FP64, counts, offsets)
+    torch.cuda.synchronize()
+    total = int(offsets[-1].item())
+    hits = ph.HitBuffer(max(total // 8, 1024))
+    totals = ph.status_totals()
+    sink = ph.sink_telescopes(tel, hits, totals)
+    stream = torch.cuda.current_stream()
+
+    def step(prec, ev=None):
+        ph.gen_cherenkov(d, atm, 300.0, 600.0, seed, ph.FP64, counts, offsets)
+        hits.t["count"].zero_()
+        totals.zero_()
+        if ev is not None:
+            ev[0].record(stream)
+        ph.run_fused(d, atm, em, seed, prec, offsets, -1, sink)
+        if ev is not None:
+            ev[1].record(stream)
+
+    results = {}
+    for name, prec in (("fp32", ph.FP32), ("fp64", ph.FP64)):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for k in range(args.steps):
+            step(prec, evs[k])
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        fused_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        tot = totals.cpu().numpy()
+        assert int(tot.sum()) == total, (tot, total)
+        assert hits.count() <= hits.capacity
+        results[name] = dict(ms_per_step=ms / args.steps, fused_ms=fused_ms,
+                             photons_per_s=total * args.steps / (ms * 1e-3),
+                             hits=hits.count(), status_totals=[int(x) for x in tot])
+
+    r32 = results["fp32"]
+    achieved = SLOTS_PER_PHOTON["fp32"] * total / (r32["fused_ms"] * 1e-3)
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+                    frac=achieved / PEAK_SLOTS, traffic=traffic_per_launch(),
+                    kernel="k_fused<float,256>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
+                    fused_ms=r32["fused_ms"])
+    r64 = results["fp64"]
+    out = {
+        "metric": "photons propagated/s on 1 MI355X (FP64 vs FP32-split, batched) + % roofline",
+        "value": r32["photons_per_s"], "unit": "photons/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "shower-shaped Cherenkov: 2e5 segments, 1 TeV gamma profile, zenith 20 deg, "
+                               "16 telescopes R=6 m on a 100 m grid, absorption, 300-600 nm",
+                   "segments": n, "photons": total, "precision": "fp32 bulk, fp64 time/path"},
+        "roofline": roofline,
+        "fp64": {"value": r64["photons_per_s"], "ms_per_step": r64["ms_per_step"], "fused_ms": r64["fused_ms"],
+                 "frac": SLOTS_PER_PHOTON["fp64"] * total / (r64["fused_ms"] * 1e-3) / PEAK_SLOTS},
+        "hits": r32["hits"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(seg, a, tel, seed)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -248,8 +248,12 @@ int photon_collect(const photon_block* in, const photon_atmosphere* atm, const p
    photon of `seg` in registers, without a photon block, by one persistent
    kernel that takes work chunks of the photon index space from an atomic
    queue. `offsets` (n+1, device) comes from a generation call with
-   out == NULL for the same segments, emission and seed; n_photons must equal
-   offsets[n]. Results equal those of gen + propagate + collect. */
+   out == NULL for the same segments, emission and seed. n_photons is the
+   number of photon slots to process: offsets[n], or -1 to have the kernel
+   read offsets[n] on the device (no host round trip; slots beyond
+   offsets[n] count as INVALID). Results equal those of gen + propagate +
+   collect. One call at a time per device: calls share the device's work
+   queue counter. */
 int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
                      const photon_emission* em, uint64_t seed, int32_t precision,
                      const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,

@@ -416,8 +416,11 @@ __global__ __launch_bounds__(BS) void k_fused(SegView seg, int64_t n_seg, AtmDev
   const bool cher = g.kind == PHOTON_CHERENKOV;
   StatusCounter sc;
   sc.clear();
-  // slots at or beyond offsets[n_seg] belong to no segment: counted INVALID
-  const uint64_t lim = min((uint64_t)n_ph, offsets[n_seg]);
+  // n_ph < 0: the photon total is offsets[n_seg], read here on the device.
+  // Slots at or beyond offsets[n_seg] belong to no segment: counted INVALID.
+  const uint64_t total = offsets[n_seg];
+  if (n_ph < 0) n_ph = (int64_t)total;
+  const uint64_t lim = min((uint64_t)n_ph, total);
 
   for (;;) {
     if (tid == 0) s_c0 = atomicAdd(cursor, (unsigned long long)chunk);
@@ -791,8 +794,10 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<T, BS>, BS, 0) != hipSuccess || occ < 1) occ = 1;
   if (bpc > 0 && bpc < occ) occ = bpc;
   int64_t grid = (int64_t)dev->cu * occ;
-  const int64_t chunks = ceil_div(n_ph, chunk);
-  if (grid > chunks) grid = chunks;
+  if (n_ph >= 0) {
+    const int64_t chunks = ceil_div(n_ph, chunk);
+    if (grid > chunks) grid = chunks;
+  }
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
   hipLaunchKernelGGL((k_fused<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, sv, n, atm, g, k0, k1, offsets, n_ph,
@@ -903,7 +908,7 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm, c
   if ((rc = prep_precision(precision))) return rc;
   if ((rc = prep_sink(sink, &sk))) return rc;
   if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
-  if (n_photons < 0) return fail(PHOTON_EINVAL, "n_photons < 0");
+  if (n_photons < -1) return fail(PHOTON_EINVAL, "n_photons must be >= 0, or -1 (total read on the device)");
   if (tuning && (tuning->block != 128 && tuning->block != 256 && tuning->block != 512))
     return fail(PHOTON_EINVAL, "tuning.block must be 128, 256 or 512");
   if (tuning && (tuning->chunk < tuning->block || tuning->chunk % tuning->block))
