@@ -259,6 +259,42 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
                      const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
                      const photon_tuning* tuning, void* stream);
 
+/* ---- captured steps (HIP graphs) and launch-shape tuning ------------------ */
+
+/* A plan is one whole step captured into a HIP graph: per-segment counts and
+   offsets (as photon_gen_cherenkov / photon_gen_fluor with out == NULL),
+   clearing of the sink outputs (status totals, hit counter, grid) by fill
+   kernels, and the fused persistent kernel reading the photon total on the
+   device. Replays reuse the pointers given at creation; the caller keeps those
+   buffers alive and unchanged in size until photon_plan_destroy. Creation
+   validates like photon_run_fused and needs the device work area, which it
+   creates (photon_init). */
+typedef struct photon_plan_s* photon_plan;
+
+int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm,
+                       const photon_emission* em, uint64_t seed, int32_t precision,
+                       uint32_t* counts, uint64_t* offsets, const photon_sink* sink,
+                       const photon_tuning* tuning, photon_plan* out);
+
+/* Enqueues one replay of the plan on `stream`. */
+int photon_plan_launch(photon_plan plan, void* stream);
+
+/* Releases the graph (after the last replay has completed). NULL is a no-op. */
+int photon_plan_destroy(photon_plan plan);
+
+/* Launch-shape tuning of the fused kernel: runs photon_run_fused once per
+   candidate shape (after one untimed run each), `reps` timed runs per
+   candidate measured with HIP events on `stream`, and returns the fastest in
+   *best with its median time in *best_ms. The sink outputs are left in an
+   unspecified state (the caller clears them). Synchronises `stream`.
+   Errors: EINVAL (no candidates, reps < 1, invalid candidate), as
+   photon_run_fused otherwise. */
+int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm,
+                    const photon_emission* em, uint64_t seed, int32_t precision,
+                    const uint64_t* offsets, const photon_sink* sink,
+                    const photon_tuning* candidates, int32_t n_candidates, int32_t reps,
+                    photon_tuning* best, float* best_ms, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

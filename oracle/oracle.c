@@ -664,6 +664,32 @@ void or_grid(const or_photon* ph, int64_t count, double x_min, double y_min, dou
   for (int64_t q = 0; q < count; ++q) cell_of[q] = or_grid_cell(&ph[q], x_min, y_min, cell, nx, ny);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Ground photon density by Gaussian splatting (the differentiable form).   */
+/* Each landed photon adds w * exp(-|r_g - r_l|^2 / (2 sigma^2)) /         */
+/* (2 pi sigma^2) to every cell whose centre r_g lies within trunc*sigma   */
+/* of the landing point in x and in y.                                      */
+/* ------------------------------------------------------------------------ */
+void or_splat(const or_photon* ph, const double* weight, int64_t count, double x_min, double y_min,
+              double cell, int32_t nx, int32_t ny, double sigma, double trunc, double* D) {
+  const double norm = 1.0 / (2.0 * OR_PI * sigma * sigma);
+  const double reach = trunc * sigma;
+  for (int64_t q = 0; q < count; ++q) {
+    if (ph[q].status != OR_LANDED) continue;
+    const double x = ph[q].xl, y = ph[q].yl;
+    for (int32_t iy = 0; iy < ny; ++iy) {
+      const double gy = y_min + (iy + 0.5) * cell;
+      if (fabs(gy - y) > reach) continue;
+      for (int32_t ix = 0; ix < nx; ++ix) {
+        const double gx = x_min + (ix + 0.5) * cell;
+        if (fabs(gx - x) > reach) continue;
+        const double r2 = (gx - x) * (gx - x) + (gy - y) * (gy - y);
+        D[(int64_t)iy * nx + ix] += weight[q] * norm * exp(-r2 / (2.0 * sigma * sigma));
+      }
+    }
+  }
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

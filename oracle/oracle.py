@@ -90,6 +90,8 @@ def lib():
         L.or_telescopes.argtypes = [P, C.c_int64, P, C.c_int32, C.c_double, P, P]
         L.or_grid.argtypes = [P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32,
                               C.c_int32, P]
+        L.or_splat.argtypes = [P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                               C.c_double, C.c_double, P]
         L.or_num_threads.restype = C.c_int
         L.or_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -296,3 +298,31 @@ def line_cdf(rel):
     cdf = np.zeros(len(rel))
     lib().or_line_cdf(_ptr(rel), len(rel), _ptr(cdf))
     return cdf
+
+
+def splat(ph: np.ndarray, weight: np.ndarray, x_min, y_min, cell, nx, ny, sigma, trunc=4.0):
+    """Gaussian-splatted density (ny, nx) of landed photons with weights."""
+    ph = np.ascontiguousarray(ph)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    D = np.zeros(int(ny) * int(nx))
+    lib().or_splat(_ptr(ph), _ptr(w), len(ph), float(x_min), float(y_min), float(cell), int(nx), int(ny),
+                   float(sigma), float(trunc), _ptr(D))
+    return D.reshape(int(ny), int(nx))
+
+
+def splat_density(seg: dict, atm: "Atmosphere", counts0, mu0, seed, grid: dict, sigma, trunc=4.0,
+                  lambda_nm=(300.0, 600.0)):
+    """Density of the differentiable form: Cherenkov photons of every segment
+    with its frozen count counts0 (drawn at the nominal parameters), generated
+    and propagated under the parameters in seg/atm, weighted by
+    mu(theta)/mu0 (the mean at the current parameters over the nominal one)
+    times the transmission exp(-tau)."""
+    cnt = np.asarray(counts0, np.int64)
+    s_list = np.repeat(np.arange(len(cnt)), cnt)
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    j_list = np.arange(off[-1]) - off[s_list]
+    ph = photons(seg, atm, "cherenkov", seed, s_list, j_list, lambda_nm=lambda_nm)
+    _, mu, _ = counts(seg, atm, "cherenkov", seed, lambda_nm=lambda_nm)
+    ratio = np.where(np.asarray(mu0) > 0, mu / np.where(np.asarray(mu0) > 0, mu0, 1.0), 0.0)
+    w = ratio[s_list] * ph["weight"]
+    return splat(ph, w, grid["x_min"], grid["y_min"], grid["cell"], grid["nx"], grid["ny"], sigma, trunc)

@@ -200,6 +200,11 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // -------------------------------------------------------------- generation --
 template <typename T>
 __device__ __forceinline__ void generate(const SegConst<T>& c, uint32_t j, const GenParams& g, uint32_t k0,
@@ -668,6 +673,7 @@ struct DeviceState {
   bool ok = false;
   int cu = 0;
   unsigned long long* work = nullptr;  // [0] = fused work cursor
+  int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fused blocks per CU by [precision][block 128/256/512]
 };
 std::mutex g_mu;
 DeviceState g_dev[64];
@@ -786,12 +792,35 @@ int launch_collect(const photon_block* b, const AtmDev& atm, const SinkDev& sk, 
   return check_launch();
 }
 
+constexpr int bs_slot(int bs) { return bs == 128 ? 0 : (bs == 256 ? 1 : 2); }
+
+// Resident blocks per CU of a fused variant, queried once per device (the
+// query is not a stream operation, but it is kept out of captured steps).
+template <typename T, int BS>
+int fused_occupancy(DeviceState* dev) {
+  int& o = dev->occ[sizeof(T) == 8 ? 0 : 1][bs_slot(BS)];
+  if (o == 0) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<T, BS>, BS, 0) != hipSuccess || occ < 1) occ = 1;
+    o = occ;
+  }
+  return o;
+}
+
+void warm_occupancy(DeviceState* dev) {
+  fused_occupancy<float, 128>(dev);
+  fused_occupancy<float, 256>(dev);
+  fused_occupancy<float, 512>(dev);
+  fused_occupancy<double, 128>(dev);
+  fused_occupancy<double, 256>(dev);
+  fused_occupancy<double, 512>(dev);
+}
+
 template <typename T, int BS>
 int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                     const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
                     DeviceState* dev, hipStream_t st) {
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<T, BS>, BS, 0) != hipSuccess || occ < 1) occ = 1;
+  int occ = fused_occupancy<T, BS>(dev);
   if (bpc > 0 && bpc < occ) occ = bpc;
   int64_t grid = (int64_t)dev->cu * occ;
   if (n_ph >= 0) {
@@ -822,7 +851,81 @@ int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParam
   }
 }
 
+int validate_tuning(const photon_tuning* t) {
+  if (!t) return PHOTON_OK;
+  if (t->block != 128 && t->block != 256 && t->block != 512) return fail(PHOTON_EINVAL, "tuning.block must be 128, 256 or 512");
+  if (t->chunk < t->block || t->chunk % t->block) return fail(PHOTON_EINVAL, "tuning.chunk must be a positive multiple of block");
+  if (t->blocks_per_cu < 0) return fail(PHOTON_EINVAL, "tuning.blocks_per_cu must be >= 0");
+  return PHOTON_OK;
+}
+
+// Everything a fused step needs, validated.
+struct StepArgs {
+  SegView sv;
+  int64_t n = 0;
+  AtmDev ad;
+  GenParams g;
+  SinkDev sk;
+  int kind = 0;
+  double K = 0.0;
+  uint64_t seed = 0;
+  int32_t precision = 0;
+};
+
+int prep_step(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em, uint64_t seed,
+              int32_t precision, const photon_sink* sink, const photon_tuning* tuning, StepArgs* a) {
+  int rc;
+  if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
+  if ((rc = prep_seg(seg, &a->sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
+  if ((rc = prep_atm(atm, &a->ad))) return rc;
+  if ((rc = prep_emission(em, &a->g))) return rc;
+  if ((rc = prep_precision(precision))) return rc;
+  if ((rc = prep_sink(sink, &a->sk))) return rc;
+  if ((rc = validate_tuning(tuning))) return rc;
+  a->n = seg->n;
+  a->kind = em->kind;
+  a->K = (em->kind == PHOTON_CHERENKOV) ? (2.0 * kPi * kAlpha) * ((1e9 / em->lambda_min_nm) - (1e9 / em->lambda_max_nm))
+                                         : em->yield_per_MeV;
+  a->seed = seed;
+  a->precision = precision;
+  return PHOTON_OK;
+}
+
+int clear_sink(const SinkDev& sk, hipStream_t st) {
+  if (sk.totals) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, sk.totals, PHOTON_N_STATUS);
+  if (sk.kind == PHOTON_SINK_TELESCOPES)
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, sk.hits.count, 1);
+  if (sk.kind == PHOTON_SINK_GRID) {
+    const int cells = sk.nx * sk.ny;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, sk.grid_count, cells);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, sk.grid_weight, cells);
+  }
+  return check_launch();
+}
+
+int enqueue_fused(const StepArgs& a, const uint64_t* offsets, int64_t n_ph, const photon_tuning* tun,
+                  DeviceState* dev, hipStream_t st) {
+  if (a.n == 0 || n_ph == 0) return PHOTON_OK;
+  return a.precision == PHOTON_FP64
+             ? launch_fused<double>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st)
+             : launch_fused<float>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st);
+}
+
+// One whole step: counts + offsets, cleared outputs, fused kernel.
+int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const photon_tuning* tun,
+                 DeviceState* dev, hipStream_t st) {
+  int rc;
+  if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.seed, counts, offsets, st))) return rc;
+  if ((rc = clear_sink(a.sk, st))) return rc;
+  return enqueue_fused(a, offsets, -1, tun, dev, st);
+}
+
 }  // namespace
+
+struct photon_plan_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 // ================================================================= C ABI ==
 extern "C" {
@@ -920,6 +1023,115 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm, c
   return precision == PHOTON_FP64
              ? launch_fused<double>(sv, seg->n, ad, g, seed, offsets, n_photons, tuning, sk, dev, st)
              : launch_fused<float>(sv, seg->n, ad, g, seed, offsets, n_photons, tuning, sk, dev, st);
+}
+
+int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                       uint64_t seed, int32_t precision, uint32_t* counts, uint64_t* offsets,
+                       const photon_sink* sink, const photon_tuning* tuning, photon_plan* out) {
+  if (!out) return fail(PHOTON_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  StepArgs a;
+  int rc;
+  if ((rc = prep_step(seg, atm, em, seed, precision, sink, tuning, &a))) return rc;
+  if (!offsets || !counts) return fail(PHOTON_EINVAL, "counts/offsets are NULL");
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  warm_occupancy(dev);
+  hipStream_t cs;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  photon_plan_s* p = new photon_plan_s;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    hipStreamDestroy(cs);
+    delete p;
+    return fail(PHOTON_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  rc = enqueue_step(a, counts, offsets, tuning, dev, cs);
+  e = hipStreamEndCapture(cs, &p->graph);
+  hipStreamDestroy(cs);
+  if (rc || e != hipSuccess) {
+    if (p->graph) hipGraphDestroy(p->graph);
+    delete p;
+    return rc ? rc : fail(PHOTON_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(p->graph);
+    delete p;
+    return fail(PHOTON_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return PHOTON_OK;
+}
+
+int photon_plan_launch(photon_plan plan, void* stream) {
+  if (!plan || !plan->exec) return fail(PHOTON_EINVAL, "plan is NULL");
+  HIP_TRY(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+  return PHOTON_OK;
+}
+
+int photon_plan_destroy(photon_plan plan) {
+  if (!plan) return PHOTON_OK;
+  if (plan->exec) hipGraphExecDestroy(plan->exec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  delete plan;
+  return PHOTON_OK;
+}
+
+int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                    uint64_t seed, int32_t precision, const uint64_t* offsets, const photon_sink* sink,
+                    const photon_tuning* candidates, int32_t n_candidates, int32_t reps, photon_tuning* best,
+                    float* best_ms, void* stream) {
+  StepArgs a;
+  int rc;
+  if ((rc = prep_step(seg, atm, em, seed, precision, sink, nullptr, &a))) return rc;
+  if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
+  if (!candidates || n_candidates < 1) return fail(PHOTON_EINVAL, "no candidate shapes");
+  if (reps < 1) return fail(PHOTON_EINVAL, "reps must be >= 1");
+  if (!best || !best_ms) return fail(PHOTON_EINVAL, "best/best_ms is NULL");
+  for (int i = 0; i < n_candidates; ++i)
+    if ((rc = validate_tuning(&candidates[i]))) return rc;
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best_t = 0.0f;
+  int best_i = -1;
+  for (int i = 0; i < n_candidates && rc == PHOTON_OK; ++i) {
+    if ((rc = enqueue_fused(a, offsets, -1, &candidates[i], dev, st))) break;
+    float t[64];
+    const int nr = reps < 64 ? reps : 64;
+    for (int r = 0; r < nr; ++r) {
+      hipEventRecord(e0, st);
+      if ((rc = enqueue_fused(a, offsets, -1, &candidates[i], dev, st))) break;
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(PHOTON_EHIP, "hipEventSynchronize failed");
+        break;
+      }
+      hipEventElapsedTime(&t[r], e0, e1);
+    }
+    if (rc) break;
+    for (int x = 1; x < nr; ++x)  // insertion sort for the median
+      for (int y = x; y > 0 && t[y] < t[y - 1]; --y) {
+        const float tmp = t[y];
+        t[y] = t[y - 1];
+        t[y - 1] = tmp;
+      }
+    const float med = t[nr / 2];
+    if (best_i < 0 || med < best_t) {
+      best_t = med;
+      best_i = i;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  *best = candidates[best_i];
+  *best_ms = best_t;
+  return PHOTON_OK;
 }
 
 }  // extern "C"

@@ -93,8 +93,13 @@ def lib():
         L.photon_propagate.argtypes = [P, P, P]
         L.photon_collect.argtypes = [P, P, P, P]
         L.photon_run_fused.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, C.c_int64, P, P, P]
+        L.photon_plan_create.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P, P, P]
+        L.photon_plan_launch.argtypes = [P, P]
+        L.photon_plan_destroy.argtypes = [P]
+        L.photon_autotune.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P, C.c_int32, C.c_int32, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
-                  "photon_run_fused"):
+                  "photon_run_fused", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
+                  "photon_autotune"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -356,3 +361,48 @@ def tuning(block=256, chunk=4096, blocks_per_cu=0) -> Tuning:
     t = Tuning()
     t.block, t.chunk, t.blocks_per_cu = int(block), int(chunk), int(blocks_per_cu)
     return t
+
+
+class Plan:
+    """One whole step (counts, offsets, cleared sink, fused kernel) captured
+    into a HIP graph by the library; replay with launch()."""
+
+    def __init__(self, seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precision, counts, offsets,
+                 sink: Sink, tuning: Tuning | None = None):
+        self._keep = (seg, counts, offsets, sink)      # buffers the graph points at
+        self._seg = seg.struct()
+        self.handle = C.c_void_p()
+        _check(lib().photon_plan_create(C.byref(self._seg), C.byref(atm), C.byref(em), int(seed),
+                                        int(precision), _ptr(counts), _ptr(offsets), C.byref(sink),
+                                        None if tuning is None else C.byref(tuning), C.byref(self.handle)))
+
+    def launch(self):
+        _check(lib().photon_plan_launch(self.handle, _stream()))
+
+    def close(self):
+        if self.handle:
+            torch.cuda.synchronize()
+            _check(lib().photon_plan_destroy(self.handle))
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precision, offsets, sink: Sink,
+             candidates, reps=5):
+    """Fastest fused launch shape among candidates [(block, chunk, blocks_per_cu)]:
+    returns (Tuning, median ms)."""
+    arr = (Tuning * len(candidates))()
+    for i, (b, c, o) in enumerate(candidates):
+        arr[i].block, arr[i].chunk, arr[i].blocks_per_cu = int(b), int(c), int(o)
+    best = Tuning()
+    ms = C.c_float()
+    s = seg.struct()
+    _check(lib().photon_autotune(C.byref(s), C.byref(atm), C.byref(em), int(seed), int(precision),
+                                 _ptr(offsets), C.byref(sink), arr, len(candidates), int(reps), C.byref(best),
+                                 C.byref(ms), _stream()))
+    return best, ms.value
