@@ -20,6 +20,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -68,11 +69,23 @@ struct GenParams {
   double line_nm[PHOTON_MAX_LINES];
 };
 
+// Candidate grid of the telescope test: a landed photon whose arrival
+// direction is within kCapZenith of the vertical can only hit sphere k if its
+// landing point lies within R_k / cos(cap) + |z_k - h_obs| tan(cap) of the
+// sphere centre horizontally (the line's closest approach is at least the
+// horizontal offset at the centre's height times cos(zenith)). Each cell of
+// a coarse grid over those capture disks keeps a bitmask of the spheres whose
+// disk touches it; steeper photons test every sphere.
+constexpr int kCandCells = 12;
+constexpr double kCapCos = 0.5;  // cos(60 deg)
+
 struct SinkDev {
   int32_t kind;
   int32_t n_tel;
   unsigned long long* totals;
   double tel[PHOTON_MAX_TELESCOPES][4];
+  double cand_x0, cand_y0, cand_inv_cell;
+  uint32_t cand_mask[kCandCells * kCandCells];
   photon_hits hits;
   double x_min, y_min, cell;
   int32_t nx, ny;
@@ -323,7 +336,18 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
   if (sk.kind == PHOTON_SINK_TELESCOPES) {
     int k = -1;
     T s_hit = (T)0;
-    if (active && st == PHOTON_LANDED) k = telescope_hit<T>(p, tel, sk.n_tel, s_hit);
+    if (active && st == PHOTON_LANDED) {
+      uint32_t mask;
+      if (-(double)p.uz >= kCapCos) {
+        const double fx = ((double)p.x - sk.cand_x0) * sk.cand_inv_cell;
+        const double fy = ((double)p.y - sk.cand_y0) * sk.cand_inv_cell;
+        const bool in = fx >= 0.0 && fy >= 0.0 && fx < (double)kCandCells && fy < (double)kCandCells;
+        mask = in ? sk.cand_mask[(int)fy * kCandCells + (int)fx] : 0u;
+      } else {
+        mask = sk.n_tel >= 32 ? 0xffffffffu : ((1u << sk.n_tel) - 1u);
+      }
+      k = telescope_hit_masked<T>(p, tel, mask, s_hit);
+    }
     const bool hit = k >= 0;
     const unsigned long long m = __ballot(hit);
     if (m) {
@@ -538,6 +562,21 @@ int prep_atm(const photon_atmosphere* a, AtmDev* d) {
     d->abs_l[i] = a->abs_lambda_nm[i];
     d->abs_k[i] = a->abs_k_per_m[i];
   }
+  for (int i = 0; i < PHOTON_MAX_LAYERS; ++i) {
+    d->invH[i] = 1.0 / d->H[i];
+    d->em_full[i] = (i + 1 < a->n_layers) ? std::expm1(-(a->h_base[i + 1] - a->h_base[i]) / a->scale_height[i]) : 0.0;
+  }
+  d->em_obs = (lo + 1 < a->n_layers) ? std::expm1(-(a->h_base[lo + 1] - a->h_obs) / a->scale_height[lo]) : 0.0;
+  d->abs_uniform = 0;
+  if (a->n_abs >= 2) {
+    const double step = (a->abs_lambda_nm[a->n_abs - 1] - a->abs_lambda_nm[0]) / (a->n_abs - 1);
+    bool uni = step > 0.0;
+    for (int i = 0; i + 1 < a->n_abs && uni; ++i)
+      uni = std::fabs((a->abs_lambda_nm[i + 1] - a->abs_lambda_nm[i]) - step) <= 1e-9 * step;
+    d->abs_uniform = uni ? 1 : 0;
+    d->abs_l0 = a->abs_lambda_nm[0];
+    d->abs_inv_step = uni ? 1.0 / step : 0.0;
+  }
   return PHOTON_OK;
 }
 
@@ -625,7 +664,36 @@ int check_block(const photon_block* b, int32_t precision) {
   return prep_block<float>(b, &v, true);
 }
 
-int prep_sink(const photon_sink* s, SinkDev* d) {
+void build_candidates(const photon_sink* s, double hobs, SinkDev* d) {
+  const double tan_cap = std::sqrt(1.0 - kCapCos * kCapCos) / kCapCos;
+  double reach[PHOTON_MAX_TELESCOPES];
+  double x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300;
+  for (int k = 0; k < s->n_tel; ++k) {
+    reach[k] = s->tel[k][3] / kCapCos + std::fabs(s->tel[k][2] - hobs) * tan_cap;
+    x0 = std::min(x0, s->tel[k][0] - reach[k]);
+    x1 = std::max(x1, s->tel[k][0] + reach[k]);
+    y0 = std::min(y0, s->tel[k][1] - reach[k]);
+    y1 = std::max(y1, s->tel[k][1] + reach[k]);
+  }
+  const double cell = std::max(x1 - x0, y1 - y0) / kCandCells * (1.0 + 1e-9) + 1e-9;
+  d->cand_x0 = x0;
+  d->cand_y0 = y0;
+  d->cand_inv_cell = 1.0 / cell;
+  for (int iy = 0; iy < kCandCells; ++iy)
+    for (int ix = 0; ix < kCandCells; ++ix) {
+      uint32_t m = 0;
+      const double cx0 = x0 + ix * cell, cy0 = y0 + iy * cell;
+      for (int k = 0; k < s->n_tel; ++k) {
+        // distance from the sphere centre to the cell square, with a margin
+        const double dx = std::max(0.0, std::max(cx0 - s->tel[k][0], s->tel[k][0] - (cx0 + cell)));
+        const double dy = std::max(0.0, std::max(cy0 - s->tel[k][1], s->tel[k][1] - (cy0 + cell)));
+        if (dx * dx + dy * dy <= reach[k] * reach[k] * (1.0 + 1e-6) + 1e-6) m |= 1u << k;
+      }
+      d->cand_mask[iy * kCandCells + ix] = m;
+    }
+}
+
+int prep_sink(const photon_sink* s, SinkDev* d, double atm_hobs) {
   if (!s) return fail(PHOTON_EINVAL, "sink is NULL");
   std::memset(d, 0, sizeof *d);
   d->kind = s->kind;
@@ -648,6 +716,7 @@ int prep_sink(const photon_sink* s, SinkDev* d) {
     d->n_tel = s->n_tel;
     std::memcpy(d->tel, s->tel, sizeof d->tel);
     d->hits = h;
+    build_candidates(s, atm_hobs, d);
   } else if (s->kind == PHOTON_SINK_GRID) {
     if (s->nx < 1 || s->ny < 1 || (int64_t)s->nx * s->ny > (1 << 24))
       return fail(PHOTON_EINVAL, "grid shape %d x %d invalid", s->nx, s->ny);
@@ -880,7 +949,7 @@ int prep_step(const photon_segments* seg, const photon_atmosphere* atm, const ph
   if ((rc = prep_atm(atm, &a->ad))) return rc;
   if ((rc = prep_emission(em, &a->g))) return rc;
   if ((rc = prep_precision(precision))) return rc;
-  if ((rc = prep_sink(sink, &a->sk))) return rc;
+  if ((rc = prep_sink(sink, &a->sk, a->ad.hobs))) return rc;
   if ((rc = validate_tuning(tuning))) return rc;
   a->n = seg->n;
   a->kind = em->kind;
@@ -987,7 +1056,7 @@ int photon_collect(const photon_block* in, const photon_atmosphere* atm, const p
   int rc;
   if (!in) return fail(PHOTON_EINVAL, "photon block is NULL");
   if ((rc = prep_atm(atm, &ad))) return rc;
-  if ((rc = prep_sink(sink, &sk))) return rc;
+  if ((rc = prep_sink(sink, &sk, ad.hobs))) return rc;
   if ((rc = prep_precision(in->precision))) return rc;
   if ((rc = check_block(in, in->precision))) return rc;
   DeviceState* dev;
@@ -1009,7 +1078,7 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm, c
   if ((rc = prep_atm(atm, &ad))) return rc;
   if ((rc = prep_emission(em, &g))) return rc;
   if ((rc = prep_precision(precision))) return rc;
-  if ((rc = prep_sink(sink, &sk))) return rc;
+  if ((rc = prep_sink(sink, &sk, ad.hobs))) return rc;
   if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
   if (n_photons < -1) return fail(PHOTON_EINVAL, "n_photons must be >= 0, or -1 (total read on the device)");
   if (tuning && (tuning->block != 128 && tuning->block != 256 && tuning->block != 512))
@@ -1042,21 +1111,21 @@ int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm,
   photon_plan_s* p = new photon_plan_s;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     delete p;
     return fail(PHOTON_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
   }
   rc = enqueue_step(a, counts, offsets, tuning, dev, cs);
   e = hipStreamEndCapture(cs, &p->graph);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (rc || e != hipSuccess) {
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     delete p;
     return rc ? rc : fail(PHOTON_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
   }
   e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
-    hipGraphDestroy(p->graph);
+    (void)hipGraphDestroy(p->graph);
     delete p;
     return fail(PHOTON_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   }
@@ -1072,8 +1141,8 @@ int photon_plan_launch(photon_plan plan, void* stream) {
 
 int photon_plan_destroy(photon_plan plan) {
   if (!plan) return PHOTON_OK;
-  if (plan->exec) hipGraphExecDestroy(plan->exec);
-  if (plan->graph) hipGraphDestroy(plan->graph);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
   delete plan;
   return PHOTON_OK;
 }
@@ -1104,14 +1173,14 @@ int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm, co
     float t[64];
     const int nr = reps < 64 ? reps : 64;
     for (int r = 0; r < nr; ++r) {
-      hipEventRecord(e0, st);
+      (void)hipEventRecord(e0, st);
       if ((rc = enqueue_fused(a, offsets, -1, &candidates[i], dev, st))) break;
-      hipEventRecord(e1, st);
+      (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess) {
         rc = fail(PHOTON_EHIP, "hipEventSynchronize failed");
         break;
       }
-      hipEventElapsedTime(&t[r], e0, e1);
+      (void)hipEventElapsedTime(&t[r], e0, e1);
     }
     if (rc) break;
     for (int x = 1; x < nr; ++x)  // insertion sort for the median
@@ -1126,8 +1195,8 @@ int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm, co
       best_i = i;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   *best = candidates[best_i];
   *best_ms = best_t;

@@ -52,8 +52,9 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 
 // (x + 1/2) 2^-32: exact in double, strictly inside (0,1).
 __device__ __forceinline__ double u01d(uint32_t x) { return (double)x * 0x1p-32 + 0x1p-33; }
-// 24-bit form for the float path: ((x >> 8) + 1/2) 2^-24, exact in float.
-__device__ __forceinline__ float u01f(uint32_t x) { return (float)(x >> 8) * 0x1p-24f + 0x1p-25f; }
+// Float form: the 32-bit word converted with one rounding, so u keeps about
+// 6e-8 relative precision down to 2^-33 (1 - u is taken as u(~x)).
+__device__ __forceinline__ float u01f(uint32_t x) { return __builtin_fmaf((float)x, 0x1p-32f, 0x1p-33f); }
 
 template <typename T>
 __device__ __forceinline__ T u01(uint32_t x);
@@ -76,6 +77,11 @@ struct AtmDev {
   double eta0, hobs, rho_obs, n_obs;
   int32_t l_obs;          // layer of h_obs
   int32_t homog_mask;     // bit i set: layer i has infinite scale height
+  double invH[PHOTON_MAX_LAYERS];
+  double em_full[PHOTON_MAX_LAYERS];  // expm1(-(hb[l+1] - hb[l]) / H[l]): density ratio - 1 across layer l
+  double em_obs;                      // expm1(-(top of the observation layer - hobs) / H[l_obs])
+  int32_t abs_uniform;                // absorption nodes equally spaced
+  double abs_l0, abs_inv_step;
   double abs_l[PHOTON_MAX_ABS];
   double abs_k[PHOTON_MAX_ABS];
 };
@@ -282,8 +288,12 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
   p.y = (T)c.y0 + s * c.dy;
   p.z = (T)c.z0 + s * c.dz;
   p.t = c.t0 + (double)s * c.inv_bc;
-  const T ct = (T)1 - (T)2 * u1;
-  const T st = (T)2 * sqrt(u1 * ((T)1 - u1));
+  // cos = 1 - 2 u1 = -(w - 2^31 + 1/2) 2^-31, and 1 - u1 = u(~w): both taken
+  // from the 32-bit word, so rays near the horizon keep their relative
+  // precision in either arithmetic
+  const int32_t sw = (int32_t)(r.w[1] ^ 0x80000000u);
+  const T ct = -((T)sw + (T)0.5) * (T)0x1p-31;
+  const T st = (T)2 * sqrt(u01<T>(r.w[1]) * u01<T>(~r.w[1]));
   T sp, cp;
   sincos2pi(u2, &sp, &cp);
   p.ux = st * cp;
@@ -314,49 +324,80 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
 // Differences are formed from eps_a expm1(-(b-a)/H) so that thin pieces and
 // nearly vertical rays keep full relative precision.
 // ---------------------------------------------------------------------------
-struct Piece4 {
-  double g0, p, o, t;  // int dh/r, path, optical path, density-weighted path
+// Precision-specific primitives: the float path uses the hardware
+// reciprocal, square root and logarithm (about 1 ulp); the double path uses
+// correctly rounded IEEE operations and the library functions.
+template <typename T>
+struct Fm;
+template <>
+struct Fm<double> {
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+  static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+};
+template <>
+struct Fm<float> {
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+  // log1p(x) = log(u) x / (u - 1) with u = 1 + x rounded (exact u - 1)
+  static __device__ __forceinline__ float log1p_(float x) {
+    const float u = 1.0f + x;
+    return (u == 1.0f) ? x : __logf(u) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
+  }
+  static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+  static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
 };
 
+// Integrals over one layer piece [a, b] (a below b) of dh/r, n dh/r,
+// n^2 dh/r and rho n dh/r, with r = sqrt(n^2 - S^2) and eps = n - 1 falling
+// exponentially with scale height H. rho_a is rho/rho0 at a and
+// em = rho_b/rho_a - 1; ra and rb are r at both ends. C2 = 1 - S^2.
+//   C2 > 0:  int dh/r = (b-a)/C + (H/C) log((C r_b + C^2 + eps_b) / (C r_a + C^2 + eps_a))
+//   C2 < 0:  int dh/r = (H/K) [asin((eps_a - K^2)/(eps_a S)) - asin((eps_b - K^2)/(eps_b S))], K^2 = -C2
+//   C2 = 0:  int dh/r = H (r_b/eps_b - r_a/eps_a)
+//   int n dh/r   = int dh/r + H log((n_a + r_a)/(n_b + r_b))
+//   int n^2 dh/r = int n dh/r + H (r_a - r_b)
+//   int rho n dh/r = H (rho_a - rho_b)(2 + eps_a + eps_b)/(r_a + r_b)
+// The log arguments are written as 1 + (small difference) and the
+// differences come from em, so thin pieces and near-vertical rays keep their
+// relative precision.
 template <typename T>
-__device__ __forceinline__ void piece_integrals(T rho_a, T dh, T H, bool homog, T eta0, T C2, T S,
-                                                T& g0, T& pth, T& opt, T& col) {
+__device__ __forceinline__ void piece_integrals(T rho_a, T em, T dh, T H, bool homog, T eta0, T C2, T Cc, T invC,
+                                                T S, T ra, T rb, T& g0, T& pth, T& opt, T& col) {
+  using F = Fm<T>;
   const T eps_a = eta0 * rho_a;
   const T na = (T)1 + eps_a;
   if (homog) {
-    const T r = sqrt(C2 + eps_a * ((T)2 + eps_a));
-    g0 = dh / r;
+    g0 = dh * F::rcp(ra);
     pth = na * g0;
     opt = na * pth;
     col = rho_a * pth;
     return;
   }
-  const T em = expm1(-dh / H);          // rho_b/rho_a - 1 (<= 0)
   const T drho = rho_a * em;            // rho_b - rho_a
   const T d = eta0 * drho;              // eps_b - eps_a
   const T eps_b = eps_a + d;
   const T nb = (T)1 + eps_b;
-  const T ra = sqrt(C2 + eps_a * ((T)2 + eps_a));
-  const T rb = sqrt(C2 + eps_b * ((T)2 + eps_b));
-  const T rs = ra + rb;
+  const T inv_rs = F::rcp(ra + rb);
   const T two_e = (T)2 + eps_a + eps_b;
-  const T rd = -d * two_e / rs;         // r_a - r_b
+  const T rd = -d * two_e * inv_rs;     // r_a - r_b
   if (C2 > (T)0) {
-    const T Cc = sqrt(C2);
     const T den = Cc * ra + C2 + eps_a;
-    const T delta = d * ((T)1 + Cc * two_e / rs);
-    g0 = dh / Cc + (H / Cc) * log1p(delta / den);
+    const T delta = d * ((T)1 + Cc * two_e * inv_rs);
+    g0 = dh * invC + (H * invC) * F::log1p_(delta * F::rcp(den));
   } else if (C2 < (T)0) {
     const T K2 = -C2;
-    const T Kk = sqrt(K2);
+    const T Kk = F::sqrt_(K2);
     g0 = (H / Kk) * (asin((eps_a - K2) / (eps_a * S)) - asin((eps_b - K2) / (eps_b * S)));
   } else {
     g0 = H * (rb / eps_b - ra / eps_a);
   }
-  const T lg = log1p((-d + rd) / (nb + rb));
+  const T lg = F::log1p_((-d + rd) * F::rcp(nb + rb));
   pth = g0 + H * lg;
   opt = pth + H * rd;
-  col = -H * drho * two_e / rs;
+  col = -H * drho * two_e * inv_rs;
 }
 
 template <typename T>
@@ -365,96 +406,132 @@ __device__ __forceinline__ T abs_coeff(const AtmDev& a, T lambda) {
   const double l = (double)lambda;
   if (l <= a.abs_l[0]) return (T)a.abs_k[0];
   if (l >= a.abs_l[a.n_abs - 1]) return (T)a.abs_k[a.n_abs - 1];
-  int lo = 0, hi = a.n_abs - 1;  // abs_l[lo] <= l < abs_l[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a.abs_l[mid] <= l) lo = mid; else hi = mid;
+  int lo, hi;
+  if (a.abs_uniform) {
+    lo = (int)((l - a.abs_l0) * a.abs_inv_step);
+    lo = lo < 0 ? 0 : (lo > a.n_abs - 2 ? a.n_abs - 2 : lo);
+    // guard against the last bit of the index computation
+    if (l < a.abs_l[lo]) --lo;
+    else if (!(l < a.abs_l[lo + 1])) ++lo;
+    hi = lo + 1;
+  } else {
+    lo = 0;
+    hi = a.n_abs - 1;  // abs_l[lo] <= l < abs_l[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.abs_l[mid] <= l) lo = mid; else hi = mid;
+    }
   }
   const double f = (l - a.abs_l[lo]) / (a.abs_l[hi] - a.abs_l[lo]);
   return (T)(a.abs_k[lo] + f * (a.abs_k[hi] - a.abs_k[lo]));
 }
 
-// Threshold on |C^2| below which the float path evaluates a piece in double
+// Threshold on |C^2| below which the float path evaluates the ray in double
 // (rays within about 13 degrees of the horizontal, where the float closed
 // forms lose digits to cancellation).
 constexpr float kNearHorizonC2 = 0.05f;
 
+// Layer pieces from the emission height ze down to h_obs in precision C.
+// rho_e = rho_bot (1 + em_e) is the density at ze, se/ce the sine/cosine of
+// the zenith angle at emission. Accumulates int dh/r (g0), path and optical
+// path (double) and the density-weighted path (col).
+template <typename C>
+__device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C em_e, C rho_e, C se, C ce,
+                                           C& g0, double& pth, double& opt, C& col, C& ne) {
+  using F = Fm<C>;
+  const C eta0 = (C)a.eta0;
+  const C eps_e = eta0 * rho_e;
+  ne = (C)1 + eps_e;
+  const C S = ne * se;
+  // 1 - S = ce^2/(1 + se) - eps_e se, free of cancellation for S well below 1
+  const C C2 = (ce * ce * F::rcp((C)1 + se) - eps_e * se) * ((C)1 + S);
+  const C Cc = C2 > (C)0 ? F::sqrt_(C2) : (C)0;
+  const C invC = C2 > (C)0 ? F::rcp(Cc) : (C)0;
+  C r_top = ne * ce;  // r at ze: sqrt(ne^2 - S^2) = ne cos
+  g0 = (C)0;
+  col = (C)0;
+  pth = 0.0;
+  opt = 0.0;
+  // the layer index runs wave-uniformly (lanes above their emission layer
+  // skip the iteration), so the layer constants stay in scalar registers
+  for (int l = a.nl - 1; l >= a.l_obs; --l) {
+    if (l > le) continue;
+    const double top = (l == le) ? ze : a.hb[l + 1];
+    const double bot = (l == a.l_obs) ? a.hobs : a.hb[l];
+    const double dh = top - bot;
+    if (!(dh > 0.0)) continue;
+    const C rho_a = (C)((l == a.l_obs) ? a.rho_obs : a.rb[l]);
+    const C em = (l == le) ? em_e : (C)((l == a.l_obs) ? a.em_obs : a.em_full[l]);
+    const C eps_a = eta0 * rho_a;
+    const C ra = F::sqrt_(C2 + eps_a * ((C)2 + eps_a));
+    C q0, q1, q2, q3;
+    piece_integrals<C>(rho_a, em, (C)dh, (C)a.H[l], (a.homog_mask >> l) & 1, eta0, C2, Cc, invC, S, ra, r_top,
+                       q0, q1, q2, q3);
+    g0 += q0;
+    pth += (double)q1;
+    opt += (double)q2;
+    col += q3;
+    r_top = ra;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
+  using F = Fm<T>;
   if (p.status != PHOTON_LANDED) return;
   if (!(p.uz < (T)0)) {
     p.status = PHOTON_UP;
     return;
   }
-  if ((double)p.z < a.hobs) {
+  const double ze = (double)p.z;
+  if (ze < a.hobs) {
     p.status = PHOTON_BELOW;
     return;
   }
-  const T un = sqrt(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz);
-  const T ux = p.ux / un, uy = p.uy / un, ce = -p.uz / un;
-  const T se = sqrt(ux * ux + uy * uy);
-
-  const double ze = (double)p.z;
+  const T inv_un = F::rcp(F::sqrt_(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz));
+  const T ux = p.ux * inv_un, uy = p.uy * inv_un, ce = -p.uz * inv_un;
+  const T se = F::sqrt_(ux * ux + uy * uy);
   const int le = layer_of(a, ze);
-  const double rho_e_d = a.rb[le] * exp(-(ze - a.hb[le]) / a.H[le]);
-  const T rho_e = (T)rho_e_d;
-  const T eta0 = (T)a.eta0;
-  const T eps_e = eta0 * rho_e;
-  const T ne = (T)1 + eps_e;
-  const T S = ne * se;
-  // 1 - S = ce^2/(1 + se) - eps_e se, without cancellation for S well below 1
-  const T one_m_S = ce * ce / ((T)1 + se) - eps_e * se;
-  const T C2 = one_m_S * ((T)1 + S);
-  const bool dbl = (sizeof(T) == 4) && !(fabs((float)C2) > kNearHorizonC2);
-  const double C2d = dbl ? ((double)ce * (double)ce / (1.0 + (double)se) - (double)eps_e * (double)se) *
-                               (1.0 + (double)ne * (double)se)
-                         : 0.0;
+  const double bot = (le == a.l_obs) ? a.hobs : a.hb[le];
+  const double rho_bot = (le == a.l_obs) ? a.rho_obs : a.rb[le];
+  const bool homog_e = (a.homog_mask >> le) & 1;
 
-  T g0 = (T)0, col = (T)0;
-  double pth = 0.0, opt = 0.0;
-  double top = ze;
-  T rho_top = rho_e;
-  for (int l = le; l >= a.l_obs; --l) {
-    const double bot = (l == a.l_obs) ? a.hobs : a.hb[l];
-    const double dh = top - bot;
-    // density at the bottom of the piece (known exactly at layer bases)
-    const double rho_bot = (l == a.l_obs) ? a.rho_obs : a.rb[l];
-    if (dh > 0.0) {
-      const bool homog = (a.homog_mask >> l) & 1;
-      if (sizeof(T) == 8 || dbl) {
-        double q0, q1, q2, q3;
-        const double Sd = (double)ne * (double)se;
-        piece_integrals<double>(rho_bot, dh, a.H[l], homog, a.eta0, sizeof(T) == 8 ? (double)C2 : C2d, Sd,
-                                q0, q1, q2, q3);
-        g0 += (T)q0;
-        pth += q1;
-        opt += q2;
-        col += (T)q3;
-      } else {
-        T q0, q1, q2, q3;
-        piece_integrals<T>((T)rho_bot, (T)dh, (T)a.H[l], homog, eta0, C2, S, q0, q1, q2, q3);
-        g0 += q0;
-        pth += (double)q1;
-        opt += (double)q2;
-        col += q3;
-      }
+  T g0, col, ne;
+  double pth, opt;
+  bool done = false;
+  if (sizeof(T) == 4) {
+    // near the horizon the float closed forms lose digits: use double there
+    const T em_e = homog_e ? (T)0 : F::expm1_((T)(-(ze - bot) * a.invH[le]));
+    const T rho_e = (T)rho_bot * ((T)1 + em_e);
+    const T eps_e = (T)a.eta0 * rho_e;
+    const T S = ((T)1 + eps_e) * se;
+    const T C2 = (ce * ce * F::rcp((T)1 + se) - eps_e * se) * ((T)1 + S);
+    if (C2 > (T)kNearHorizonC2) {
+      ray_pieces<T>(a, le, ze, em_e, rho_e, se, ce, g0, pth, opt, col, ne);
+      done = true;
     }
-    top = bot;
-    rho_top = (T)rho_bot;
   }
-  (void)rho_top;
+  if (!done) {
+    double g0d, cold, ned;
+    const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * a.invH[le]);
+    const double rho_e = rho_bot * (1.0 + em_e);
+    ray_pieces<double>(a, le, ze, em_e, rho_e, (double)se, (double)ce, g0d, pth, opt, cold, ned);
+    g0 = (T)g0d;
+    col = (T)cold;
+    ne = (T)ned;
+  }
   p.x = p.x + ux * ne * g0;
   p.y = p.y + uy * ne * g0;
   p.z = (T)a.hobs;
-  p.t = p.t + opt / kC;
+  p.t = p.t + opt * (1.0 / kC);
   p.path = pth;
   const T tau = abs_coeff<T>(a, p.lambda) * col;
-  p.w = exp(-tau);
-  const T q = ne / (T)a.n_obs;
+  p.w = F::exp_(-tau);
+  const T q = ne * (T)(1.0 / a.n_obs);
   p.ux = ux * q;
   p.uy = uy * q;
   const T sl = se * q;
-  p.uz = -sqrt(((T)1 - sl) * ((T)1 + sl));
+  p.uz = -F::sqrt_(((T)1 - sl) * ((T)1 + sl));
   p.status = PHOTON_LANDED;
 }
 
@@ -466,6 +543,31 @@ __device__ __forceinline__ int telescope_hit(const Photon<T>& p, const double (*
   int best = -1;
   T best_s = (T)INFINITY;
   for (int k = 0; k < n_tel; ++k) {
+    const T ox = p.x - (T)tel[k][0], oy = p.y - (T)tel[k][1], oz = p.z - (T)tel[k][2];
+    const T R = (T)tel[k][3];
+    const T b = p.ux * ox + p.uy * oy + p.uz * oz;
+    const T cc = (ox * ox + oy * oy + oz * oz) - R * R;
+    const T disc = b * b - cc;
+    if (disc < (T)0) continue;
+    const T s = -b - sqrt(disc);
+    if (s < best_s) {
+      best_s = s;
+      best = k;
+    }
+  }
+  s_hit = best_s;
+  return best;
+}
+
+// Same test restricted to the spheres whose bits are set in mask.
+template <typename T>
+__device__ __forceinline__ int telescope_hit_masked(const Photon<T>& p, const double (*tel)[4], uint32_t mask,
+                                                    T& s_hit) {
+  int best = -1;
+  T best_s = (T)INFINITY;
+  while (mask) {
+    const int k = __builtin_ctz(mask);
+    mask &= mask - 1u;
     const T ox = p.x - (T)tel[k][0], oy = p.y - (T)tel[k][1], oz = p.z - (T)tel[k][2];
     const T R = (T)tel[k][3];
     const T b = p.ux * ox + p.uy * oy + p.uz * oz;

@@ -1,0 +1,115 @@
+"""GPU tests of the runtime around the fused kernel: HIP-graph plans and the
+launch-shape autotuner."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2309_15861_amd import photon as ph
+from paper_2309_15861_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def hit_keys(hits):
+    h = hits.numpy()
+    return np.sort((h["segment"].astype(np.int64) << 32) | h["j"].astype(np.int64))
+
+
+@pytest.fixture(scope="module")
+def batched():
+    a = W.default_atmosphere(absorption=True)
+    seg = W.batched_showers(seed=4, n_showers=12, n_min=100, n_max=3000)
+    d = ph.DeviceSegments(seg)
+    atm = ph.atmosphere(a)
+    em = ph.emission_cherenkov()
+    counts, offsets = ph.count(d, atm, em, 4)
+    torch.cuda.synchronize()
+    return a, seg, d, atm, em, counts, offsets, int(offsets[-1].item())
+
+
+@pytest.mark.parametrize("prec", [ph.FP32, ph.FP64])
+def test_plan_replays_match_direct_run(batched, prec):
+    a, seg, d, atm, em, counts, offsets, total = batched
+    tel = W.telescopes_16(radius=20.0)
+    # direct run
+    hits0 = ph.HitBuffer(total)
+    tot0 = ph.status_totals()
+    ph.run_fused(d, atm, em, 4, prec, offsets, total, ph.sink_telescopes(tel, hits0, tot0))
+    torch.cuda.synchronize()
+    ref_keys, ref_tot = hit_keys(hits0), tot0.cpu().numpy()
+    assert ref_tot.sum() == total and len(ref_keys) > 0
+    # captured step: counts, offsets, cleared outputs and the fused kernel
+    c2 = torch.full_like(counts, -1)
+    o2 = torch.full_like(offsets, -1)
+    hits = ph.HitBuffer(total)
+    tot = ph.status_totals()
+    plan = ph.Plan(d, atm, em, 4, prec, c2, o2, ph.sink_telescopes(tel, hits, tot))
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for r in range(4):
+        # eager work and a dirty output between replays
+        scratch.add_(1.0)
+        hits.t["count"].fill_(12345)
+        tot.fill_(7)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(c2, counts), r
+        assert torch.equal(o2, offsets), r
+        assert np.array_equal(tot.cpu().numpy(), ref_tot), r
+        assert np.array_equal(hit_keys(hits), ref_keys), r
+    plan.close()
+
+
+def test_plan_with_grid_sink(batched):
+    a, seg, d, atm, em, counts, offsets, total = batched
+    g = W.grid_64()
+    n = g["nx"] * g["ny"]
+    gc0 = torch.zeros(n, dtype=torch.int32, device="cuda")
+    gw0 = torch.zeros(n, dtype=torch.int64, device="cuda")
+    ph.run_fused(d, atm, em, 4, ph.FP32, offsets, total,
+                 ph.sink_grid(g["x_min"], g["y_min"], g["cell"], g["nx"], g["ny"], gc0, gw0))
+    gc = torch.full((n,), 99, dtype=torch.int32, device="cuda")
+    gw = torch.full((n,), 99, dtype=torch.int64, device="cuda")
+    c2 = torch.empty_like(counts)
+    o2 = torch.empty_like(offsets)
+    plan = ph.Plan(d, atm, em, 4, ph.FP32, c2, o2,
+                   ph.sink_grid(g["x_min"], g["y_min"], g["cell"], g["nx"], g["ny"], gc, gw))
+    for _ in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(gc, gc0) and torch.equal(gw, gw0)
+    assert int(gc0.sum().item()) > 0
+    plan.close()
+
+
+def test_autotune_picks_a_candidate_with_identical_results(batched):
+    a, seg, d, atm, em, counts, offsets, total = batched
+    tel = W.telescopes_16(radius=20.0)
+    hits = ph.HitBuffer(total)
+    sink = ph.sink_telescopes(tel, hits)
+    cands = [(128, 1024, 0), (256, 4096, 0), (256, 16384, 0), (512, 8192, 1)]
+    best, ms = ph.autotune(d, atm, em, 4, ph.FP32, offsets, sink, cands, reps=3)
+    assert (best.block, best.chunk, best.blocks_per_cu) in cands
+    assert ms > 0
+    keys = []
+    for tun in (None, best):
+        hits.clear()
+        ph.run_fused(d, atm, em, 4, ph.FP32, offsets, total, sink, tun)
+        torch.cuda.synchronize()
+        keys.append(hit_keys(hits))
+    assert np.array_equal(keys[0], keys[1])
+
+
+def test_device_total_matches_explicit_total(batched):
+    """n_photons = -1 (total read on the device) equals passing the total,
+    and a too-large explicit count marks the extra slots INVALID."""
+    a, seg, d, atm, em, counts, offsets, total = batched
+    res = []
+    for n_ph in (total, -1, total + 1000):
+        tot = ph.status_totals()
+        ph.run_fused(d, atm, em, 4, ph.FP32, offsets, n_ph, ph.sink_status(tot))
+        torch.cuda.synchronize()
+        res.append(tot.cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+    extra = res[2] - res[0]
+    assert extra[ph.INVALID] == 1000 and extra.sum() == 1000
