@@ -34,6 +34,9 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9          # VALU lane-slots/s: CUs x SIMDs x la
 # selection and hit test (~30).
 SLOTS_PER_PHOTON = {"fp32": 300.0, "fp64": 750.0}
 PMC_FILE = os.path.join(ROOT, "profiles", "fused_shower_fp32_traffic.json")
+# launch shapes the autotuner chooses from: (block, chunk, blocks per CU; 0 = as many as fit)
+TUNING_CANDIDATES = [(256, 4096, 0), (256, 8192, 0), (256, 16384, 0), (512, 8192, 0), (512, 16384, 0),
+                     (128, 4096, 0), (256, 8192, 2)]
 
 
 def source_hash() -> str:
@@ -85,6 +88,49 @@ def cpu_baseline(seg, atm_dict, tel, seed, max_threads=16):
                        f"counts + generation + quadrature propagation + telescope test; {dt:.1f} s")
 
 
+def batched_showers(args):
+    """64 showers (segment counts log-uniform 1e3..1e6, zenith 0..60 deg) in
+    one graph-captured step, FP32 bulk, telescope sink per shower core."""
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+
+    seg = W.batched_showers(seed=4)
+    a = W.default_atmosphere(absorption=True)
+    d = ph.DeviceSegments(seg)
+    atm = ph.atmosphere(a)
+    em = ph.emission_cherenkov(300.0, 600.0)
+    counts = torch.empty(d.n, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(d.n + 1, dtype=torch.int64, device="cuda")
+    ph.gen_cherenkov(d, atm, 300.0, 600.0, 4, ph.FP64, counts, offsets)
+    torch.cuda.synchronize()
+    total = int(offsets[-1].item())
+    hits = ph.HitBuffer(1 << 22)       # hits beyond the capacity are still counted in the totals
+    totals = ph.status_totals()
+    sink = ph.sink_telescopes(W.telescopes_16(), hits, totals)
+    best, _ = ph.autotune(d, atm, em, 4, ph.FP32, offsets, sink, TUNING_CANDIDATES, reps=2)
+    plan = ph.Plan(d, atm, em, 4, ph.FP32, counts, offsets, sink, best)
+    plan.launch()
+    torch.cuda.synchronize()
+    steps = max(2, args.steps // 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tot = totals.cpu().numpy()
+    assert int(tot[:7].sum()) == total
+    plan.close()
+    return dict(workload="64 showers, segments log-uniform 1e3..1e6 per shower, zenith 0..60 deg",
+                segments=d.n, photons=total, hits=int(tot[ph.HIT]), ms_per_step=ms,
+                photons_per_s=total / (ms * 1e-3),
+                precision="fp32 bulk, fp64 time/path", steps=steps,
+                tuning=[best.block, best.chunk, best.blocks_per_cu])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +140,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 form (profiling runs)")
+    ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time 64 showers of 1e3..1e6 segments in one graph-captured step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -134,46 +182,47 @@ def main():
     sink = ph.sink_telescopes(tel, hits, totals)
     stream = torch.cuda.current_stream()
 
-    def step(prec, ev=None):
-        ph.gen_cherenkov(d, atm, 300.0, 600.0, seed, ph.FP64, counts, offsets)
-        hits.t["count"].zero_()
-        totals.zero_()
-        if ev is not None:
-            ev[0].record(stream)
-        ph.run_fused(d, atm, em, seed, prec, offsets, -1, sink)
-        if ev is not None:
-            ev[1].record(stream)
-
     results = {}
     forms = (("fp32", ph.FP32),) if args.fp32_only else (("fp32", ph.FP32), ("fp64", ph.FP64))
     for name, prec in forms:
+        # launch shape from the autotuner, then the whole step captured in a graph
+        best, _ = ph.autotune(d, atm, em, seed, prec, offsets, sink, TUNING_CANDIDATES, reps=3)
+        plan = ph.Plan(d, atm, em, seed, prec, counts, offsets, sink, best)
         for _ in range(args.warmup):
-            step(prec)
+            plan.launch()
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
         start.record(stream)
-        for k in range(args.steps):
-            step(prec, evs[k])
+        for _ in range(args.steps):
+            plan.launch()
         end.record(stream)
         torch.cuda.synchronize()
         ms = start.elapsed_time(end)
-        fused_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
         tot = totals.cpu().numpy()
-        assert int(tot.sum()) == total, (tot, total)
+        assert int(tot[:7].sum()) == total, (tot, total)
         assert hits.count() <= hits.capacity
+        nhits = hits.count()
+        plan.close()
+        # the fused kernel alone, same shape, bracketed by events on its stream
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            ph.run_fused(d, atm, em, seed, prec, offsets, -1, sink, best)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        fused_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
         results[name] = dict(ms_per_step=ms / args.steps, fused_ms=fused_ms,
-                             photons_per_s=total * args.steps / (ms * 1e-3),
-                             hits=hits.count(), status_totals=[int(x) for x in tot])
+                             photons_per_s=total * args.steps / (ms * 1e-3), hits=nhits,
+                             status_totals=[int(x) for x in tot],
+                             tuning=[best.block, best.chunk, best.blocks_per_cu])
 
     r32 = results["fp32"]
     achieved = SLOTS_PER_PHOTON["fp32"] * total / (r32["fused_ms"] * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=achieved / PEAK_SLOTS, traffic=traffic_per_launch(),
-                    kernel="k_fused<float,256>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
-                    fused_ms=r32["fused_ms"])
+                    kernel=f"k_fused<float,{r32['tuning'][0]}>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
+                    fused_ms=r32["fused_ms"], tuning=r32["tuning"])
     r64 = results.get("fp64", r32)
     out = {
         "metric": "photons propagated/s on 1 MI355X (FP64 vs FP32-split, batched) + % roofline",
@@ -188,6 +237,8 @@ def main():
                  "frac": SLOTS_PER_PHOTON["fp64"] * total / (r64["fused_ms"] * 1e-3) / PEAK_SLOTS},
         "hits": r32["hits"],
     }
+    if args.batched:
+        out["batched"] = batched_showers(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seg, a, tel, seed)
     print(json.dumps(out))

@@ -70,11 +70,17 @@ extern "C" {
 #define PHOTON_OFFGRID 4        /* landed outside the ground grid           */
 #define PHOTON_INVALID 6        /* slot without a valid segment             */
 #define PHOTON_N_STATUS 8
+/* Slot 7 of the status totals is not a photon status: it counts rays near
+   the horizon that a fused FP32 run evaluated in float because its deferral
+   queue was full (2^24 rays per device, shared evenly among the kernel's
+   blocks); slots 0..6 partition the photons. */
+#define PHOTON_HORIZON_FLOAT 7
 
 /* ---- sink kinds ---------------------------------------------------------- */
 #define PHOTON_SINK_STATUS 0    /* per-status photon totals only            */
 #define PHOTON_SINK_TELESCOPES 1
 #define PHOTON_SINK_GRID 2
+#define PHOTON_SINK_PLANE 3     /* every photon written at its slot         */
 
 #define PHOTON_MAX_LAYERS 8
 #define PHOTON_MAX_ABS 40
@@ -135,9 +141,10 @@ typedef struct {
 /* The common photon block (section 1: photons of both generators are
    written to one memory block and processed downstream), structure of
    arrays with `capacity` slots (device pointers). Slot q holds photon j of
-   segment `segment[q]`, with q = offsets[segment] + j. Position, direction,
-   wavelength and weight are double (PHOTON_FP64) or float (PHOTON_FP32);
-   time and path length are double in both. After generation: emission point,
+   segment `segment[q]`, with q = offsets[segment] + j. Horizontal position,
+   direction, wavelength and weight are double (PHOTON_FP64) or float
+   (PHOTON_FP32); the height z, the time and the path length are double in
+   both. After generation: emission point,
    time and direction, path 0, weight 1, status LANDED (or INVALID). After
    propagation: landing point (z = h_obs), arrival time, arrival direction,
    geometric path length, transmission weight exp(-tau) and status. */
@@ -145,8 +152,8 @@ typedef struct {
   int64_t capacity;
   int64_t n_photons;                  /* slots in use = offsets[n]          */
   int32_t precision;
-  void *x, *y, *z, *ux, *uy, *uz, *wavelength_nm, *weight;
-  double *t_ns, *path_m;
+  void *x, *y, *ux, *uy, *uz, *wavelength_nm, *weight;
+  double *z, *t_ns, *path_m;
   uint32_t *segment, *j;
   int32_t *status;
 } photon_block;
@@ -171,7 +178,11 @@ typedef struct {
    sphere along the ray is recorded with time t + n_obs * s / c (s the
    signed distance from the landing point). GRID: nx * ny cells of size
    `cell` from (x_min, y_min), half-open; grid_count[iy*nx+ix] counts landed
-   photons, grid_weight the sum of their weights in units of 2^-32. */
+   photons, grid_weight the sum of their weights in units of 2^-32. PLANE:
+   every photon's final state is written at its slot q = offsets[s] + j of
+   `plane` (arrays of the run's precision, capacity >= number of photons;
+   slots beyond the capacity are not written), as photon_propagate leaves a
+   photon block. */
 typedef struct {
   int32_t kind;
   unsigned long long *status_totals;
@@ -182,6 +193,7 @@ typedef struct {
   int32_t nx, ny;
   uint32_t *grid_count;
   unsigned long long *grid_weight;
+  const photon_block *plane;
 } photon_sink;
 
 /* Launch shape of the fused kernel: threads per block (64..1024, multiple
@@ -252,8 +264,11 @@ int photon_collect(const photon_block* in, const photon_atmosphere* atm, const p
    number of photon slots to process: offsets[n], or -1 to have the kernel
    read offsets[n] on the device (no host round trip; slots beyond
    offsets[n] count as INVALID). Results equal those of gen + propagate +
-   collect. One call at a time per device: calls share the device's work
-   queue counter. */
+   collect. In the FP32 form, rays within about 6 degrees of the horizon are
+   handed to a second, double kernel that regenerates them from their random
+   numbers (a per-device queue of 2^24 rays, allocated on the first such
+   call; see PHOTON_HORIZON_FLOAT). One call at a time per device: calls
+   share the device's work queue counters. */
 int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
                      const photon_emission* em, uint64_t seed, int32_t precision,
                      const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,

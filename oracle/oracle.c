@@ -227,8 +227,9 @@ double or_mean_fluor(const or_segments* s, int64_t i, double yield_per_MeV) {
 /* Poisson(mu) count by sequential inverse CDF on the COUNT stream.
    mu is split into m equal chunks of at most 128 (exp(-mu) would underflow
    for large mu); each chunk draws the smallest k with F(k) >= u, F the
-   Poisson(mu/m) CDF summed term by term p_k = p_{k-1} * mc / k. The sum of
-   m independent Poisson(mu/m) variates is Poisson(mu).
+   Poisson(mu/m) CDF summed term by term p_k = (p_{k-1} * mc) * (1/k), with
+   1/k rounded to double. The sum of m independent Poisson(mu/m) variates is
+   Poisson(mu).
    *margin receives min over chunks of |u - F(k)| at the accepted k and at
    k-1 (how close the decision was). */
 #define OR_POISSON_CHUNK 128.0
@@ -251,7 +252,7 @@ uint32_t or_poisson(double mu, uint64_t seed, uint32_t idx, uint32_t shower, dou
     double F = p, Fprev = 0.0;
     while (u[0] > F && k < OR_POISSON_KMAX) {
       k += 1;
-      p = (p * mc) / (double)k;
+      p = (p * mc) * (1.0 / (double)k);
       Fprev = F;
       F = F + p;
     }

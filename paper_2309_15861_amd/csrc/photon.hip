@@ -55,8 +55,8 @@ constexpr int kWaveSize = 64;
 // ------------------------------------------------------------------ views --
 template <typename T>
 struct BlockView {
-  T *x, *y, *z, *ux, *uy, *uz, *lam, *w;
-  double *t, *path;
+  T *x, *y, *ux, *uy, *uz, *lam, *w;
+  double *z, *t, *path;
   uint32_t *seg, *j;
   int32_t* status;
 };
@@ -91,6 +91,12 @@ struct SinkDev {
   int32_t nx, ny;
   uint32_t* grid_count;
   unsigned long long* grid_weight;
+  // PLANE: every photon written at its slot (arrays of the run's precision)
+  int64_t plane_capacity;
+  void *px, *py, *pux, *puy, *puz, *plam, *pw;
+  double *pz, *pt, *ppath;
+  uint32_t *pseg, *pj;
+  int32_t* pstatus;
 };
 
 // ------------------------------------------------------ wave/block helpers --
@@ -143,22 +149,65 @@ __device__ __forceinline__ int64_t lane_upper_index(const uint64_t* off, int64_t
 }
 
 // ------------------------------------------------------------- count+scan --
+// Counts: lane i computes the mean of segment i and its number of Poisson
+// chunks; each wave then spreads the (segment, chunk) draws of its 64
+// segments over its lanes, so that lanes do not idle while one segment with
+// a large mean draws chunk after chunk. Chunk results are summed per segment
+// with LDS atomics (integer sums: the order does not matter).
 template <int KIND>
 __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, AtmDev atm, double K, uint32_t k0,
                                                       uint32_t k1, uint32_t* __restrict__ counts,
                                                       uint64_t* __restrict__ offsets) {
   __shared__ unsigned long long part[kScanBlock / kWaveSize];
-  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-  uint32_t c = 0;
+  __shared__ double rk[kPoissonKmax + 1];
+  __shared__ double s_mc[kScanBlock], s_p0[kScanBlock];
+  __shared__ uint32_t s_start[kScanBlock], s_cnt[kScanBlock], s_idx[kScanBlock], s_sh[kScanBlock];
+  const int tid = threadIdx.x;
+  for (int k = tid; k <= (int)kPoissonKmax; k += kScanBlock) rk[k] = 1.0 / (double)k;
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + tid;
+  uint32_t m = 0;
+  double mc = 0.0, p0 = 0.0;
+  uint32_t idx = 0, sh = 0;
   if (i < n) {
+#pragma clang fp contract(off)
     const double mu = (KIND == PHOTON_CHERENKOV) ? mean_cherenkov(seg, i, atm, K) : mean_fluor(seg, i, K);
-    c = poisson_count(mu, k0, k1, seg_idx(seg, i), seg_shower(seg, i));
-    counts[i] = c;
+    m = poisson_chunks(mu);
+    if (m) {
+      mc = mu / (double)m;
+      p0 = exp(-mc);
+    }
+    idx = seg_idx(seg, i);
+    sh = seg_shower(seg, i);
   }
-  const unsigned long long s = wave_sum((unsigned long long)c);
-  if (lane_id() == 0) part[threadIdx.x / kWaveSize] = s;
+  const unsigned long long incl = wave_incl_scan((unsigned long long)m);
+  const uint32_t total = (uint32_t)__shfl(incl, kWaveSize - 1, kWaveSize);
+  s_start[tid] = (uint32_t)(incl - m);
+  s_mc[tid] = mc;
+  s_p0[tid] = p0;
+  s_cnt[tid] = 0u;
+  s_idx[tid] = idx;
+  s_sh[tid] = sh;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  const int wb = (tid / kWaveSize) * kWaveSize;
+  for (uint32_t t = (uint32_t)lane_id(); t < total; t += kWaveSize) {
+    // the segment lane L of item t: the last L with start[L] <= t
+    int lo = 0, hi = kWaveSize;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_start[wb + mid] <= t) lo = mid; else hi = mid;
+    }
+    const int L = wb + lo;
+    const uint32_t c = t - s_start[L];
+    const double u = u01d(philox(c, s_idx[L], s_sh[L], kDomCount, k0, k1).w[0]);
+    atomicAdd(&s_cnt[L], poisson_chunk(u, s_mc[L], s_p0[L], rk));
+  }
+  __syncthreads();
+  const uint32_t cnt = s_cnt[tid];
+  if (i < n) counts[i] = cnt;
+  const unsigned long long s = wave_sum((unsigned long long)cnt);
+  if (lane_id() == 0) part[tid / kWaveSize] = s;
+  __syncthreads();
+  if (tid == 0) {
     unsigned long long t = 0;
     for (int w = 0; w < kScanBlock / kWaveSize; ++w) t += part[w];
     const int64_t pos = min((int64_t)(blockIdx.x + 1) * kScanBlock, n);
@@ -286,6 +335,7 @@ __global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, i
   p.t = b.t[q];
   p.path = b.path[q];
   p.status = b.status[q];
+  p.uzd = (double)p.uz;
   propagate<T>(atm, p);
   b.x[q] = p.x;
   b.y[q] = p.y;
@@ -331,9 +381,25 @@ __device__ void flush_status(StatusCounter& sc, unsigned long long* totals) {
 // per wave reserves the slots, lanes write at their rank among the hits.
 template <typename T>
 __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], double n_obs, Photon<T>& p,
-                                           uint32_t seg_row, uint32_t j, bool active) {
+                                           uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q = 0) {
   int st = active ? p.status : -1;
-  if (sk.kind == PHOTON_SINK_TELESCOPES) {
+  if (sk.kind == PHOTON_SINK_PLANE) {
+    if (active && slot_q < (uint64_t)sk.plane_capacity) {
+      ((T*)sk.px)[slot_q] = p.x;
+      ((T*)sk.py)[slot_q] = p.y;
+      sk.pz[slot_q] = p.z;
+      ((T*)sk.pux)[slot_q] = p.ux;
+      ((T*)sk.puy)[slot_q] = p.uy;
+      ((T*)sk.puz)[slot_q] = p.uz;
+      ((T*)sk.plam)[slot_q] = p.lambda;
+      ((T*)sk.pw)[slot_q] = p.w;
+      sk.pt[slot_q] = p.t;
+      sk.ppath[slot_q] = p.path;
+      sk.pseg[slot_q] = seg_row;
+      sk.pj[slot_q] = j;
+      sk.pstatus[slot_q] = p.status;
+    }
+  } else if (sk.kind == PHOTON_SINK_TELESCOPES) {
     int k = -1;
     T s_hit = (T)0;
     if (active && st == PHOTON_LANDED) {
@@ -364,7 +430,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
           sk.hits.telescope[slot] = k;
           sk.hits.x[slot] = (double)p.x + (double)s_hit * (double)p.ux;
           sk.hits.y[slot] = (double)p.y + (double)s_hit * (double)p.uy;
-          sk.hits.z[slot] = (double)p.z + (double)s_hit * (double)p.uz;
+          sk.hits.z[slot] = p.z + (double)s_hit * (double)p.uz;
           sk.hits.t_ns[slot] = p.t + n_obs * (double)s_hit / kC;
           sk.hits.ux[slot] = (float)p.ux;
           sk.hits.uy[slot] = (float)p.uy;
@@ -416,7 +482,7 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
     s = b.seg[q];
     j = b.j[q];
   }
-  const int st = sink_photon<T>(sk, s_tel, n_obs, p, s, j, active);
+  const int st = sink_photon<T>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q);
   if (active) sc.add(st);
   if (sk.totals) flush_status(sc, sk.totals);
 }
@@ -424,10 +490,31 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
 // ------------------------------------------------------------ fused kernel --
 constexpr int kWindow = 256;  // segments staged in LDS per work chunk
 
+// Everything the fused kernels take, as one kernel argument.
+struct FusedArgs {
+  SegView seg;
+  int64_t n_seg;
+  AtmDev atm;
+  GenParams g;
+  uint32_t k0, k1;
+  const uint64_t* offsets;
+  int64_t n_ph;                       // < 0: offsets[n_seg]
+  int64_t chunk;
+  SinkDev sk;
+  unsigned long long* cursor;         // work queue position
+  unsigned long long* defer_counts;   // per block: near-horizon rays handed to the double pass
+  uint2* defer_q;                     // their (segment row, j), defer_cap entries per block
+  int64_t defer_cap;
+};
+static_assert(sizeof(FusedArgs) <= 4000, "fused kernel arguments must stay below 4 KB");
+
+// Persistent kernel: blocks take chunks of the photon index space from an
+// atomic queue; per chunk the segments it covers are found by two wave
+// searches and their constants staged in LDS; every photon is generated,
+// propagated and collected in registers. In the float form, rays near the
+// horizon are appended to a queue for the double pass instead.
 template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_fused(SegView seg, int64_t n_seg, AtmDev atm, GenParams g, uint32_t k0,
-                                              uint32_t k1, const uint64_t* __restrict__ offsets, int64_t n_ph,
-                                              int64_t chunk, SinkDev sk, unsigned long long* cursor) {
+__global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
   __shared__ SegConst<T> s_seg[kWindow];
   __shared__ uint64_t s_off[kWindow + 1];
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
@@ -435,28 +522,32 @@ __global__ __launch_bounds__(BS) void k_fused(SegView seg, int64_t n_seg, AtmDev
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
+  __shared__ unsigned int s_dcount;
+  constexpr bool kDefer = sizeof(T) == 4;
 
   const int tid = threadIdx.x;
+  if (tid == 0) s_dcount = 0u;
   if (tid < PHOTON_MAX_LINES) {
-    s_thr[tid] = g.thr[tid];
-    s_lines[tid] = (T)g.line_nm[tid];
+    s_thr[tid] = A.g.thr[tid];
+    s_lines[tid] = (T)A.g.line_nm[tid];
   }
-  for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&sk.tel[0][0])[k];
-  const bool cher = g.kind == PHOTON_CHERENKOV;
+  for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+  const bool cher = A.g.kind == PHOTON_CHERENKOV;
+  const int64_t n_seg = A.n_seg;
+  const uint64_t* __restrict__ offsets = A.offsets;
   StatusCounter sc;
   sc.clear();
-  // n_ph < 0: the photon total is offsets[n_seg], read here on the device.
   // Slots at or beyond offsets[n_seg] belong to no segment: counted INVALID.
   const uint64_t total = offsets[n_seg];
-  if (n_ph < 0) n_ph = (int64_t)total;
+  const int64_t n_ph = A.n_ph < 0 ? (int64_t)total : A.n_ph;
   const uint64_t lim = min((uint64_t)n_ph, total);
 
   for (;;) {
-    if (tid == 0) s_c0 = atomicAdd(cursor, (unsigned long long)chunk);
+    if (tid == 0) s_c0 = atomicAdd(A.cursor, (unsigned long long)A.chunk);
     __syncthreads();
     const uint64_t c0 = s_c0;
     if (c0 >= (uint64_t)n_ph) break;
-    const uint64_t c1 = min(c0 + (uint64_t)chunk, (uint64_t)n_ph);
+    const uint64_t c1 = min(c0 + (uint64_t)A.chunk, (uint64_t)n_ph);
     const uint64_t v1 = min(c1, lim);  // valid slots of this chunk: [c0, v1)
     for (uint64_t q = max(c0, v1) + tid; q < c1; q += BS) sc.add(PHOTON_INVALID);
     if (c0 >= v1) {
@@ -465,12 +556,12 @@ __global__ __launch_bounds__(BS) void k_fused(SegView seg, int64_t n_seg, AtmDev
     }
     const int wave = tid / kWaveSize;
     if (wave == 0) {
-      const int64_t s = wave_upper_index(offsets, n_seg, c0);
-      if (lane_id() == 0) s_lo = s;
+      const int64_t sl = wave_upper_index(offsets, n_seg, c0);
+      if (lane_id() == 0) s_lo = sl;
     }
     if (wave == (BS > kWaveSize ? 1 : 0)) {
-      const int64_t s = wave_upper_index(offsets, n_seg, v1 - 1);
-      if (lane_id() == 0) s_hi = s;
+      const int64_t sh = wave_upper_index(offsets, n_seg, v1 - 1);
+      if (lane_id() == 0) s_hi = sh;
     }
     __syncthreads();
     // both ends lie in [0, n_seg) for offsets from the count call; the
@@ -480,7 +571,7 @@ __global__ __launch_bounds__(BS) void k_fused(SegView seg, int64_t n_seg, AtmDev
     const bool win = W >= 1 && W <= kWindow;
     if (win) {
       for (int t = tid; t < W; t += BS) {
-        seg_const<T>(seg, lo + t, atm, cher, s_seg[t]);
+        seg_const<T>(A.seg, lo + t, A.atm, cher, s_seg[t]);
         s_off[t] = offsets[lo + t];
       }
       if (tid == 0) s_off[W] = offsets[lo + W];
@@ -501,19 +592,98 @@ __global__ __launch_bounds__(BS) void k_fused(SegView seg, int64_t n_seg, AtmDev
         s = lo + a;
       } else {
         s = lane_upper_index(offsets, n_seg, q);
-        seg_const<T>(seg, s, atm, cher, c);
+        seg_const<T>(A.seg, s, A.atm, cher, c);
         off_s = offsets[s];
       }
       const uint32_t j = (uint32_t)(q - off_s);
       Photon<T> p;
-      generate<T>(c, j, g, k0, k1, s_thr, s_lines, p);
-      propagate<T>(atm, p);
-      const int st = sink_photon<T>(sk, s_tel, atm.n_obs, p, (uint32_t)s, j, true);
-      sc.add(st);
+      generate<T>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
+      propagate<T, kDefer>(A.atm, p);
+      bool forced = false;
+      if (kDefer) {
+        const bool defer = p.status == kDeferred;
+        const unsigned long long m = __ballot(defer);
+        if (m) {
+          // the block's own queue: one LDS atomic per wave
+          const int leader = __ffsll((long long)m) - 1;
+          unsigned int base = 0;
+          if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
+          base = __shfl(base, leader, kWaveSize);
+          if (defer) {
+            const uint64_t slot = (uint64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+            if (slot < (uint64_t)A.defer_cap) {
+              A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
+            } else {
+              // queue full: this ray is evaluated in float after all
+              p.status = PHOTON_LANDED;
+              propagate<T, false, true>(A.atm, p);
+              forced = true;
+            }
+          }
+        }
+      }
+      if (!kDefer || p.status != kDeferred) {
+        const int st = sink_photon<T>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q);
+        sc.add(st);
+        if (forced) sc.add(PHOTON_HORIZON_FLOAT);
+      }
     }
     __syncthreads();
   }
-  if (sk.totals) flush_status(sc, sk.totals);
+  if (kDefer && tid == 0) {
+    const uint64_t nd = s_dcount;
+    A.defer_counts[blockIdx.x] = nd < (uint64_t)A.defer_cap ? nd : (uint64_t)A.defer_cap;
+  }
+  if (A.sk.totals) flush_status(sc, A.sk.totals);
+}
+
+// Double pass over the near-horizon rays queued by the float kernel: each is
+// regenerated in double from its counter-based random numbers and carried
+// through propagation and collection in double.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
+  __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
+  __shared__ double s_lines[PHOTON_MAX_LINES];
+  __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  const int tid = threadIdx.x;
+  if (tid < PHOTON_MAX_LINES) {
+    s_thr[tid] = A.g.thr[tid];
+    s_lines[tid] = A.g.line_nm[tid];
+  }
+  for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+  __syncthreads();
+  const bool cher = A.g.kind == PHOTON_CHERENKOV;
+  StatusCounter sc;
+  sc.clear();
+  // block b finishes the queue of the float kernel's block b
+  const unsigned long long cnt = A.defer_counts[blockIdx.x];
+  const uint64_t n = cnt < (unsigned long long)A.defer_cap ? cnt : (uint64_t)A.defer_cap;
+  const uint2* q = A.defer_q + (uint64_t)blockIdx.x * (uint64_t)A.defer_cap;
+  for (uint64_t i = tid; i < n; i += BS) {
+    const uint2 e = q[i];
+    const int64_t s = e.x < (uint32_t)A.n_seg ? (int64_t)e.x : A.n_seg - 1;
+    SegConst<double> c;
+    seg_const<double>(A.seg, s, A.atm, cher, c);
+    Photon<double> p;
+    generate<double>(c, e.y, A.g, A.k0, A.k1, s_thr, s_lines, p);
+    propagate<double>(A.atm, p);
+    // collected in the run's precision (float)
+    Photon<float> pf;
+    pf.x = (float)p.x;
+    pf.y = (float)p.y;
+    pf.ux = (float)p.ux;
+    pf.uy = (float)p.uy;
+    pf.uz = (float)p.uz;
+    pf.lambda = (float)p.lambda;
+    pf.w = (float)p.w;
+    pf.z = p.z;
+    pf.t = p.t;
+    pf.path = p.path;
+    pf.status = p.status;
+    const int st = sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y);
+    sc.add(st);
+  }
+  if (A.sk.totals) flush_status(sc, A.sk.totals);
 }
 
 // ------------------------------------------------------------ host helpers --
@@ -650,8 +820,8 @@ int prep_block(const photon_block* b, BlockView<T>* v, bool need_cap) {
     for (int k = 0; k < 13; ++k)
       if (!req[k]) return fail(PHOTON_EINVAL, "photon block array %d is NULL", k);
   }
-  *v = BlockView<T>{(T*)b->x, (T*)b->y, (T*)b->z, (T*)b->ux, (T*)b->uy, (T*)b->uz, (T*)b->wavelength_nm,
-                    (T*)b->weight, b->t_ns, b->path_m, b->segment, b->j, b->status};
+  *v = BlockView<T>{(T*)b->x, (T*)b->y, (T*)b->ux, (T*)b->uy, (T*)b->uz, (T*)b->wavelength_nm, (T*)b->weight,
+                    b->z, b->t_ns, b->path_m, b->segment, b->j, b->status};
   return PHOTON_OK;
 }
 
@@ -693,7 +863,7 @@ void build_candidates(const photon_sink* s, double hobs, SinkDev* d) {
     }
 }
 
-int prep_sink(const photon_sink* s, SinkDev* d, double atm_hobs) {
+int prep_sink(const photon_sink* s, SinkDev* d, double atm_hobs, int32_t precision) {
   if (!s) return fail(PHOTON_EINVAL, "sink is NULL");
   std::memset(d, 0, sizeof *d);
   d->kind = s->kind;
@@ -730,6 +900,31 @@ int prep_sink(const photon_sink* s, SinkDev* d, double atm_hobs) {
     d->ny = s->ny;
     d->grid_count = s->grid_count;
     d->grid_weight = s->grid_weight;
+  } else if (s->kind == PHOTON_SINK_PLANE) {
+    const photon_block* b = s->plane;
+    if (!b) return fail(PHOTON_EINVAL, "plane sink without a photon block");
+    if (b->precision != precision) return fail(PHOTON_EINVAL, "plane block precision differs from the run's");
+    if (b->capacity < 0) return fail(PHOTON_EINVAL, "plane capacity < 0");
+    if (b->capacity > 0) {
+      const void* req[] = {b->x, b->y, b->z, b->ux, b->uy, b->uz, b->wavelength_nm, b->weight, b->t_ns, b->path_m,
+                           b->segment, b->j, b->status};
+      for (int k = 0; k < 13; ++k)
+        if (!req[k]) return fail(PHOTON_EINVAL, "plane array %d is NULL", k);
+    }
+    d->plane_capacity = b->capacity;
+    d->px = b->x;
+    d->py = b->y;
+    d->pz = b->z;
+    d->pux = b->ux;
+    d->puy = b->uy;
+    d->puz = b->uz;
+    d->plam = b->wavelength_nm;
+    d->pw = b->weight;
+    d->pt = b->t_ns;
+    d->ppath = b->path_m;
+    d->pseg = b->segment;
+    d->pj = b->j;
+    d->pstatus = b->status;
   } else if (s->kind != PHOTON_SINK_STATUS) {
     return fail(PHOTON_EINVAL, "unknown sink kind %d", s->kind);
   }
@@ -737,11 +932,17 @@ int prep_sink(const photon_sink* s, SinkDev* d, double atm_hobs) {
 }
 
 // ---------------------------------------------------------------- devices --
+constexpr int64_t kDeferCap = 1 << 24;  // near-horizon rays queued per fused FP32 call
+constexpr int kWorkWords = 8192;         // u64 words of the per-device work area
+constexpr int kDeferCounts = 64;         // offset of the per-block deferred counts
+constexpr int kMaxFusedGrid = kWorkWords - kDeferCounts;
+
 struct DeviceState {
   bool checked = false;
   bool ok = false;
   int cu = 0;
-  unsigned long long* work = nullptr;  // [0] = fused work cursor
+  unsigned long long* work = nullptr;  // [0] = fused work cursor, [kDeferCounts..] per-block deferred counts
+  uint2* defer_q = nullptr;            // deferred (segment row, j), kDeferCap entries
   int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fused blocks per CU by [precision][block 128/256/512]
 };
 std::mutex g_mu;
@@ -759,12 +960,13 @@ int current_device(DeviceState** out) {
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(PHOTON_ENODEV, "hipGetDeviceProperties failed");
     d.ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
     d.cu = prop.multiProcessorCount;
-    if (d.ok && hipMalloc(&d.work, 4096) != hipSuccess) {
+    if (d.ok && hipMalloc(&d.work, sizeof(unsigned long long) * kWorkWords) != hipSuccess) {
       d.ok = false;
       d.work = nullptr;
       return fail(PHOTON_EHIP, "work area allocation failed");
     }
-    if (d.ok && hipMemset(d.work, 0, 4096) != hipSuccess) return fail(PHOTON_EHIP, "work area clear failed");
+    if (d.ok && hipMemset(d.work, 0, sizeof(unsigned long long) * kWorkWords) != hipSuccess)
+      return fail(PHOTON_EHIP, "work area clear failed");
   }
   if (!d.ok) return fail(PHOTON_ENODEV, "current device is not gfx950");
   *out = &d;
@@ -885,6 +1087,18 @@ void warm_occupancy(DeviceState* dev) {
   fused_occupancy<double, 512>(dev);
 }
 
+// The deferral queue of the float form, allocated on first use (not inside
+// a stream capture: plan creation allocates it before capturing).
+int ensure_defer_queue(DeviceState* dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev->defer_q) return PHOTON_OK;
+  if (hipMalloc(&dev->defer_q, sizeof(uint2) * kDeferCap) != hipSuccess) {
+    dev->defer_q = nullptr;
+    return fail(PHOTON_EHIP, "deferral queue allocation failed");
+  }
+  return PHOTON_OK;
+}
+
 template <typename T, int BS>
 int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                     const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
@@ -896,10 +1110,30 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
     const int64_t chunks = ceil_div(n_ph, chunk);
     if (grid > chunks) grid = chunks;
   }
-  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  if (grid > kMaxFusedGrid) grid = kMaxFusedGrid;
+  const bool defer = sizeof(T) == 4;
+  if (defer) {
+    const int rc = ensure_defer_queue(dev);
+    if (rc) return rc;
+  }
+  FusedArgs A;
+  A.seg = sv;
+  A.n_seg = n;
+  A.atm = atm;
+  A.g = g;
+  A.k0 = (uint32_t)(seed & 0xffffffffu);
+  A.k1 = (uint32_t)(seed >> 32);
+  A.offsets = offsets;
+  A.n_ph = n_ph;
+  A.chunk = chunk;
+  A.sk = sk;
+  A.cursor = dev->work;
+  A.defer_counts = dev->work + kDeferCounts;
+  A.defer_q = dev->defer_q;
+  A.defer_cap = defer ? kDeferCap / grid : 0;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
-  hipLaunchKernelGGL((k_fused<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, sv, n, atm, g, k0, k1, offsets, n_ph,
-                     chunk, sk, dev->work);
+  hipLaunchKernelGGL((k_fused<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, A);
+  if (defer) hipLaunchKernelGGL((k_fused_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A);
   return check_launch();
 }
 
@@ -949,7 +1183,7 @@ int prep_step(const photon_segments* seg, const photon_atmosphere* atm, const ph
   if ((rc = prep_atm(atm, &a->ad))) return rc;
   if ((rc = prep_emission(em, &a->g))) return rc;
   if ((rc = prep_precision(precision))) return rc;
-  if ((rc = prep_sink(sink, &a->sk, a->ad.hobs))) return rc;
+  if ((rc = prep_sink(sink, &a->sk, a->ad.hobs, precision))) return rc;
   if ((rc = validate_tuning(tuning))) return rc;
   a->n = seg->n;
   a->kind = em->kind;
@@ -1056,8 +1290,8 @@ int photon_collect(const photon_block* in, const photon_atmosphere* atm, const p
   int rc;
   if (!in) return fail(PHOTON_EINVAL, "photon block is NULL");
   if ((rc = prep_atm(atm, &ad))) return rc;
-  if ((rc = prep_sink(sink, &sk, ad.hobs))) return rc;
   if ((rc = prep_precision(in->precision))) return rc;
+  if ((rc = prep_sink(sink, &sk, ad.hobs, in->precision))) return rc;
   if ((rc = check_block(in, in->precision))) return rc;
   DeviceState* dev;
   if ((rc = current_device(&dev))) return rc;
@@ -1068,30 +1302,17 @@ int photon_collect(const photon_block* in, const photon_atmosphere* atm, const p
 int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em, uint64_t seed,
                      int32_t precision, const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
                      const photon_tuning* tuning, void* stream) {
-  SegView sv;
-  AtmDev ad;
-  GenParams g;
-  SinkDev sk;
+  StepArgs a;
   int rc;
-  if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
-  if ((rc = prep_seg(seg, &sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
-  if ((rc = prep_atm(atm, &ad))) return rc;
-  if ((rc = prep_emission(em, &g))) return rc;
-  if ((rc = prep_precision(precision))) return rc;
-  if ((rc = prep_sink(sink, &sk, ad.hobs))) return rc;
+  if ((rc = prep_step(seg, atm, em, seed, precision, sink, tuning, &a))) return rc;
   if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
   if (n_photons < -1) return fail(PHOTON_EINVAL, "n_photons must be >= 0, or -1 (total read on the device)");
-  if (tuning && (tuning->block != 128 && tuning->block != 256 && tuning->block != 512))
-    return fail(PHOTON_EINVAL, "tuning.block must be 128, 256 or 512");
-  if (tuning && (tuning->chunk < tuning->block || tuning->chunk % tuning->block))
-    return fail(PHOTON_EINVAL, "tuning.chunk must be a positive multiple of block");
+  if (sink->kind == PHOTON_SINK_PLANE && n_photons > sink->plane->capacity)
+    return fail(PHOTON_ECAPACITY, "n_photons = %lld exceeds the plane capacity %lld", (long long)n_photons,
+                (long long)sink->plane->capacity);
   DeviceState* dev;
   if ((rc = current_device(&dev))) return rc;
-  if (n_photons == 0 || seg->n == 0) return PHOTON_OK;
-  hipStream_t st = (hipStream_t)stream;
-  return precision == PHOTON_FP64
-             ? launch_fused<double>(sv, seg->n, ad, g, seed, offsets, n_photons, tuning, sk, dev, st)
-             : launch_fused<float>(sv, seg->n, ad, g, seed, offsets, n_photons, tuning, sk, dev, st);
+  return enqueue_fused(a, offsets, n_photons, tuning, dev, (hipStream_t)stream);
 }
 
 int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
@@ -1106,6 +1327,7 @@ int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm,
   DeviceState* dev;
   if ((rc = current_device(&dev))) return rc;
   warm_occupancy(dev);
+  if (precision == PHOTON_FP32 && (rc = ensure_defer_queue(dev))) return rc;
   hipStream_t cs;
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   photon_plan_s* p = new photon_plan_s;

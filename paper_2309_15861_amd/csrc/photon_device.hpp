@@ -155,29 +155,52 @@ __device__ __forceinline__ double mean_fluor(const SegView& s, int64_t i, double
   return (Y * e) * s.len[i];
 }
 
-// Poisson(mu): m = ceil(mu/128) chunks of mean mc = mu/m, each the smallest
-// k with F(k) >= u, F summed term by term p_k = p_{k-1} mc / k.
-__device__ __forceinline__ uint32_t poisson_count(double mu, uint32_t k0, uint32_t k1, uint32_t idx,
-                                                  uint32_t shower) {
+// Chunking of a mean for the Poisson draw: m chunks of mean mc (m = 0 when
+// the segment emits nothing).
+__device__ __forceinline__ uint32_t poisson_chunks(double mu) {
 #pragma clang fp contract(off)
   if (!(mu > 0.0) || !(mu <= kMaxMean)) return 0u;
-  const uint32_t m = (mu <= kPoissonChunk) ? 1u : (uint32_t)ceil(mu / kPoissonChunk);
-  const double mc = mu / (double)m;
-  const double p0 = exp(-mc);
-  uint32_t total = 0;
-  for (uint32_t c = 0; c < m; ++c) {
-    const double u = u01d(philox(c, idx, shower, kDomCount, k0, k1).w[0]);
-    uint32_t k = 0;
-    double p = p0, F = p0;
-    while (u > F && k < kPoissonKmax) {
-      k += 1;
-      p = (p * mc) / (double)k;
-      F = F + p;
-    }
-    total += k;
-  }
-  return total;
+  return (mu <= kPoissonChunk) ? 1u : (uint32_t)ceil(mu / kPoissonChunk);
 }
+
+// One chunk: the smallest k with F(k) >= u for Poisson(mc), p0 = exp(-mc).
+__device__ __forceinline__ uint32_t poisson_chunk(double u, double mc, double p0, const double* rk) {
+#pragma clang fp contract(off)
+  uint32_t k = 0;
+  double p = p0, F = p0;
+  while (u > F && k < kPoissonKmax) {
+    k += 1;
+    p = (p * mc) * rk[k];
+    F = F + p;
+  }
+  return k;
+}
+
+// Precision-specific primitives: the float path uses the hardware
+// reciprocal, square root and logarithm (about 1 ulp); the double path uses
+// correctly rounded IEEE operations and the library functions.
+template <typename T>
+struct Fm;
+template <>
+struct Fm<double> {
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+  static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+};
+template <>
+struct Fm<float> {
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+  // log1p(x) = log(u) x / (u - 1) with u = 1 + x rounded (exact u - 1)
+  static __device__ __forceinline__ float log1p_(float x) {
+    const float u = 1.0f + x;
+    return (u == 1.0f) ? x : __logf(u) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
+  }
+  static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+  static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
+};
 
 // ---------------------------------------------------------------------------
 // Per-segment constants of photon generation, computed once per segment
@@ -237,15 +260,29 @@ __device__ __forceinline__ void seg_const(const SegView& s, int64_t i, const Atm
   }
 }
 
+// One photon in registers. The height z, the time and the path length are
+// double in both precisions: along slant paths of hundreds of km a float
+// height (2 mm ulp at 30 km) would cost about 0.1 ns of arrival time.
+// uzd is the vertical direction component in double: exact for isotropic
+// photons (from the 32-bit word), the float value otherwise. The float path
+// takes the ray's C^2 and its long-path terms from it.
 template <typename T>
 struct Photon {
-  T x, y, z, ux, uy, uz, lambda, w;
-  double t, path;
+  T x, y, ux, uy, uz, lambda, w;
+  double z, t, path, uzd;
   int32_t status;
 };
 
 __device__ __forceinline__ void sincos2pi(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
 __device__ __forceinline__ void sincos2pi(float u, float* s, float* c) { sincospif(2.0f * u, s, c); }
+// Cone azimuth: in float the hardware sine/cosine, whose argument is in
+// revolutions (u in (0,1)); its error enters the direction scaled by the
+// small sin(theta_c).
+__device__ __forceinline__ void cone_sincos(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
+__device__ __forceinline__ void cone_sincos(float u, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(u);
+  *c = __builtin_amdgcn_cosf(u);
+}
 
 // Photon j of a Cherenkov segment (section 1.2, Fig. 1): cone vector
 // p = (cos c sin Tc, sin c sin Tc, -cos Tc) at azimuth c = 2 pi u1
@@ -259,16 +296,17 @@ __device__ __forceinline__ void gen_cherenkov(const SegConst<T>& c, uint32_t j, 
   const T s = u0 * c.len;
   p.x = (T)c.x0 + s * c.dx;
   p.y = (T)c.y0 + s * c.dy;
-  p.z = (T)c.z0 + s * c.dz;
+  p.z = c.z0 + (double)(s * c.dz);
   p.t = c.t0 + (double)s * c.inv_bc;
   T sp, cp;
-  sincos2pi(u1, &sp, &cp);
+  cone_sincos(u1, &sp, &cp);
   const T px = cp * c.sin_c, py = sp * c.sin_c, pz = -c.cos_c;
   const T ap2 = (T)2 * (c.ax * px + c.ay * py + c.az * pz);
   p.ux = ap2 * c.ax - px;
   p.uy = ap2 * c.ay - py;
   p.uz = ap2 * c.az - pz;
-  p.lambda = (T)1 / (inv_l1 - u2 * inv_dl);
+  p.uzd = (double)p.uz;
+  p.lambda = Fm<T>::rcp(inv_l1 - u2 * inv_dl);
   p.w = (T)1;
   p.path = 0.0;
   p.status = PHOTON_LANDED;
@@ -286,19 +324,21 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
   const T s = u0 * c.len;
   p.x = (T)c.x0 + s * c.dx;
   p.y = (T)c.y0 + s * c.dy;
-  p.z = (T)c.z0 + s * c.dz;
+  p.z = c.z0 + (double)(s * c.dz);
   p.t = c.t0 + (double)s * c.inv_bc;
   // cos = 1 - 2 u1 = -(w - 2^31 + 1/2) 2^-31, and 1 - u1 = u(~w): both taken
   // from the 32-bit word, so rays near the horizon keep their relative
   // precision in either arithmetic
   const int32_t sw = (int32_t)(r.w[1] ^ 0x80000000u);
-  const T ct = -((T)sw + (T)0.5) * (T)0x1p-31;
+  const double ctd = -((double)sw + 0.5) * 0x1p-31;
+  const T ct = (T)ctd;
   const T st = (T)2 * sqrt(u01<T>(r.w[1]) * u01<T>(~r.w[1]));
   T sp, cp;
   sincos2pi(u2, &sp, &cp);
   p.ux = st * cp;
   p.uy = st * sp;
   p.uz = ct;
+  p.uzd = ctd;
   int k = 0;
   const uint64_t w3 = r.w[3];
   while (k < n_lines - 1 && !(w3 < thr[k])) ++k;
@@ -324,32 +364,6 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
 // Differences are formed from eps_a expm1(-(b-a)/H) so that thin pieces and
 // nearly vertical rays keep full relative precision.
 // ---------------------------------------------------------------------------
-// Precision-specific primitives: the float path uses the hardware
-// reciprocal, square root and logarithm (about 1 ulp); the double path uses
-// correctly rounded IEEE operations and the library functions.
-template <typename T>
-struct Fm;
-template <>
-struct Fm<double> {
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-  static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
-  static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
-  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
-};
-template <>
-struct Fm<float> {
-  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-  // log1p(x) = log(u) x / (u - 1) with u = 1 + x rounded (exact u - 1)
-  static __device__ __forceinline__ float log1p_(float x) {
-    const float u = 1.0f + x;
-    return (u == 1.0f) ? x : __logf(u) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
-  }
-  static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
-  static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
-};
-
 // Integrals over one layer piece [a, b] (a below b) of dh/r, n dh/r,
 // n^2 dh/r and rho n dh/r, with r = sqrt(n^2 - S^2) and eps = n - 1 falling
 // exponentially with scale height H. rho_a is rho/rho0 at a and
@@ -362,18 +376,26 @@ struct Fm<float> {
 //   int rho n dh/r = H (rho_a - rho_b)(2 + eps_a + eps_b)/(r_a + r_b)
 // The log arguments are written as 1 + (small difference) and the
 // differences come from em, so thin pieces and near-vertical rays keep their
-// relative precision.
+// relative precision. The dominant term of int dh/r, (b-a)/C (or (b-a)/r in a
+// homogeneous layer), is left to the caller, which adds it in double; the
+// piece returns the remainder g0c and the path increments lgH = int n dh/r -
+// int dh/r and rdH = int n^2 dh/r - int n dh/r, all small.
+template <typename T>
+struct PieceOut {
+  T g0c, lgH, rdH, col;
+};
+
 template <typename T>
 __device__ __forceinline__ void piece_integrals(T rho_a, T em, T dh, T H, bool homog, T eta0, T C2, T Cc, T invC,
-                                                T S, T ra, T rb, T& g0, T& pth, T& opt, T& col) {
+                                                T S, T ra, T rb, PieceOut<T>& o) {
   using F = Fm<T>;
   const T eps_a = eta0 * rho_a;
-  const T na = (T)1 + eps_a;
   if (homog) {
-    g0 = dh * F::rcp(ra);
-    pth = na * g0;
-    opt = na * pth;
-    col = rho_a * pth;
+    const T g = dh * F::rcp(ra);
+    o.g0c = (T)0;
+    o.lgH = eps_a * g;
+    o.rdH = eps_a * ((T)1 + eps_a) * g;
+    o.col = rho_a * ((T)1 + eps_a) * g;
     return;
   }
   const T drho = rho_a * em;            // rho_b - rho_a
@@ -386,18 +408,17 @@ __device__ __forceinline__ void piece_integrals(T rho_a, T em, T dh, T H, bool h
   if (C2 > (T)0) {
     const T den = Cc * ra + C2 + eps_a;
     const T delta = d * ((T)1 + Cc * two_e * inv_rs);
-    g0 = dh * invC + (H * invC) * F::log1p_(delta * F::rcp(den));
+    o.g0c = (H * invC) * F::log1p_(delta * F::rcp(den));
   } else if (C2 < (T)0) {
     const T K2 = -C2;
     const T Kk = F::sqrt_(K2);
-    g0 = (H / Kk) * (asin((eps_a - K2) / (eps_a * S)) - asin((eps_b - K2) / (eps_b * S)));
+    o.g0c = (H / Kk) * (asin((eps_a - K2) / (eps_a * S)) - asin((eps_b - K2) / (eps_b * S)));
   } else {
-    g0 = H * (rb / eps_b - ra / eps_a);
+    o.g0c = H * (rb / eps_b - ra / eps_a);
   }
-  const T lg = F::log1p_((-d + rd) * F::rcp(nb + rb));
-  pth = g0 + H * lg;
-  opt = pth + H * rd;
-  col = -H * drho * two_e * inv_rs;
+  o.lgH = H * F::log1p_((-d + rd) * F::rcp(nb + rb));
+  o.rdH = H * rd;
+  o.col = -H * drho * two_e * inv_rs;
 }
 
 template <typename T>
@@ -426,29 +447,56 @@ __device__ __forceinline__ T abs_coeff(const AtmDev& a, T lambda) {
   return (T)(a.abs_k[lo] + f * (a.abs_k[hi] - a.abs_k[lo]));
 }
 
-// Threshold on |C^2| below which the float path evaluates the ray in double
-// (rays within about 13 degrees of the horizontal, where the float closed
-// forms lose digits to cancellation).
-constexpr float kNearHorizonC2 = 0.05f;
+// Double square root and reciprocal square root for the float path: a
+// float seed refined by Newton steps in double (relative error ~1e-15), at a
+// fraction of the cost of the correctly rounded double routines.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double r = (double)__builtin_amdgcn_rsqf((float)x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r;
+}
+__device__ __forceinline__ double sqrt_refined(double x) {
+  if (!(x > 0.0)) return 0.0;
+  const double r = rsqrt_refined(x);
+  const double s = x * r;
+  return s + 0.5 * r * (x - s * s);
+}
+
+// Rays with C^2 = 1 - S^2 below this (within about 6 degrees of the
+// horizontal) are not evaluated in float: the float closed forms and the
+// float direction lose digits there. In the unfused path they are evaluated
+// in double in place; the fused path hands them to a double pass.
+constexpr float kNearHorizonC2 = 0.01f;
+// Internal status of a photon left to the double pass (never reported).
+constexpr int kDeferred = 7;
 
 // Layer pieces from the emission height ze down to h_obs in precision C.
 // rho_e = rho_bot (1 + em_e) is the density at ze, se/ce the sine/cosine of
-// the zenith angle at emission. Accumulates int dh/r (g0), path and optical
-// path (double) and the density-weighted path (col).
+// the zenith angle at emission. Accumulates in double int dh/r (g0), the path
+// and the optical path, and in C the density-weighted path (col).
+// ced/sed: cosine and sine of the emission zenith angle in double; the float
+// form takes C^2 and the dominant 1/C from them.
 template <typename C>
-__device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C em_e, C rho_e, C se, C ce,
-                                           C& g0, double& pth, double& opt, C& col, C& ne) {
+__device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C em_e, C rho_e, double sed,
+                                           double ced, double& g0, double& pth, double& opt, C& col, C& ne) {
   using F = Fm<C>;
   const C eta0 = (C)a.eta0;
   const C eps_e = eta0 * rho_e;
   ne = (C)1 + eps_e;
+  const C se = (C)sed;
   const C S = ne * se;
   // 1 - S = ce^2/(1 + se) - eps_e se, free of cancellation for S well below 1
-  const C C2 = (ce * ce * F::rcp((C)1 + se) - eps_e * se) * ((C)1 + S);
+  const double epsd = (double)eps_e;
+  const double C2d = (ced * ced / (1.0 + sed) - epsd * sed) * (1.0 + (1.0 + epsd) * sed);
+  const C C2 = (C)C2d;
   const C Cc = C2 > (C)0 ? F::sqrt_(C2) : (C)0;
   const C invC = C2 > (C)0 ? F::rcp(Cc) : (C)0;
+  // 1/C in double for the dominant (b - a)/C terms of long slant paths
+  const double invCd = C2 > (C)0 ? (sizeof(C) == 8 ? (double)invC : rsqrt_refined(C2d)) : 0.0;
+  const C ce = (C)ced;
   C r_top = ne * ce;  // r at ze: sqrt(ne^2 - S^2) = ne cos
-  g0 = (C)0;
+  g0 = 0.0;
   col = (C)0;
   pth = 0.0;
   opt = 0.0;
@@ -464,18 +512,22 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C
     const C em = (l == le) ? em_e : (C)((l == a.l_obs) ? a.em_obs : a.em_full[l]);
     const C eps_a = eta0 * rho_a;
     const C ra = F::sqrt_(C2 + eps_a * ((C)2 + eps_a));
-    C q0, q1, q2, q3;
-    piece_integrals<C>(rho_a, em, (C)dh, (C)a.H[l], (a.homog_mask >> l) & 1, eta0, C2, Cc, invC, S, ra, r_top,
-                       q0, q1, q2, q3);
-    g0 += q0;
-    pth += (double)q1;
-    opt += (double)q2;
-    col += q3;
+    const bool homog = (a.homog_mask >> l) & 1;
+    PieceOut<C> o;
+    piece_integrals<C>(rho_a, em, (C)dh, (C)a.H[l], homog, eta0, C2, Cc, invC, S, ra, r_top, o);
+    const double main = homog ? dh / (double)ra : (C2 > (C)0 ? dh * invCd : 0.0);
+    const double gp = main + (double)o.g0c;
+    g0 += gp;
+    pth += gp + (double)o.lgH;
+    opt += gp + (double)o.lgH + (double)o.rdH;
+    col += o.col;
     r_top = ra;
   }
 }
 
-template <typename T>
+// DEFER (float only): a near-horizon ray is only marked kDeferred.
+// FORCE_FLOAT (float only): every ray is evaluated in float.
+template <typename T, bool DEFER = false, bool FORCE_FLOAT = false>
 __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
   using F = Fm<T>;
   if (p.status != PHOTON_LANDED) return;
@@ -483,21 +535,26 @@ __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
     p.status = PHOTON_UP;
     return;
   }
-  const double ze = (double)p.z;
+  const double ze = p.z;
   if (ze < a.hobs) {
     p.status = PHOTON_BELOW;
     return;
   }
   const T inv_un = F::rcp(F::sqrt_(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz));
-  const T ux = p.ux * inv_un, uy = p.uy * inv_un, ce = -p.uz * inv_un;
-  const T se = F::sqrt_(ux * ux + uy * uy);
+  const T ux = p.ux * inv_un, uy = p.uy * inv_un;
+  // zenith cosine and sine in double from the double vertical component (the
+  // float form's directions are unit to rounding; rescaling the exact
+  // component by a float norm would only add error)
+  const double ced = sizeof(T) == 8 ? -p.uzd * (double)inv_un : -p.uzd;
+  const double sed = sizeof(T) == 8 ? sqrt((1.0 - ced) * (1.0 + ced)) : sqrt_refined((1.0 - ced) * (1.0 + ced));
+  const T ce = (T)ced, se = (T)sed;
   const int le = layer_of(a, ze);
   const double bot = (le == a.l_obs) ? a.hobs : a.hb[le];
   const double rho_bot = (le == a.l_obs) ? a.rho_obs : a.rb[le];
   const bool homog_e = (a.homog_mask >> le) & 1;
 
-  T g0, col, ne;
-  double pth, opt;
+  T col, ne, em_out;
+  double g0, pth, opt;
   bool done = false;
   if (sizeof(T) == 4) {
     // near the horizon the float closed forms lose digits: use double there
@@ -506,32 +563,41 @@ __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
     const T eps_e = (T)a.eta0 * rho_e;
     const T S = ((T)1 + eps_e) * se;
     const T C2 = (ce * ce * F::rcp((T)1 + se) - eps_e * se) * ((T)1 + S);
-    if (C2 > (T)kNearHorizonC2) {
-      ray_pieces<T>(a, le, ze, em_e, rho_e, se, ce, g0, pth, opt, col, ne);
+    if (FORCE_FLOAT || C2 > (T)kNearHorizonC2) {
+      ray_pieces<T>(a, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
+      em_out = em_e;
       done = true;
+    } else if (DEFER) {
+      p.status = kDeferred;
+      return;
     }
   }
   if (!done) {
-    double g0d, cold, ned;
+    double cold, ned;
     const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * a.invH[le]);
     const double rho_e = rho_bot * (1.0 + em_e);
-    ray_pieces<double>(a, le, ze, em_e, rho_e, (double)se, (double)ce, g0d, pth, opt, cold, ned);
-    g0 = (T)g0d;
+    ray_pieces<double>(a, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, cold, ned);
     col = (T)cold;
     ne = (T)ned;
+    em_out = (T)em_e;
   }
-  p.x = p.x + ux * ne * g0;
-  p.y = p.y + uy * ne * g0;
-  p.z = (T)a.hobs;
+  const double disp = (double)ne * g0;
+  p.x = (T)((double)p.x + (double)ux * disp);
+  p.y = (T)((double)p.y + (double)uy * disp);
+  p.z = a.hobs;
   p.t = p.t + opt * (1.0 / kC);
   p.path = pth;
   const T tau = abs_coeff<T>(a, p.lambda) * col;
   p.w = F::exp_(-tau);
-  const T q = ne * (T)(1.0 / a.n_obs);
+  // arrival direction by Snell: horizontal part scaled by q = ne/n_obs and
+  // u_z^2 = ce^2 + se^2 (1 - q)(1 + q), with 1 - q = eta0 (rho_obs - rho_e)/n_obs
+  // formed from density differences (no cancellation near the horizon)
+  const T drho = (T)(a.rho_obs - rho_bot) - (T)rho_bot * em_out;
+  const T omq = (T)a.eta0 * drho * (T)(1.0 / a.n_obs);
+  const T q = (T)1 - omq;
   p.ux = ux * q;
   p.uy = uy * q;
-  const T sl = se * q;
-  p.uz = -F::sqrt_(((T)1 - sl) * ((T)1 + sl));
+  p.uz = -F::sqrt_(ce * ce + se * se * omq * ((T)2 - omq));
   p.status = PHOTON_LANDED;
 }
 
@@ -543,7 +609,7 @@ __device__ __forceinline__ int telescope_hit(const Photon<T>& p, const double (*
   int best = -1;
   T best_s = (T)INFINITY;
   for (int k = 0; k < n_tel; ++k) {
-    const T ox = p.x - (T)tel[k][0], oy = p.y - (T)tel[k][1], oz = p.z - (T)tel[k][2];
+    const T ox = p.x - (T)tel[k][0], oy = p.y - (T)tel[k][1], oz = (T)(p.z - tel[k][2]);
     const T R = (T)tel[k][3];
     const T b = p.ux * ox + p.uy * oy + p.uz * oz;
     const T cc = (ox * ox + oy * oy + oz * oz) - R * R;
@@ -568,7 +634,7 @@ __device__ __forceinline__ int telescope_hit_masked(const Photon<T>& p, const do
   while (mask) {
     const int k = __builtin_ctz(mask);
     mask &= mask - 1u;
-    const T ox = p.x - (T)tel[k][0], oy = p.y - (T)tel[k][1], oz = p.z - (T)tel[k][2];
+    const T ox = p.x - (T)tel[k][0], oy = p.y - (T)tel[k][1], oz = (T)(p.z - tel[k][2]);
     const T R = (T)tel[k][3];
     const T b = p.ux * ox + p.uy * oy + p.uz * oz;
     const T cc = (ox * ox + oy * oy + oz * oz) - R * R;

@@ -20,8 +20,9 @@ OK, EINVAL, ECAPACITY, EHIP, ENODEV = 0, -1, -2, -3, -4
 FP64, FP32 = 0, 1
 CHERENKOV, FLUORESCENCE = 0, 1
 LANDED, HIT, UP, BELOW, OFFGRID, ABSORBED, INVALID = 0, 1, 2, 3, 4, 5, 6
+HORIZON_FLOAT = 7          # totals slot: near-horizon rays evaluated in float (queue full)
 N_STATUS = 8
-SINK_STATUS, SINK_TELESCOPES, SINK_GRID = 0, 1, 2
+SINK_STATUS, SINK_TELESCOPES, SINK_GRID, SINK_PLANE = 0, 1, 2, 3
 MAX_LAYERS, MAX_ABS, MAX_LINES, MAX_TELESCOPES = 8, 40, 32, 32
 
 P = C.c_void_p
@@ -48,7 +49,7 @@ class Emission(C.Structure):
 
 class Block(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("n_photons", C.c_int64), ("precision", C.c_int32)] + [
-        (f, P) for f in ("x", "y", "z", "ux", "uy", "uz", "wavelength_nm", "weight", "t_ns", "path_m",
+        (f, P) for f in ("x", "y", "ux", "uy", "uz", "wavelength_nm", "weight", "z", "t_ns", "path_m",
                          "segment", "j", "status")]
 
 
@@ -62,7 +63,7 @@ class Sink(C.Structure):
     _fields_ = [("kind", C.c_int32), ("status_totals", P), ("n_tel", C.c_int32),
                 ("tel", (C.c_double * 4) * MAX_TELESCOPES), ("hits", Hits), ("x_min", C.c_double),
                 ("y_min", C.c_double), ("cell", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
-                ("grid_count", P), ("grid_weight", P)]
+                ("grid_count", P), ("grid_weight", P), ("plane", P)]
 
 
 class Tuning(C.Structure):
@@ -176,7 +177,7 @@ class DeviceSegments:
 class PhotonBlock:
     """The common photon block (structure of arrays) on the GPU."""
 
-    REAL = ("x", "y", "z", "ux", "uy", "uz", "wavelength_nm", "weight")
+    REAL = ("x", "y", "ux", "uy", "uz", "wavelength_nm", "weight")
 
     def __init__(self, capacity: int, precision: int, device="cuda"):
         dt = torch.float64 if precision == FP64 else torch.float32
@@ -185,6 +186,7 @@ class PhotonBlock:
         self.n_photons = 0
         n = max(self.capacity, 1)
         self.t = {f: torch.empty(n, dtype=dt, device=device) for f in self.REAL}
+        self.t["z"] = torch.empty(n, dtype=torch.float64, device=device)
         self.t["t_ns"] = torch.empty(n, dtype=torch.float64, device=device)
         self.t["path_m"] = torch.empty(n, dtype=torch.float64, device=device)
         self.t["segment"] = torch.empty(n, dtype=torch.int32, device=device)
@@ -275,6 +277,16 @@ def sink_grid(x_min, y_min, cell, nx, ny, grid_count, grid_weight, totals=None) 
     s.x_min, s.y_min, s.cell, s.nx, s.ny = float(x_min), float(y_min), float(cell), int(nx), int(ny)
     s.grid_count = grid_count.data_ptr()
     s.grid_weight = grid_weight.data_ptr()
+    return s
+
+
+def sink_plane(block: PhotonBlock, totals=None) -> Sink:
+    """Every photon's final state written at its slot of `block`."""
+    s = Sink()
+    s.kind = SINK_PLANE
+    s.status_totals = None if totals is None else totals.data_ptr()
+    s._plane = block.struct()          # kept alive with the sink
+    s.plane = C.addressof(s._plane)
     return s
 
 
