@@ -247,3 +247,28 @@ def subsample(seg: dict, idx) -> dict:
         else:
             out[k] = v
     return out
+
+
+def splat_grid_128() -> dict:
+    """Ground grid of the differentiable form: 128 x 128 cells of 5 m centred
+    on the core, Gaussian width 5 m, square truncation at 4 sigma."""
+    return dict(x_min=-320.0, y_min=-320.0, cell=5.0, nx=128, ny=128, sigma=5.0, trunc=4.0)
+
+
+def perturbed_parameters(atm: dict, seg: dict, seed: int):
+    """Parameters of the target density of the differentiable form: scale
+    heights H_l (1 + 0.02 xi_l) with xi_l = +-1, n0 - 1 times 0.97, and every
+    segment direction turned by 0.2 degrees about a random axis (Rodrigues'
+    rotation), drawn from numpy's PCG64 under seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H = np.asarray(atm["scale_height"], np.float64)
+    xi = rng.choice([-1.0, 1.0], size=len(H))
+    H1 = H * (1.0 + 0.02 * xi)
+    eta1 = float(atm["n0_minus_1"]) * 0.97
+    d = np.stack([seg["dx"], seg["dy"], seg["dz"]], axis=1).astype(np.float64)
+    k = rng.normal(size=d.shape)
+    k /= np.linalg.norm(k, axis=1, keepdims=True)
+    a = np.deg2rad(0.2)
+    d1 = (d * np.cos(a) + np.cross(k, d) * np.sin(a)
+          + k * np.sum(k * d, axis=1, keepdims=True) * (1.0 - np.cos(a)))
+    return H1, eta1, d1
