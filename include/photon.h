@@ -310,6 +310,65 @@ int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm,
                     const photon_tuning* candidates, int32_t n_candidates, int32_t reps,
                     photon_tuning* best, float* best_ms, void* stream);
 
+/* ---- differentiable form: splatted ground density and its adjoint ---------- */
+
+/* Ground grid of the splat: cell (ix, iy) has its centre at
+   (x_min + (ix + 1/2) cell, y_min + (iy + 1/2) cell), row-major (ny rows of
+   nx cells). A landed photon of weight w adds
+   w exp(-d^2 / (2 sigma^2)) / (2 pi sigma^2) (per m^2) to every cell whose
+   centre lies within trunc * sigma of its landing point in x and in y.
+   Limits: nx ny <= 2^22, trunc sigma <= 64 cells. */
+typedef struct {
+  double x_min, y_min, cell;
+  int32_t nx, ny;
+  double sigma, trunc;
+} photon_splat_grid;
+
+/* Per-segment means (device f64, n) exactly as the count step evaluates
+   them: Frank-Tamm (section 1.2) or Y dE/dx L (section 1.1); 0 for
+   invalid segments. Errors: EINVAL. */
+int photon_means(const photon_segments* seg, const photon_atmosphere* atm,
+                 const photon_emission* em, double* mean, void* stream);
+
+/* Splatted ground density D of the Cherenkov photons of `seg` with the
+   counts frozen: `offsets` (n+1, device) and `mean0` (n, device f64) are
+   the offsets and means of the nominal parameters (photon_gen_cherenkov with
+   out == NULL and photon_means), while `seg` and `atm` hold the current
+   ones. Each landed photon carries the weight mu(current)/mean0 of its
+   segment (0 where mean0 <= 0) times its transmission exp(-tau); the random
+   numbers of photon (segment, j) are those of the plain form. density:
+   device, ny*nx values of the precision's type (double for PHOTON_FP64,
+   float for PHOTON_FP32), overwritten. status_totals: optional device
+   u64[PHOTON_N_STATUS]; landed photons with no cell in reach count as
+   OFFGRID. The FP32 form accumulates each block's density in LDS when it
+   has at most 16384 cells. Summation order varies between runs (atomic
+   adds). One call at a time per device. Errors: EINVAL (NULL pointers,
+   band, atmosphere, precision, grid). */
+int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* atm,
+                         double lambda_min_nm, double lambda_max_nm, uint64_t seed,
+                         int32_t precision, const uint64_t* offsets, const double* mean0,
+                         const photon_splat_grid* grid, void* density,
+                         unsigned long long* status_totals, void* stream);
+
+/* Adjoint of photon_splat_forward (same arguments): given the gradient
+   grad_density = dL/dD (device, the precision's type, ny*nx), writes
+   dL/dH_l for l < n_layers (grad_scale_height, device f64; 0 for layers of
+   infinite scale height), dL/d(n0 - 1) (grad_n0_minus_1, device f64, one
+   value) and the gradient with respect to each segment's direction vector
+   (dx, dy, dz) as given (grad_dx/dy/dz, device f64, n each; the direction
+   is normalised inside, so the gradient is orthogonal to it). Every photon
+   is regenerated from its random numbers and carried forward and back; the
+   truncation edge of the splat is not differentiated. Direction gradients
+   are summed with atomic adds (order varies between runs); the global ones
+   in a fixed order of per-block partial sums. One call at a time per
+   device. Errors: as photon_splat_forward. */
+int photon_splat_backward(const photon_segments* seg, const photon_atmosphere* atm,
+                          double lambda_min_nm, double lambda_max_nm, uint64_t seed,
+                          int32_t precision, const uint64_t* offsets, const double* mean0,
+                          const photon_splat_grid* grid, const void* grad_density,
+                          double* grad_scale_height, double* grad_n0_minus_1, double* grad_dx,
+                          double* grad_dy, double* grad_dz, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

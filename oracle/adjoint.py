@@ -231,28 +231,38 @@ class SplatModel:
         return np.sum((D - T) ** 2)
 
     # -------------------------------------------------------------- gradient --
-    def gradient(self, T, H, eta0, dx, dy, dz):
-        """dL/dH (per layer), dL/d(n0 - 1) and dL/d(dx, dy, dz) (per segment),
-        by the complex step. Layers with infinite scale height get 0."""
+    def vjp(self, G, H, eta0, dx, dy, dz):
+        """sum_g G_g dD_g/dtheta for a fixed array G (ny, nx): per-layer
+        scale heights, n0 - 1 and the per-segment directions, by the complex
+        step. Layers with infinite scale height get 0."""
         H = np.asarray(H, np.float64)
         dx, dy, dz = (np.asarray(v, np.float64) for v in (dx, dy, dz))
-        T = np.asarray(T, np.float64)
+        Gf = np.asarray(G, np.float64).ravel()
+
+        def dot(qq_flat_v):
+            _, flat, v = qq_flat_v
+            return float(np.sum(Gf[flat] * v.imag)) / STEP
+
         g_H = np.zeros(len(H))
         for l in range(len(H)):
             if not np.isfinite(H[l]):
                 continue
             Hc = H.astype(np.complex128)
             Hc[l] += 1j * STEP
-            g_H[l] = self.loss(T, Hc, eta0, dx, dy, dz).imag / STEP
-        g_eta = self.loss(T, H, eta0 + 1j * STEP, dx, dy, dz).imag / STEP
+            g_H[l] = dot(self.contributions(Hc, eta0, dx, dy, dz))
+        g_eta = dot(self.contributions(H, eta0 + 1j * STEP, dx, dy, dz))
         # per-segment directions: every photon depends on its own segment
         # only, so one complex step per component gives all segments at once
-        R = 2.0 * (self.density(H, eta0, dx, dy, dz).real - T).ravel()
         g_d = np.zeros((len(dx), 3))
         for c in range(3):
             d = [dx.astype(np.complex128), dy.astype(np.complex128), dz.astype(np.complex128)]
             d[c] = d[c] + 1j * STEP
             qq, flat, v = self.contributions(H, eta0, *d)
-            np.add.at(g_d[:, c], self.s_list[qq], R[flat] * v.imag / STEP)
+            np.add.at(g_d[:, c], self.s_list[qq], Gf[flat] * v.imag / STEP)
         return g_H, g_eta, g_d
 
+    def gradient(self, T, H, eta0, dx, dy, dz):
+        """dL/dH (per layer), dL/d(n0 - 1) and dL/d(dx, dy, dz) (per segment)
+        of L = sum (D - T)^2: the product with G = dL/dD = 2 (D - T)."""
+        D = self.density(H, eta0, dx, dy, dz).real
+        return self.vjp(2.0 * (D - np.asarray(T, np.float64)), H, eta0, dx, dy, dz)

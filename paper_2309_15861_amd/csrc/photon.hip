@@ -14,6 +14,9 @@
 //   k_fused      persistent: work chunks of the photon index space from an
 //                atomic queue; generation + propagation + collection in
 //                registers, per-segment constants staged in LDS.
+//   k_splat_adjoint persistent like k_fused: every photon regenerated and
+//                carried forward and back through the adjoint of the
+//                splatted ground density.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,6 +29,7 @@
 
 #include "photon.h"
 #include "photon_device.hpp"
+#include "photon_adjoint.hpp"
 
 using namespace ph;
 
@@ -65,6 +69,7 @@ struct GenParams {
   int32_t kind;
   int32_t n_lines;
   double inv_l1, inv_dl;                // Cherenkov: 1/lambda_min, 1/lambda_min - 1/lambda_max
+  double K;                             // Frank-Tamm prefactor (Cherenkov) or yield per MeV
   uint64_t thr[PHOTON_MAX_LINES];       // fluorescence line thresholds on the 32-bit word
   double line_nm[PHOTON_MAX_LINES];
 };
@@ -97,7 +102,15 @@ struct SinkDev {
   double *pz, *pt, *ppath;
   uint32_t *pseg, *pj;
   int32_t* pstatus;
+  // SPLAT (differentiable form): density of the run's precision, frozen
+  // nominal means; splat_lds: accumulate in LDS first (float form)
+  SplatGeom sg;
+  void* density;
+  const double* mu0;
+  int32_t splat_lds;
 };
+// Sink of the differentiable form (reached through photon_splat_forward only).
+constexpr int32_t kSinkSplat = 16;
 
 // ------------------------------------------------------ wave/block helpers --
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -267,6 +280,13 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
+// Grid-stride clear of n 64-bit words (a kernel, not a memset node, so that
+// captured graphs replay it faithfully).
+__global__ void k_zero64_n(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
 // -------------------------------------------------------------- generation --
 template <typename T>
 __device__ __forceinline__ void generate(const SegConst<T>& c, uint32_t j, const GenParams& g, uint32_t k0,
@@ -376,14 +396,70 @@ __device__ void flush_status(StatusCounter& sc, unsigned long long* totals) {
   if (threadIdx.x < PHOTON_N_STATUS && s_tot[threadIdx.x]) atomicAdd(&totals[threadIdx.x], s_tot[threadIdx.x]);
 }
 
+// A telescope hit record as staged in LDS.
+struct HitRec {
+  double x, y, z, t;
+  uint32_t seg, j;
+  int32_t tel;
+  float ux, uy, uz, lam, w;
+};
+constexpr int kHitStage = 128;  // hit records staged per block and work chunk
+
+struct HitStage {
+  unsigned int n;
+  HitRec rec[kHitStage];
+};
+
+__device__ __forceinline__ void write_hit(const photon_hits& h, unsigned long long slot, const HitRec& r) {
+  h.segment[slot] = r.seg;
+  h.j[slot] = r.j;
+  h.telescope[slot] = r.tel;
+  h.x[slot] = r.x;
+  h.y[slot] = r.y;
+  h.z[slot] = r.z;
+  h.t_ns[slot] = r.t;
+  h.ux[slot] = r.ux;
+  h.uy[slot] = r.uy;
+  h.uz[slot] = r.uz;
+  h.wavelength_nm[slot] = r.lam;
+  h.weight[slot] = r.w;
+}
+
+// Block-wide: moves the staged hits to the output with one global atomic.
+__device__ __forceinline__ void flush_hits(HitStage* st, const photon_hits& h) {
+  __shared__ unsigned long long s_base;
+  __syncthreads();
+  const unsigned int n = st->n < (unsigned int)kHitStage ? st->n : (unsigned int)kHitStage;
+  if (threadIdx.x == 0) s_base = n ? atomicAdd(h.count, (unsigned long long)n) : 0ull;
+  __syncthreads();
+  for (unsigned int i = threadIdx.x; i < n; i += blockDim.x) {
+    const unsigned long long slot = s_base + i;
+    if (slot < (unsigned long long)h.capacity) write_hit(h, slot, st->rec[i]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) st->n = 0u;
+}
+
 // Applies the sink to one propagated photon (in the lanes that hold one);
 // returns the final status. Hit records are compacted per wave: one atomic
 // per wave reserves the slots, lanes write at their rank among the hits.
-template <typename T>
+// SPLAT: the sink of the differentiable form only (a separate instantiation,
+// so that the other sinks' kernels carry none of its code).
+template <typename T, bool SPLAT = false>
 __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], double n_obs, Photon<T>& p,
-                                           uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q = 0) {
+                                           uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q = 0,
+                                           HitStage* stage = nullptr, float* splat_lds = nullptr) {
   int st = active ? p.status : -1;
-  if (sk.kind == PHOTON_SINK_PLANE) {
+  if constexpr (SPLAT) {
+    if (active && st == PHOTON_LANDED) {
+      bool in;
+      if (sizeof(T) == 4 && splat_lds)
+        in = splat_add<T, float>(sk.sg, (double)p.x, (double)p.y, p.w, splat_lds);
+      else
+        in = splat_add<T, T>(sk.sg, (double)p.x, (double)p.y, p.w, (T*)sk.density);
+      if (!in) st = PHOTON_OFFGRID;
+    }
+  } else if (sk.kind == PHOTON_SINK_PLANE) {
     if (active && slot_q < (uint64_t)sk.plane_capacity) {
       ((T*)sk.px)[slot_q] = p.x;
       ((T*)sk.py)[slot_q] = p.y;
@@ -417,28 +493,46 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
     const bool hit = k >= 0;
     const unsigned long long m = __ballot(hit);
     if (m) {
-      const int leader = __ffsll((long long)m) - 1;
-      unsigned long long base = 0;
-      if (lane_id() == leader) base = atomicAdd(sk.hits.count, (unsigned long long)__popcll(m));
-      base = __shfl(base, leader, kWaveSize);
+      HitRec r;
       if (hit) {
-        const unsigned long long rank = __popcll(m & ((1ull << lane_id()) - 1ull));
-        const unsigned long long slot = base + rank;
-        if (slot < (unsigned long long)sk.hits.capacity) {
-          sk.hits.segment[slot] = seg_row;
-          sk.hits.j[slot] = j;
-          sk.hits.telescope[slot] = k;
-          sk.hits.x[slot] = (double)p.x + (double)s_hit * (double)p.ux;
-          sk.hits.y[slot] = (double)p.y + (double)s_hit * (double)p.uy;
-          sk.hits.z[slot] = p.z + (double)s_hit * (double)p.uz;
-          sk.hits.t_ns[slot] = p.t + n_obs * (double)s_hit / kC;
-          sk.hits.ux[slot] = (float)p.ux;
-          sk.hits.uy[slot] = (float)p.uy;
-          sk.hits.uz[slot] = (float)p.uz;
-          sk.hits.wavelength_nm[slot] = (float)p.lambda;
-          sk.hits.weight[slot] = (float)p.w;
-        }
+        r.seg = seg_row;
+        r.j = j;
+        r.tel = k;
+        r.x = (double)p.x + (double)s_hit * (double)p.ux;
+        r.y = (double)p.y + (double)s_hit * (double)p.uy;
+        r.z = p.z + (double)s_hit * (double)p.uz;
+        r.t = p.t + n_obs * (double)s_hit / kC;
+        r.ux = (float)p.ux;
+        r.uy = (float)p.uy;
+        r.uz = (float)p.uz;
+        r.lam = (float)p.lambda;
+        r.w = (float)p.w;
         st = PHOTON_HIT;
+      }
+      // one atomic per wave reserves the slots (in the block's LDS stage when
+      // there is one, else in the output); lanes write at their rank
+      const int leader = __ffsll((long long)m) - 1;
+      const unsigned int nh = (unsigned int)__popcll(m);
+      const unsigned int rank = (unsigned int)__popcll(m & ((1ull << lane_id()) - 1ull));
+      unsigned long long base = 0;
+      if (stage) {
+        if (lane_id() == leader) base = atomicAdd(&stage->n, nh);
+        base = __shfl(base, leader, kWaveSize);
+        if (hit) {
+          if (base + rank < (unsigned long long)kHitStage) {
+            stage->rec[base + rank] = r;
+          } else {
+            const unsigned long long slot = atomicAdd(sk.hits.count, 1ull);  // stage full
+            if (slot < (unsigned long long)sk.hits.capacity) write_hit(sk.hits, slot, r);
+          }
+        }
+      } else {
+        if (lane_id() == leader) base = atomicAdd(sk.hits.count, (unsigned long long)nh);
+        base = __shfl(base, leader, kWaveSize);
+        if (hit) {
+          const unsigned long long slot = base + rank;
+          if (slot < (unsigned long long)sk.hits.capacity) write_hit(sk.hits, slot, r);
+        }
       }
     }
   } else if (sk.kind == PHOTON_SINK_GRID) {
@@ -508,12 +602,21 @@ struct FusedArgs {
 };
 static_assert(sizeof(FusedArgs) <= 4000, "fused kernel arguments must stay below 4 KB");
 
+// Weight factor of segment s in the differentiable form: its Frank-Tamm mean
+// at the current parameters over the frozen nominal mean (section 1.2).
+template <typename T>
+__device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
+  const double m0 = A.sk.mu0[s];
+  const double mu = mean_cherenkov(A.seg, s, A.atm, A.g.K);
+  return (T)(m0 > 0.0 ? mu / m0 : 0.0);
+}
+
 // Persistent kernel: blocks take chunks of the photon index space from an
 // atomic queue; per chunk the segments it covers are found by two wave
 // searches and their constants staged in LDS; every photon is generated,
 // propagated and collected in registers. In the float form, rays near the
 // horizon are appended to a queue for the double pass instead.
-template <typename T, int BS>
+template <typename T, int BS, bool SPLAT = false>
 __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
   __shared__ SegConst<T> s_seg[kWindow];
   __shared__ uint64_t s_off[kWindow + 1];
@@ -523,10 +626,21 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ unsigned int s_dcount;
+  __shared__ HitStage s_hits;
+  __shared__ T s_wsc[SPLAT ? kWindow : 1];  // SPLAT: per-segment weight factors mu/mu0
+  extern __shared__ float s_splat[];         // dynamic: the float density of the block (SPLAT)
   constexpr bool kDefer = sizeof(T) == 4;
+  const bool stage_hits = !SPLAT && A.sk.kind == PHOTON_SINK_TELESCOPES;
+  float* splat_lds = (SPLAT && A.sk.splat_lds) ? s_splat : nullptr;
+  const int n_cells = A.sk.sg.nx * A.sk.sg.ny;
 
   const int tid = threadIdx.x;
-  if (tid == 0) s_dcount = 0u;
+  if (tid == 0) {
+    s_dcount = 0u;
+    s_hits.n = 0u;
+  }
+  if (splat_lds)
+    for (int k = tid; k < n_cells; k += BS) splat_lds[k] = 0.0f;
   if (tid < PHOTON_MAX_LINES) {
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = (T)A.g.line_nm[tid];
@@ -572,6 +686,7 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
     if (win) {
       for (int t = tid; t < W; t += BS) {
         seg_const<T>(A.seg, lo + t, A.atm, cher, s_seg[t]);
+        if constexpr (SPLAT) s_wsc[t] = splat_wscale<T>(A, lo + t);
         s_off[t] = offsets[lo + t];
       }
       if (tid == 0) s_off[W] = offsets[lo + W];
@@ -581,6 +696,7 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
       SegConst<T> c;
       uint64_t off_s;
       int64_t s;
+      T wsc = (T)1;
       if (win) {
         int a = 0, b = (int)W;  // s_off[a] <= q < s_off[b]
         while (b - a > 1) {
@@ -588,17 +704,20 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
           if (s_off[mid] <= q) a = mid; else b = mid;
         }
         c = s_seg[a];
+        if constexpr (SPLAT) wsc = s_wsc[a];
         off_s = s_off[a];
         s = lo + a;
       } else {
         s = lane_upper_index(offsets, n_seg, q);
         seg_const<T>(A.seg, s, A.atm, cher, c);
+        if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
         off_s = offsets[s];
       }
       const uint32_t j = (uint32_t)(q - off_s);
       Photon<T> p;
       generate<T>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
       propagate<T, kDefer>(A.atm, p);
+      if constexpr (SPLAT) p.w *= wsc;
       bool forced = false;
       if (kDefer) {
         const bool defer = p.status == kDeferred;
@@ -623,16 +742,26 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
         }
       }
       if (!kDefer || p.status != kDeferred) {
-        const int st = sink_photon<T>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q);
+        const int st = sink_photon<T, SPLAT>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
+                                             stage_hits ? &s_hits : nullptr, splat_lds);
         sc.add(st);
         if (forced) sc.add(PHOTON_HORIZON_FLOAT);
       }
     }
+    if (stage_hits) flush_hits(&s_hits, A.sk.hits);
     __syncthreads();
   }
   if (kDefer && tid == 0) {
     const uint64_t nd = s_dcount;
     A.defer_counts[blockIdx.x] = nd < (uint64_t)A.defer_cap ? nd : (uint64_t)A.defer_cap;
+  }
+  if (splat_lds) {
+    // the block's density into the output (the loop above ends with a barrier)
+    float* D = (float*)A.sk.density;
+    for (int k = tid; k < n_cells; k += BS) {
+      const float v = splat_lds[k];
+      if (v != 0.0f) atomicAdd(&D[k], v);
+    }
   }
   if (A.sk.totals) flush_status(sc, A.sk.totals);
 }
@@ -667,6 +796,8 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     Photon<double> p;
     generate<double>(c, e.y, A.g, A.k0, A.k1, s_thr, s_lines, p);
     propagate<double>(A.atm, p);
+    const bool splat = A.sk.kind == kSinkSplat;
+    if (splat) p.w *= splat_wscale<double>(A, s);
     // collected in the run's precision (float)
     Photon<float> pf;
     pf.x = (float)p.x;
@@ -680,10 +811,191 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     pf.t = p.t;
     pf.path = p.path;
     pf.status = p.status;
-    const int st = sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y);
+    const int st = splat ? sink_photon<float, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true)
+                         : sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y);
     sc.add(st);
   }
   if (A.sk.totals) flush_status(sc, A.sk.totals);
+}
+
+// ---------------------------------------------- adjoint of the splatted density --
+struct AdjArgs {
+  SegView seg;
+  int64_t n_seg;
+  AtmDev atm;
+  uint32_t k0, k1;
+  double K, inv_l1, inv_dl;
+  const uint64_t* offsets;   // frozen counts' offsets (n_seg + 1)
+  int64_t chunk;
+  const double* mu0;         // frozen nominal means
+  SplatGeom sg;
+  const void* grad;          // dL/dD, the run's precision
+  double *gdx, *gdy, *gdz;   // per-segment direction gradients (accumulated)
+  double* partials;          // kAdjWords per block
+  unsigned long long* cursor;
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int d = kWaveSize / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWaveSize);
+  return v;
+}
+
+// Sums over each run of equal keys of a wave (keys nondecreasing over the
+// lanes that hold a photon, negative and distinct in the others); the last
+// lane of a run adds the run's sums to the outputs, one atomic per component.
+__device__ __forceinline__ void seg_reduce_add(long long key, double v0, double v1, double v2, double* o0,
+                                               double* o1, double* o2) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWaveSize; d <<= 1) {
+    const long long ku = __shfl_up(key, d, kWaveSize);
+    const double a0 = __shfl_up(v0, d, kWaveSize);
+    const double a1 = __shfl_up(v1, d, kWaveSize);
+    const double a2 = __shfl_up(v2, d, kWaveSize);
+    if (lane >= d && ku == key) {
+      v0 += a0;
+      v1 += a1;
+      v2 += a2;
+    }
+  }
+  const long long kn = __shfl_down(key, 1, kWaveSize);
+  const bool last = lane == kWaveSize - 1 || kn != key;
+  if (last && key >= 0 && (v0 != 0.0 || v1 != 0.0 || v2 != 0.0)) {
+    atomicAdd(&o0[key], v0);
+    atomicAdd(&o1[key], v1);
+    atomicAdd(&o2[key], v2);
+  }
+}
+
+// Persistent like k_fused: chunks of the photon index space from an atomic
+// queue, the chunk's segment offsets staged in LDS. Every photon is
+// regenerated and carried forward and back (adjoint_photon); direction
+// gradients are reduced per segment over the wave, the global sums per block
+// into partials (summed in a fixed order by k_adj_finalize).
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
+  __shared__ uint64_t s_off[kWindow + 1];
+  __shared__ unsigned long long s_c0;
+  __shared__ int64_t s_lo, s_hi;
+  __shared__ double s_red[BS / kWaveSize][kAdjWords];
+  const int tid = threadIdx.x;
+  const int64_t n_seg = A.n_seg;
+  const uint64_t* __restrict__ offsets = A.offsets;
+  const uint64_t total = offsets[n_seg];
+  const T* G = (const T*)A.grad;
+  AdjSums acc;
+  adj_clear(acc);
+  for (;;) {
+    if (tid == 0) s_c0 = atomicAdd(A.cursor, (unsigned long long)A.chunk);
+    __syncthreads();
+    const uint64_t c0 = s_c0;
+    if (c0 >= total) break;
+    const uint64_t v1 = min(c0 + (uint64_t)A.chunk, total);
+    const int wave = tid / kWaveSize;
+    if (wave == 0) {
+      const int64_t sl = wave_upper_index(offsets, n_seg, c0);
+      if (lane_id() == 0) s_lo = sl;
+    }
+    if (wave == (BS > kWaveSize ? 1 : 0)) {
+      const int64_t sh = wave_upper_index(offsets, n_seg, v1 - 1);
+      if (lane_id() == 0) s_hi = sh;
+    }
+    __syncthreads();
+    const int64_t lo = min(s_lo, n_seg - 1);
+    const int64_t W = min(s_hi, n_seg - 1) - lo + 1;
+    const bool win = W >= 1 && W <= kWindow;
+    if (win)
+      for (int t = tid; t <= W; t += BS) s_off[t] = offsets[lo + t];
+    __syncthreads();
+    for (uint64_t qb = c0; qb < v1; qb += BS) {
+      const uint64_t q = qb + tid;
+      long long key = -1 - (long long)lane_id();
+      double dd[3] = {0.0, 0.0, 0.0};
+      if (q < v1) {
+        int64_t s;
+        uint64_t off_s;
+        if (win) {
+          int a = 0, b = (int)W;  // s_off[a] <= q < s_off[b]
+          while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            if (s_off[mid] <= q) a = mid; else b = mid;
+          }
+          s = lo + a;
+          off_s = s_off[a];
+        } else {
+          s = lane_upper_index(offsets, n_seg, q);
+          off_s = offsets[s];
+        }
+        key = s;
+        if (seg_ok(A.seg, s)) {
+          SegRaw sg;
+          sg.x0 = A.seg.x0[s];
+          sg.y0 = A.seg.y0[s];
+          sg.z0 = A.seg.z0[s];
+          sg.dx = A.seg.dx[s];
+          sg.dy = A.seg.dy[s];
+          sg.dz = A.seg.dz[s];
+          sg.len = A.seg.len[s];
+          sg.beta = A.seg.beta[s];
+          sg.zz = A.seg.charge ? (double)(A.seg.charge[s] * A.seg.charge[s]) : 1.0;
+          sg.mu0 = A.mu0[s];
+          sg.idx = seg_idx(A.seg, s);
+          sg.shower = seg_shower(A.seg, s);
+          adjoint_photon<T, T>(A.atm, sg, (uint32_t)(q - off_s), A.k0, A.k1, A.K, A.inv_l1, A.inv_dl, A.sg, G, acc,
+                               dd);
+        }
+      }
+      seg_reduce_add(key, dd[0], dd[1], dd[2], A.gdx, A.gdy, A.gdz);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kAdjWords; ++k) {
+    const double v = wave_sum_d(adj_word(acc, k));
+    if (lane_id() == 0) s_red[tid / kWaveSize][k] = v;
+  }
+  __syncthreads();
+  if (tid < kAdjWords) {
+    double t = 0.0;
+    for (int w = 0; w < BS / kWaveSize; ++w) t += s_red[w][tid];
+    A.partials[(int64_t)blockIdx.x * kAdjWords + tid] = t;
+  }
+}
+
+// Sums the block partials in block order and maps them to the parameters:
+// dL/dH_k = direct part + sum over layers m > k of dL/d ln rb[m] times
+// d ln rb[m]/dH_k = (hb[k+1] - hb[k])/H_k^2 (rb[m] is the product of
+// exp(-(hb[i+1] - hb[i])/H_i) over i < m). Layers of infinite scale height get 0.
+__global__ __launch_bounds__(64) void k_adj_finalize(const double* __restrict__ partials, int nb, AtmDev atm,
+                                                     double* grad_H, double* grad_eta) {
+  __shared__ double s[kAdjWords];
+  const int k = threadIdx.x;
+  if (k < kAdjWords) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partials[(int64_t)b * kAdjWords + k];
+    s[k] = t;
+  }
+  __syncthreads();
+  if (k < atm.nl) {
+    const bool homog = (atm.homog_mask >> k) & 1;
+    double g = s[PHOTON_MAX_LAYERS + k];
+    if (k + 1 < atm.nl) {
+      const double f = (atm.hb[k + 1] - atm.hb[k]) * atm.invH[k] * atm.invH[k];
+      for (int m = k + 1; m < atm.nl; ++m) g += s[m] * f;
+    }
+    grad_H[k] = homog ? 0.0 : g;
+  }
+  if (k == 0) *grad_eta = s[2 * PHOTON_MAX_LAYERS];
+}
+
+// Per-segment means (section 1.2 Frank-Tamm, section 1.1 yield), the same
+// evaluation as the count kernel's.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_means(SegView seg, int64_t n, AtmDev atm, double K, double* mean) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  mean[i] = KIND == PHOTON_CHERENKOV ? mean_cherenkov(seg, i, atm, K) : mean_fluor(seg, i, K);
 }
 
 // ------------------------------------------------------------ host helpers --
@@ -941,9 +1253,13 @@ struct DeviceState {
   bool checked = false;
   bool ok = false;
   int cu = 0;
+  size_t lds_per_block = 0;             // largest LDS allocation of one workgroup
   unsigned long long* work = nullptr;  // [0] = fused work cursor, [kDeferCounts..] per-block deferred counts
   uint2* defer_q = nullptr;            // deferred (segment row, j), kDeferCap entries
   int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fused blocks per CU by [precision][block 128/256/512]
+  int occ_splat[3] = {0, 0, 0};             // splat fused blocks per CU (see launch_fused_bs)
+  int occ_adj[2] = {0, 0};                  // adjoint blocks per CU by precision
+  double* adj_part = nullptr;               // per-block partial sums of the adjoint
 };
 std::mutex g_mu;
 DeviceState g_dev[64];
@@ -960,6 +1276,7 @@ int current_device(DeviceState** out) {
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(PHOTON_ENODEV, "hipGetDeviceProperties failed");
     d.ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
     d.cu = prop.multiProcessorCount;
+    d.lds_per_block = prop.sharedMemPerBlock;
     if (d.ok && hipMalloc(&d.work, sizeof(unsigned long long) * kWorkWords) != hipSuccess) {
       d.ok = false;
       d.work = nullptr;
@@ -1099,11 +1416,22 @@ int ensure_defer_queue(DeviceState* dev) {
   return PHOTON_OK;
 }
 
-template <typename T, int BS>
+template <typename T, int BS, bool SPLAT = false>
 int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                     const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
-                    DeviceState* dev, hipStream_t st) {
-  int occ = fused_occupancy<T, BS>(dev);
+                    DeviceState* dev, hipStream_t st, size_t dyn_lds = 0) {
+  int occ;
+  if (!SPLAT) {
+    occ = fused_occupancy<T, BS>(dev);
+  } else {
+    // splat variants: 0 float/1024 with the LDS density, 1 float/256, 2 double/256
+    int& o = dev->occ_splat[sizeof(T) == 8 ? 2 : (dyn_lds ? 0 : 1)];
+    if (o == 0) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_fused<T, BS, true>, BS, dyn_lds) != hipSuccess || o < 1)
+        o = 1;
+    }
+    occ = o;
+  }
   if (bpc > 0 && bpc < occ) occ = bpc;
   int64_t grid = (int64_t)dev->cu * occ;
   if (n_ph >= 0) {
@@ -1132,7 +1460,7 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   A.defer_q = dev->defer_q;
   A.defer_cap = defer ? kDeferCap / grid : 0;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
-  hipLaunchKernelGGL((k_fused<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, A);
+  hipLaunchKernelGGL((k_fused<T, BS, SPLAT>), dim3((unsigned)grid), dim3(BS), dyn_lds, st, A);
   if (defer) hipLaunchKernelGGL((k_fused_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A);
   return check_launch();
 }
@@ -1221,6 +1549,124 @@ int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const p
   if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.seed, counts, offsets, st))) return rc;
   if ((rc = clear_sink(a.sk, st))) return rc;
   return enqueue_fused(a, offsets, -1, tun, dev, st);
+}
+
+// ------------------------------------------------------ differentiable form --
+constexpr size_t kSplatLdsMax = 64 * 1024;  // LDS density of the float form (128 x 128 cells)
+constexpr int64_t kAdjChunk = 2048;
+
+int prep_splat_grid(const photon_splat_grid* gr, SplatGeom* g) {
+  if (!gr) return fail(PHOTON_EINVAL, "splat grid is NULL");
+  if (gr->nx < 1 || gr->ny < 1 || (int64_t)gr->nx * gr->ny > (1 << 22))
+    return fail(PHOTON_EINVAL, "splat grid shape %d x %d invalid", gr->nx, gr->ny);
+  if (!(gr->cell > 0.0) || !finite(gr->cell) || !finite(gr->x_min) || !finite(gr->y_min))
+    return fail(PHOTON_EINVAL, "splat grid origin/cell invalid");
+  if (!(gr->sigma > 0.0) || !finite(gr->sigma)) return fail(PHOTON_EINVAL, "splat sigma must be > 0");
+  if (!(gr->trunc > 0.0) || !finite(gr->trunc) || gr->trunc * gr->sigma > 64.0 * gr->cell)
+    return fail(PHOTON_EINVAL, "splat truncation must be > 0 and reach at most 64 cells");
+  g->x_min = gr->x_min;
+  g->y_min = gr->y_min;
+  g->cell = gr->cell;
+  g->nx = gr->nx;
+  g->ny = gr->ny;
+  g->sigma = gr->sigma;
+  g->reach = gr->trunc * gr->sigma;
+  g->norm = 1.0 / (2.0 * kPi * gr->sigma * gr->sigma);
+  g->inv_2s2 = 1.0 / (2.0 * gr->sigma * gr->sigma);
+  g->q = std::exp(-(gr->cell * gr->cell) / (gr->sigma * gr->sigma));
+  return PHOTON_OK;
+}
+
+struct SplatCall {
+  SegView sv;
+  int64_t n = 0;
+  AtmDev ad;
+  GenParams g;
+  SplatGeom sg;
+  uint64_t seed = 0;
+  int32_t precision = 0;
+};
+
+int prep_splat_call(const photon_segments* seg, const photon_atmosphere* atm, double lambda_min_nm,
+                    double lambda_max_nm, uint64_t seed, int32_t precision, const uint64_t* offsets,
+                    const double* mean0, const photon_splat_grid* grid, SplatCall* c) {
+  int rc;
+  photon_emission em;
+  std::memset(&em, 0, sizeof em);
+  em.kind = PHOTON_CHERENKOV;
+  em.lambda_min_nm = lambda_min_nm;
+  em.lambda_max_nm = lambda_max_nm;
+  if ((rc = prep_seg(seg, &c->sv, false))) return rc;
+  if ((rc = prep_atm(atm, &c->ad))) return rc;
+  if ((rc = prep_emission(&em, &c->g))) return rc;
+  if ((rc = prep_precision(precision))) return rc;
+  if ((rc = prep_splat_grid(grid, &c->sg))) return rc;
+  if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
+  if (!mean0 && seg->n > 0) return fail(PHOTON_EINVAL, "mean0 is NULL");
+  c->g.K = (2.0 * kPi * kAlpha) * ((1e9 / lambda_min_nm) - (1e9 / lambda_max_nm));
+  c->n = seg->n;
+  c->seed = seed;
+  c->precision = precision;
+  return PHOTON_OK;
+}
+
+int ensure_adj_partials(DeviceState* dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev->adj_part) return PHOTON_OK;
+  if (hipMalloc(&dev->adj_part, sizeof(double) * kAdjWords * kMaxFusedGrid) != hipSuccess) {
+    dev->adj_part = nullptr;
+    return fail(PHOTON_EHIP, "adjoint partial-sum allocation failed");
+  }
+  return PHOTON_OK;
+}
+
+template <typename T>
+int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* mean0, const void* grad,
+                   double* gH, double* geta, double* gdx, double* gdy, double* gdz, DeviceState* dev,
+                   hipStream_t st) {
+  constexpr int BS = 256;
+  int& occ = dev->occ_adj[sizeof(T) == 8 ? 0 : 1];
+  if (occ == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_splat_adjoint<T, BS>, BS, 0) != hipSuccess || occ < 1)
+      occ = 1;
+  }
+  int64_t grid = (int64_t)dev->cu * occ;
+  if (grid > kMaxFusedGrid) grid = kMaxFusedGrid;
+  int rc;
+  if ((rc = ensure_adj_partials(dev))) return rc;
+  if (c.n > 0) {
+    const unsigned zb = (unsigned)std::min<int64_t>(ceil_div(c.n, 256), 4096);
+    hipLaunchKernelGGL(k_zero64_n, dim3(zb), dim3(256), 0, st, (unsigned long long*)gdx, c.n);
+    hipLaunchKernelGGL(k_zero64_n, dim3(zb), dim3(256), 0, st, (unsigned long long*)gdy, c.n);
+    hipLaunchKernelGGL(k_zero64_n, dim3(zb), dim3(256), 0, st, (unsigned long long*)gdz, c.n);
+  }
+  int nb = 0;
+  if (c.n > 0) {
+    AdjArgs A;
+    A.seg = c.sv;
+    A.n_seg = c.n;
+    A.atm = c.ad;
+    A.k0 = (uint32_t)(c.seed & 0xffffffffu);
+    A.k1 = (uint32_t)(c.seed >> 32);
+    A.K = c.g.K;
+    A.inv_l1 = c.g.inv_l1;
+    A.inv_dl = c.g.inv_dl;
+    A.offsets = offsets;
+    A.chunk = kAdjChunk;
+    A.mu0 = mean0;
+    A.sg = c.sg;
+    A.grad = grad;
+    A.gdx = gdx;
+    A.gdy = gdy;
+    A.gdz = gdz;
+    A.partials = dev->adj_part;
+    A.cursor = dev->work;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
+    hipLaunchKernelGGL((k_splat_adjoint<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, A);
+    nb = (int)grid;
+  }
+  hipLaunchKernelGGL(k_adj_finalize, dim3(1), dim3(64), 0, st, (const double*)dev->adj_part, nb, c.ad, gH, geta);
+  return check_launch();
 }
 
 }  // namespace
@@ -1423,6 +1869,95 @@ int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm, co
   *best = candidates[best_i];
   *best_ms = best_t;
   return PHOTON_OK;
+}
+
+int photon_means(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em, double* mean,
+                 void* stream) {
+  SegView sv;
+  AtmDev ad;
+  GenParams g;
+  int rc;
+  if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
+  if ((rc = prep_seg(seg, &sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
+  if ((rc = prep_atm(atm, &ad))) return rc;
+  if ((rc = prep_emission(em, &g))) return rc;
+  if (!mean && seg->n > 0) return fail(PHOTON_EINVAL, "mean is NULL");
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  if (seg->n == 0) return PHOTON_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned nb = (unsigned)ceil_div(seg->n, 256);
+  if (em->kind == PHOTON_CHERENKOV) {
+    const double K = (2.0 * kPi * kAlpha) * ((1e9 / em->lambda_min_nm) - (1e9 / em->lambda_max_nm));
+    hipLaunchKernelGGL(k_means<PHOTON_CHERENKOV>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, K, mean);
+  } else {
+    hipLaunchKernelGGL(k_means<PHOTON_FLUORESCENCE>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, em->yield_per_MeV,
+                       mean);
+  }
+  return check_launch();
+}
+
+int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* atm, double lambda_min_nm,
+                         double lambda_max_nm, uint64_t seed, int32_t precision, const uint64_t* offsets,
+                         const double* mean0, const photon_splat_grid* grid, void* density,
+                         unsigned long long* status_totals, void* stream) {
+  SplatCall c;
+  int rc;
+  if ((rc = prep_splat_call(seg, atm, lambda_min_nm, lambda_max_nm, seed, precision, offsets, mean0, grid, &c)))
+    return rc;
+  if (!density) return fail(PHOTON_EINVAL, "density is NULL");
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int cells = c.sg.nx * c.sg.ny;
+  if (precision == PHOTON_FP64)
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st,
+                       (unsigned long long*)density, cells);
+  else
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, (uint32_t*)density, cells);
+  if (status_totals) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, status_totals, PHOTON_N_STATUS);
+  if (c.n == 0) return check_launch();
+  SinkDev sk;
+  std::memset(&sk, 0, sizeof sk);
+  sk.kind = kSinkSplat;
+  sk.totals = status_totals;
+  sk.sg = c.sg;
+  sk.density = density;
+  sk.mu0 = mean0;
+  const size_t lds = (size_t)cells * sizeof(float);
+  hipFuncAttributes fa;
+  const bool lds_fits = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<float, 1024, true>)) ==
+                            hipSuccess &&
+                        fa.sharedSizeBytes + lds <= dev->lds_per_block;
+  if (precision == PHOTON_FP32 && lds <= kSplatLdsMax && lds_fits) {
+    sk.splat_lds = 1;
+    return launch_fused_bs<float, 1024, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 8192, 0, sk, dev, st, lds);
+  }
+  if (precision == PHOTON_FP32)
+    return launch_fused_bs<float, 256, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st);
+  return launch_fused_bs<double, 256, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st);
+}
+
+int photon_splat_backward(const photon_segments* seg, const photon_atmosphere* atm, double lambda_min_nm,
+                          double lambda_max_nm, uint64_t seed, int32_t precision, const uint64_t* offsets,
+                          const double* mean0, const photon_splat_grid* grid, const void* grad_density,
+                          double* grad_scale_height, double* grad_n0_minus_1, double* grad_dx, double* grad_dy,
+                          double* grad_dz, void* stream) {
+  SplatCall c;
+  int rc;
+  if ((rc = prep_splat_call(seg, atm, lambda_min_nm, lambda_max_nm, seed, precision, offsets, mean0, grid, &c)))
+    return rc;
+  if (!grad_density) return fail(PHOTON_EINVAL, "grad_density is NULL");
+  if (!grad_scale_height || !grad_n0_minus_1) return fail(PHOTON_EINVAL, "global gradient outputs are NULL");
+  if (seg->n > 0 && (!grad_dx || !grad_dy || !grad_dz)) return fail(PHOTON_EINVAL, "direction gradient outputs are NULL");
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  return precision == PHOTON_FP64
+             ? launch_adjoint<double>(c, offsets, mean0, grad_density, grad_scale_height, grad_n0_minus_1, grad_dx,
+                                      grad_dy, grad_dz, dev, st)
+             : launch_adjoint<float>(c, offsets, mean0, grad_density, grad_scale_height, grad_n0_minus_1, grad_dx,
+                                     grad_dy, grad_dz, dev, st);
 }
 
 }  // extern "C"

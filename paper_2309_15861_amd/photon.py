@@ -70,6 +70,11 @@ class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("chunk", C.c_int32), ("blocks_per_cu", C.c_int32)]
 
 
+class SplatGrid(C.Structure):
+    _fields_ = [("x_min", C.c_double), ("y_min", C.c_double), ("cell", C.c_double), ("nx", C.c_int32),
+                ("ny", C.c_int32), ("sigma", C.c_double), ("trunc", C.c_double)]
+
+
 class PhotonError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libphoton error {code}: {msg}")
@@ -98,9 +103,13 @@ def lib():
         L.photon_plan_launch.argtypes = [P, P]
         L.photon_plan_destroy.argtypes = [P]
         L.photon_autotune.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P, C.c_int32, C.c_int32, P, P, P]
+        L.photon_means.argtypes = [P, P, P, P, P]
+        L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
+        L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
+                                            P, P, P, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
                   "photon_run_fused", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
-                  "photon_autotune"):
+                  "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -418,3 +427,104 @@ def autotune(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precision
                                  _ptr(offsets), C.byref(sink), arr, len(candidates), int(reps), C.byref(best),
                                  C.byref(ms), _stream()))
     return best, ms.value
+
+
+# ------------------------------------------------------ differentiable form --
+def means(seg: DeviceSegments, atm: Atmosphere, em: Emission, device="cuda"):
+    """Per-segment means (float64 tensor), as the count step evaluates them."""
+    out = torch.empty(max(seg.n, 1), dtype=torch.float64, device=device)
+    s = seg.struct()
+    _check(lib().photon_means(C.byref(s), C.byref(atm), C.byref(em), _ptr(out), _stream()))
+    return out[:seg.n]
+
+
+def splat_grid(d: dict) -> SplatGrid:
+    g = SplatGrid()
+    g.x_min, g.y_min, g.cell = float(d["x_min"]), float(d["y_min"]), float(d["cell"])
+    g.nx, g.ny = int(d["nx"]), int(d["ny"])
+    g.sigma, g.trunc = float(d["sigma"]), float(d["trunc"])
+    return g
+
+
+def _seg_with_dirs(seg: DeviceSegments, dx, dy, dz) -> Segments:
+    s = seg.struct()
+    if dx is not None:
+        s.dx, s.dy, s.dz = dx.data_ptr(), dy.data_ptr(), dz.data_ptr()
+    return s
+
+
+def splat_forward(seg: DeviceSegments, atm: Atmosphere, lmin, lmax, seed, precision, offsets, mean0,
+                  grid: SplatGrid, totals=None, dirs=None):
+    """Splatted ground density (ny, nx): float64 (FP64) or float32 (FP32)
+    tensor. dirs = (dx, dy, dz) device float64 tensors replacing the
+    segments' directions."""
+    dt = torch.float64 if precision == FP64 else torch.float32
+    D = torch.empty((grid.ny, grid.nx), dtype=dt, device=offsets.device)
+    s = _seg_with_dirs(seg, *(dirs if dirs is not None else (None, None, None)))
+    _check(lib().photon_splat_forward(C.byref(s), C.byref(atm), float(lmin), float(lmax), int(seed),
+                                      int(precision), _ptr(offsets), _ptr(mean0), C.byref(grid), _ptr(D),
+                                      _ptr(totals), _stream()))
+    return D
+
+
+def splat_backward(seg: DeviceSegments, atm: Atmosphere, lmin, lmax, seed, precision, offsets, mean0,
+                   grid: SplatGrid, grad_density, dirs=None):
+    """(dL/dH per layer, dL/d(n0-1), dL/ddx, dL/ddy, dL/ddz) as float64 tensors."""
+    dev = offsets.device
+    dt = torch.float64 if precision == FP64 else torch.float32
+    gD = grad_density.to(dtype=dt).contiguous()
+    gH = torch.zeros(int(atm.n_layers), dtype=torch.float64, device=dev)
+    ge = torch.zeros(1, dtype=torch.float64, device=dev)
+    n = max(seg.n, 1)
+    gx, gy, gz = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+    s = _seg_with_dirs(seg, *(dirs if dirs is not None else (None, None, None)))
+    _check(lib().photon_splat_backward(C.byref(s), C.byref(atm), float(lmin), float(lmax), int(seed),
+                                       int(precision), _ptr(offsets), _ptr(mean0), C.byref(grid), _ptr(gD),
+                                       _ptr(gH), _ptr(ge), _ptr(gx), _ptr(gy), _ptr(gz), _stream()))
+    return gH, ge[0], gx[:seg.n], gy[:seg.n], gz[:seg.n]
+
+
+class SplatProblem:
+    """The frozen part of the differentiable form: segments on the device,
+    atmosphere layout, band, seed, precision, grid, and the counts' offsets
+    and means at the nominal parameters."""
+
+    def __init__(self, seg: DeviceSegments, atm_dict: dict, seed, precision, grid: dict, lmin=300.0, lmax=600.0):
+        self.seg = seg
+        self.atm_dict = dict(atm_dict)
+        self.seed, self.precision = int(seed), int(precision)
+        self.lmin, self.lmax = float(lmin), float(lmax)
+        self.grid = splat_grid(grid)
+        a0 = atmosphere(self.atm_dict)
+        em = emission_cherenkov(self.lmin, self.lmax)
+        self.counts, self.offsets = count(seg, a0, em, self.seed)
+        self.mean0 = means(seg, a0, em)
+
+    def atmosphere(self, H, eta0) -> Atmosphere:
+        d = dict(self.atm_dict)
+        d["scale_height"] = [float(v) for v in H]
+        d["n0_minus_1"] = float(eta0)
+        return atmosphere(d)
+
+
+class SplatDensity(torch.autograd.Function):
+    """D(H, n0 - 1, dx, dy, dz): splatted ground density of the frozen
+    problem; backward runs the adjoint kernel (photon_splat_backward)."""
+
+    @staticmethod
+    def forward(ctx, H, eta0, dx, dy, dz, problem: SplatProblem):
+        atm = problem.atmosphere(H.detach().cpu().tolist(), float(eta0.detach().cpu()))
+        dirs = tuple(t.detach().to(torch.float64).contiguous() for t in (dx, dy, dz))
+        D = splat_forward(problem.seg, atm, problem.lmin, problem.lmax, problem.seed, problem.precision,
+                          problem.offsets, problem.mean0, problem.grid, dirs=dirs)
+        ctx.problem, ctx.atm, ctx.dirs = problem, atm, dirs
+        ctx.h_meta = (H.dtype, H.device, eta0.dtype, eta0.device)
+        return D
+
+    @staticmethod
+    def backward(ctx, gD):
+        p = ctx.problem
+        gH, ge, gx, gy, gz = splat_backward(p.seg, ctx.atm, p.lmin, p.lmax, p.seed, p.precision, p.offsets,
+                                            p.mean0, p.grid, gD, dirs=ctx.dirs)
+        hd, hdev, ed, edev = ctx.h_meta
+        return (gH.to(dtype=hd, device=hdev), ge.to(dtype=ed, device=edev).reshape(()), gx, gy, gz, None)

@@ -147,3 +147,43 @@ def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(photon, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         photon.lib()
+
+
+def test_splat_validation_errors(ph):
+    """The differentiable form's entry points validate before any device work."""
+    L = ph.lib()
+    atm = _valid_atm(ph)
+    seg = _fake_segments(ph)
+
+    def grid(**kw):
+        g = ph.SplatGrid()
+        g.x_min, g.y_min, g.cell, g.nx, g.ny, g.sigma, g.trunc = -320.0, -320.0, 5.0, 128, 128, 5.0, 4.0
+        for k, v in kw.items():
+            setattr(g, k, v)
+        return g
+
+    def fwd(g, density=0x5000, mean0=0x4000, offsets=0x3000, prec=0):
+        return L.photon_splat_forward(C.byref(seg), C.byref(atm), 300.0, 600.0, 1, prec, offsets, mean0,
+                                      None if g is None else C.byref(g), density, None, None)
+
+    def bwd(g, grad=0x5000, gH=0x6000, ge=0x7000, gd=0x8000):
+        return L.photon_splat_backward(C.byref(seg), C.byref(atm), 300.0, 600.0, 1, 0, 0x3000, 0x4000,
+                                       C.byref(g), grad, gH, ge, gd, gd, gd, None)
+
+    assert fwd(None) == ph.EINVAL
+    for bad in (dict(nx=0), dict(ny=-1), dict(nx=4096, ny=4096), dict(cell=0.0), dict(sigma=0.0),
+                dict(trunc=0.0), dict(trunc=100.0), dict(x_min=float("nan"))):
+        assert fwd(grid(**bad)) == ph.EINVAL, bad
+    assert fwd(grid(), density=None) == ph.EINVAL
+    assert fwd(grid(), mean0=None) == ph.EINVAL
+    assert fwd(grid(), offsets=None) == ph.EINVAL
+    assert fwd(grid(), prec=3) == ph.EINVAL
+    assert bwd(grid(), grad=None) == ph.EINVAL
+    assert bwd(grid(), gH=None) == ph.EINVAL
+    assert bwd(grid(), gd=None) == ph.EINVAL
+    em = ph.emission_cherenkov()
+    assert L.photon_means(C.byref(seg), C.byref(atm), C.byref(em), None, None) == ph.EINVAL
+    if not torch.cuda.is_available():
+        assert fwd(grid()) == ph.ENODEV
+        assert bwd(grid()) == ph.ENODEV
+        assert L.photon_means(C.byref(seg), C.byref(atm), C.byref(em), 0x4000, None) == ph.ENODEV
