@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -131,6 +133,54 @@ def batched_showers(args):
                 tuning=[best.block, best.chunk, best.blocks_per_cu])
 
 
+def differentiable(args):
+    """The differentiable form at 1e6 segments: splatted ground density
+    (128 x 128 cells of 5 m, sigma 5 m) with counts frozen at the nominal
+    parameters, and its adjoint for L = sum (D - T)^2 with T the density at
+    perturbed parameters; FP32 bulk, FP64 beside it."""
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+
+    seg = W.differentiable()
+    a = W.default_atmosphere(absorption=True)
+    g = W.splat_grid_128()
+    d = ph.DeviceSegments(seg)
+    H1, e1, d1 = W.perturbed_parameters(a, seg, 77)
+    dirs1 = tuple(torch.as_tensor(np.ascontiguousarray(d1[:, k]), device="cuda") for k in range(3))
+    out = dict(workload="1e6 shower segments, splat 128 x 128 cells of 5 m, sigma 5 m, trunc 4 sigma; "
+                        "L = sum (D - T)^2, T at perturbed H, n0-1, directions")
+    steps = max(2, args.steps // 4)
+    for name, prec in (("fp32", ph.FP32), ("fp64", ph.FP64)):
+        p = ph.SplatProblem(d, a, 5, prec, g)
+        atm0 = ph.atmosphere(a)
+        T = ph.splat_forward(d, p.atmosphere(H1, e1), 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, dirs=dirs1)
+        D = ph.splat_forward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid)
+        G = (2.0 * (D - T)).contiguous()
+        ph.splat_backward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, G)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for _ in range(steps):
+            ph.splat_forward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid)
+        ev[1].record()
+        for _ in range(steps):
+            grads = ph.splat_backward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, G)
+        ev[2].record()
+        torch.cuda.synchronize()
+        total = int(p.offsets[-1].item())
+        fwd = ev[0].elapsed_time(ev[1]) / steps
+        bwd = ev[1].elapsed_time(ev[2]) / steps
+        out["segments"] = d.n
+        out["photons"] = total
+        out[name] = dict(forward_ms=fwd, backward_ms=bwd, forward_photons_per_s=total / (fwd * 1e-3),
+                         backward_photons_per_s=total / (bwd * 1e-3), steps=steps,
+                         loss=float(((D - T).double() ** 2).sum()),
+                         grad_scale_height=[float(v) for v in grads[0].cpu()], grad_n0_minus_1=float(grads[1]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +192,8 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 form (profiling runs)")
     ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True,
                     help="also time 64 showers of 1e3..1e6 segments in one graph-captured step")
+    ap.add_argument("--adjoint", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the differentiable form (splat forward and adjoint, 1e6 segments)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -239,6 +291,8 @@ def main():
     }
     if args.batched:
         out["batched"] = batched_showers(args)
+    if args.adjoint:
+        out["differentiable"] = differentiable(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seg, a, tel, seed)
     print(json.dumps(out))
