@@ -192,6 +192,9 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 form (profiling runs)")
     ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True,
                     help="also time 64 showers of 1e3..1e6 segments in one graph-captured step")
+    ap.add_argument("--tuning", default=None,
+                    help="block,chunk,blocks_per_cu of the fused kernel instead of the autotuner's choice "
+                         "(profiling runs)")
     ap.add_argument("--adjoint", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the differentiable form (splat forward and adjoint, 1e6 segments)")
     args = ap.parse_args()
@@ -238,7 +241,10 @@ def main():
     forms = (("fp32", ph.FP32),) if args.fp32_only else (("fp32", ph.FP32), ("fp64", ph.FP64))
     for name, prec in forms:
         # launch shape from the autotuner, then the whole step captured in a graph
-        best, _ = ph.autotune(d, atm, em, seed, prec, offsets, sink, TUNING_CANDIDATES, reps=3)
+        if args.tuning:
+            best = ph.tuning(*(int(v) for v in args.tuning.split(",")))
+        else:
+            best, _ = ph.autotune(d, atm, em, seed, prec, offsets, sink, TUNING_CANDIDATES, reps=3)
         plan = ph.Plan(d, atm, em, seed, prec, counts, offsets, sink, best)
         for _ in range(args.warmup):
             plan.launch()

@@ -341,6 +341,9 @@ __global__ __launch_bounds__(256) void k_gen(SegView seg, int64_t n_seg, AtmDev 
 // ------------------------------------------------------------- propagation --
 template <typename T>
 __global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, int64_t n_ph) {
+  __shared__ AtmLane s_lane;
+  atm_lane_fill(atm, &s_lane);
+  __syncthreads();
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_ph) return;
   Photon<T> p;
@@ -356,7 +359,7 @@ __global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, i
   p.path = b.path[q];
   p.status = b.status[q];
   p.uzd = (double)p.uz;
-  propagate<T>(atm, p);
+  propagate<T>(atm, s_lane, p);
   b.x[q] = p.x;
   b.y[q] = p.y;
   b.z[q] = p.z;
@@ -381,6 +384,33 @@ struct StatusCounter {
     for (int k = 0; k < PHOTON_N_STATUS; ++k) c[k] += (st == k) ? 1u : 0u;
   }
 };
+
+// Status totals of a wave counted with ballots: the counts are the same in
+// every lane, so every lane of the wave calls add at the same point (st < 0
+// counts nothing) and lane 0 holds the wave's totals.
+struct WaveStatus {
+  unsigned long long c[PHOTON_N_STATUS];
+  __device__ void clear() {
+#pragma unroll
+    for (int k = 0; k < PHOTON_N_STATUS; ++k) c[k] = 0ull;
+  }
+  __device__ void add(int st) {
+#pragma unroll
+    for (int k = 0; k < PHOTON_N_STATUS; ++k) c[k] += (unsigned long long)__popcll(__ballot(st == k));
+  }
+};
+
+__device__ void flush_wave_status(const WaveStatus& w, unsigned long long* totals) {
+  __shared__ unsigned long long s_tot[PHOTON_N_STATUS];
+  if (threadIdx.x < PHOTON_N_STATUS) s_tot[threadIdx.x] = 0;
+  __syncthreads();
+  if (__lane_id() == 0)
+#pragma unroll
+    for (int k = 0; k < PHOTON_N_STATUS; ++k)
+      if (w.c[k]) atomicAdd(&s_tot[k], w.c[k]);
+  __syncthreads();
+  if (threadIdx.x < PHOTON_N_STATUS && s_tot[threadIdx.x]) atomicAdd(&totals[threadIdx.x], s_tot[threadIdx.x]);
+}
 
 // Block-wide reduction of per-lane status counters into global totals.
 __device__ void flush_status(StatusCounter& sc, unsigned long long* totals) {
@@ -447,8 +477,8 @@ __device__ __forceinline__ void flush_hits(HitStage* st, const photon_hits& h) {
 // so that the other sinks' kernels carry none of its code).
 template <typename T, bool SPLAT = false>
 __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], double n_obs, Photon<T>& p,
-                                           uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q = 0,
-                                           HitStage* stage = nullptr, float* splat_lds = nullptr) {
+                                           uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q,
+                                           HitStage* stage, float* splat_lds, const uint32_t* cand) {
   int st = active ? p.status : -1;
   if constexpr (SPLAT) {
     if (active && st == PHOTON_LANDED) {
@@ -484,7 +514,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
         const double fx = ((double)p.x - sk.cand_x0) * sk.cand_inv_cell;
         const double fy = ((double)p.y - sk.cand_y0) * sk.cand_inv_cell;
         const bool in = fx >= 0.0 && fy >= 0.0 && fx < (double)kCandCells && fy < (double)kCandCells;
-        mask = in ? sk.cand_mask[(int)fy * kCandCells + (int)fx] : 0u;
+        mask = in ? cand[(int)fy * kCandCells + (int)fx] : 0u;
       } else {
         mask = sk.n_tel >= 32 ? 0xffffffffu : ((1u << sk.n_tel) - 1u);
       }
@@ -554,7 +584,9 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
 template <typename T>
 __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, SinkDev sk, double n_obs) {
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  __shared__ uint32_t s_cand[kCandCells * kCandCells];
   if (threadIdx.x < PHOTON_MAX_TELESCOPES * 4) (&s_tel[0][0])[threadIdx.x] = (&sk.tel[0][0])[threadIdx.x];
+  if (threadIdx.x < kCandCells * kCandCells) s_cand[threadIdx.x] = sk.cand_mask[threadIdx.x];
   __syncthreads();
   StatusCounter sc;
   sc.clear();
@@ -576,7 +608,7 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
     s = b.seg[q];
     j = b.j[q];
   }
-  const int st = sink_photon<T>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q);
+  const int st = sink_photon<T>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr, s_cand);
   if (active) sc.add(st);
   if (sk.totals) flush_status(sc, sk.totals);
 }
@@ -628,6 +660,8 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
   __shared__ unsigned int s_dcount;
   __shared__ HitStage s_hits;
   __shared__ T s_wsc[SPLAT ? kWindow : 1];  // SPLAT: per-segment weight factors mu/mu0
+  __shared__ AtmLane s_lane;
+  __shared__ uint32_t s_cand[kCandCells * kCandCells];
   extern __shared__ float s_splat[];         // dynamic: the float density of the block (SPLAT)
   constexpr bool kDefer = sizeof(T) == 4;
   const bool stage_hits = !SPLAT && A.sk.kind == PHOTON_SINK_TELESCOPES;
@@ -646,11 +680,13 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
     s_lines[tid] = (T)A.g.line_nm[tid];
   }
   for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+  for (int k = tid; k < kCandCells * kCandCells; k += BS) s_cand[k] = A.sk.cand_mask[k];
+  atm_lane_fill(A.atm, &s_lane);
   const bool cher = A.g.kind == PHOTON_CHERENKOV;
   const int64_t n_seg = A.n_seg;
   const uint64_t* __restrict__ offsets = A.offsets;
-  StatusCounter sc;
-  sc.clear();
+  WaveStatus ws;
+  ws.clear();
   // Slots at or beyond offsets[n_seg] belong to no segment: counted INVALID.
   const uint64_t total = offsets[n_seg];
   const int64_t n_ph = A.n_ph < 0 ? (int64_t)total : A.n_ph;
@@ -663,12 +699,12 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
     if (c0 >= (uint64_t)n_ph) break;
     const uint64_t c1 = min(c0 + (uint64_t)A.chunk, (uint64_t)n_ph);
     const uint64_t v1 = min(c1, lim);  // valid slots of this chunk: [c0, v1)
-    for (uint64_t q = max(c0, v1) + tid; q < c1; q += BS) sc.add(PHOTON_INVALID);
+    const int wave = tid / kWaveSize;
+    if (wave == 0) ws.c[PHOTON_INVALID] += c1 - max(c0, v1);
     if (c0 >= v1) {
       __syncthreads();
       continue;
     }
-    const int wave = tid / kWaveSize;
     if (wave == 0) {
       const int64_t sl = wave_upper_index(offsets, n_seg, c0);
       if (lane_id() == 0) s_lo = sl;
@@ -692,61 +728,65 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
       if (tid == 0) s_off[W] = offsets[lo + W];
     }
     __syncthreads();
-    for (uint64_t q = c0 + tid; q < v1; q += BS) {
-      SegConst<T> c;
-      uint64_t off_s;
-      int64_t s;
-      T wsc = (T)1;
-      if (win) {
-        int a = 0, b = (int)W;  // s_off[a] <= q < s_off[b]
-        while (b - a > 1) {
-          const int mid = (a + b) >> 1;
-          if (s_off[mid] <= q) a = mid; else b = mid;
-        }
-        c = s_seg[a];
-        if constexpr (SPLAT) wsc = s_wsc[a];
-        off_s = s_off[a];
-        s = lo + a;
-      } else {
-        s = lane_upper_index(offsets, n_seg, q);
-        seg_const<T>(A.seg, s, A.atm, cher, c);
-        if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
-        off_s = offsets[s];
-      }
-      const uint32_t j = (uint32_t)(q - off_s);
-      Photon<T> p;
-      generate<T>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
-      propagate<T, kDefer>(A.atm, p);
-      if constexpr (SPLAT) p.w *= wsc;
+    // every lane runs the same number of iterations (the status ballots)
+    for (uint64_t qb = c0; qb < v1; qb += BS) {
+      const uint64_t q = qb + tid;
+      int st_out = -1;
       bool forced = false;
-      if (kDefer) {
-        const bool defer = p.status == kDeferred;
-        const unsigned long long m = __ballot(defer);
-        if (m) {
-          // the block's own queue: one LDS atomic per wave
-          const int leader = __ffsll((long long)m) - 1;
-          unsigned int base = 0;
-          if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
-          base = __shfl(base, leader, kWaveSize);
-          if (defer) {
-            const uint64_t slot = (uint64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
-            if (slot < (uint64_t)A.defer_cap) {
-              A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
-            } else {
-              // queue full: this ray is evaluated in float after all
-              p.status = PHOTON_LANDED;
-              propagate<T, false, true>(A.atm, p);
-              forced = true;
+      if (q < v1) {
+        SegConst<T> c;
+        uint64_t off_s;
+        int64_t s;
+        T wsc = (T)1;
+        if (win) {
+          int a = 0, b = (int)W;  // s_off[a] <= q < s_off[b]
+          while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            if (s_off[mid] <= q) a = mid; else b = mid;
+          }
+          c = s_seg[a];
+          if constexpr (SPLAT) wsc = s_wsc[a];
+          off_s = s_off[a];
+          s = lo + a;
+        } else {
+          s = lane_upper_index(offsets, n_seg, q);
+          seg_const<T>(A.seg, s, A.atm, cher, c);
+          if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
+          off_s = offsets[s];
+        }
+        const uint32_t j = (uint32_t)(q - off_s);
+        Photon<T> p;
+        generate<T>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
+        propagate<T, kDefer>(A.atm, s_lane, p);
+        if constexpr (SPLAT) p.w *= wsc;
+        if (kDefer) {
+          const bool defer = p.status == kDeferred;
+          const unsigned long long m = __ballot(defer);
+          if (m) {
+            // the block's own queue: one LDS atomic per wave
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned int base = 0;
+            if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
+            base = __shfl(base, leader, kWaveSize);
+            if (defer) {
+              const uint64_t slot = (uint64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+              if (slot < (uint64_t)A.defer_cap) {
+                A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
+              } else {
+                // queue full: this ray is evaluated in float after all
+                p.status = PHOTON_LANDED;
+                propagate<T, false, true>(A.atm, s_lane, p);
+                forced = true;
+              }
             }
           }
         }
+        if (!kDefer || p.status != kDeferred)
+          st_out = sink_photon<T, SPLAT>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
+                                         stage_hits ? &s_hits : nullptr, splat_lds, s_cand);
       }
-      if (!kDefer || p.status != kDeferred) {
-        const int st = sink_photon<T, SPLAT>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
-                                             stage_hits ? &s_hits : nullptr, splat_lds);
-        sc.add(st);
-        if (forced) sc.add(PHOTON_HORIZON_FLOAT);
-      }
+      ws.add(st_out);
+      if (kDefer) ws.c[PHOTON_HORIZON_FLOAT] += (unsigned long long)__popcll(__ballot(forced));
     }
     if (stage_hits) flush_hits(&s_hits, A.sk.hits);
     __syncthreads();
@@ -763,7 +803,7 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
       if (v != 0.0f) atomicAdd(&D[k], v);
     }
   }
-  if (A.sk.totals) flush_status(sc, A.sk.totals);
+  if (A.sk.totals) flush_wave_status(ws, A.sk.totals);
 }
 
 // Double pass over the near-horizon rays queued by the float kernel: each is
@@ -774,12 +814,16 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ double s_lines[PHOTON_MAX_LINES];
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  __shared__ AtmLane s_lane;
+  __shared__ uint32_t s_cand[kCandCells * kCandCells];
   const int tid = threadIdx.x;
   if (tid < PHOTON_MAX_LINES) {
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = A.g.line_nm[tid];
   }
   for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+  for (int k = tid; k < kCandCells * kCandCells; k += BS) s_cand[k] = A.sk.cand_mask[k];
+  atm_lane_fill(A.atm, &s_lane);
   __syncthreads();
   const bool cher = A.g.kind == PHOTON_CHERENKOV;
   StatusCounter sc;
@@ -795,7 +839,7 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     seg_const<double>(A.seg, s, A.atm, cher, c);
     Photon<double> p;
     generate<double>(c, e.y, A.g, A.k0, A.k1, s_thr, s_lines, p);
-    propagate<double>(A.atm, p);
+    propagate<double>(A.atm, s_lane, p);
     const bool splat = A.sk.kind == kSinkSplat;
     if (splat) p.w *= splat_wscale<double>(A, s);
     // collected in the run's precision (float)
@@ -811,8 +855,10 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     pf.t = p.t;
     pf.path = p.path;
     pf.status = p.status;
-    const int st = splat ? sink_photon<float, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true)
-                         : sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y);
+    const int st = splat ? sink_photon<float, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr,
+                                                    nullptr, s_cand)
+                         : sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y,
+                                              nullptr, nullptr, s_cand);
     sc.add(st);
   }
   if (A.sk.totals) flush_status(sc, A.sk.totals);
@@ -879,7 +925,9 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ double s_red[BS / kWaveSize][kAdjWords];
+  __shared__ AtmLane s_lane;
   const int tid = threadIdx.x;
+  atm_lane_fill(A.atm, &s_lane);
   const int64_t n_seg = A.n_seg;
   const uint64_t* __restrict__ offsets = A.offsets;
   const uint64_t total = offsets[n_seg];
@@ -942,8 +990,8 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
           sg.mu0 = A.mu0[s];
           sg.idx = seg_idx(A.seg, s);
           sg.shower = seg_shower(A.seg, s);
-          adjoint_photon<T, T>(A.atm, sg, (uint32_t)(q - off_s), A.k0, A.k1, A.K, A.inv_l1, A.inv_dl, A.sg, G, acc,
-                               dd);
+          adjoint_photon<T, T>(A.atm, s_lane, sg, (uint32_t)(q - off_s), A.k0, A.k1, A.K, A.inv_l1, A.inv_dl, A.sg,
+                               G, acc, dd);
         }
       }
       seg_reduce_add(key, dd[0], dd[1], dd[2], A.gdx, A.gdy, A.gdz);

@@ -296,9 +296,9 @@ __device__ __forceinline__ void piece_d(T rho_a, T em, double dh, T H, bool homo
 // below threshold). The float form hands rays within about 6 degrees of the
 // horizontal to the double form.
 template <typename T, typename Gt>
-__device__ bool adjoint_photon(const AtmDev& a, const SegRaw& sg, uint32_t j, uint32_t k0, uint32_t k1, double K,
-                               double inv_l1, double inv_dl, const SplatGeom& g, const Gt* G, AdjSums& acc,
-                               double dd[3]) {
+__device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& sg, uint32_t j, uint32_t k0,
+                               uint32_t k1, double K, double inv_l1, double inv_dl, const SplatGeom& g, const Gt* G,
+                               AdjSums& acc, double dd[3]) {
   using F = Fm<T>;
   dd[0] = dd[1] = dd[2] = 0.0;
   // segment (double): unit direction, index at the midpoint, cone, bisector
@@ -306,7 +306,7 @@ __device__ bool adjoint_photon(const AtmDev& a, const SegRaw& sg, uint32_t j, ui
   const double vx = sg.dx / dn, vy = sg.dy / dn, vz = sg.dz / dn;
   const double zc = sg.z0 + (0.5 * sg.len) * vz;
   const int lc = layer_of(a, zc);
-  const double rho_c = a.rb[lc] * exp(-(zc - a.hb[lc]) * a.invH[lc]);
+  const double rho_c = L.rb[lc] * exp(-(zc - L.hb[lc]) * L.invH[lc]);
   const double ns = 1.0 + a.eta0 * rho_c;
   const double bn = sg.beta * ns;
   const double cc = 1.0 / bn;
@@ -335,7 +335,7 @@ __device__ bool adjoint_photon(const AtmDev& a, const SegRaw& sg, uint32_t j, ui
   if (!(uz < (T)0) || !(ze >= a.hobs)) return false;
   const double xe = sg.x0 + (double)(s * (T)vx), ye = sg.y0 + (double)(s * (T)vy);
   const T lambda = F::rcp((T)inv_l1 - u2 * (T)inv_dl);
-  const T kabs = abs_coeff<T>(a, lambda);
+  const T kabs = abs_coeff<T>(a, L, lambda);
   const T inv_un = F::rcp(F::sqrt_(ux * ux + uy * uy + uz * uz));
   ux *= inv_un;
   uy *= inv_un;
@@ -345,11 +345,11 @@ __device__ bool adjoint_photon(const AtmDev& a, const SegRaw& sg, uint32_t j, ui
   const double ced = -(double)uz;
   const double sed = sqrt((1.0 - ced) * (1.0 + ced));
   const int le = layer_of(a, ze);
-  const double bot_e = (le == a.l_obs) ? a.hobs : a.hb[le];
-  const double rho_bot_e = (le == a.l_obs) ? a.rho_obs : a.rb[le];
+  const double bot_e = (le == a.l_obs) ? a.hobs : L.hb[le];
+  const double rho_bot_e = (le == a.l_obs) ? a.rho_obs : L.rb[le];
   const bool homog_e = (a.homog_mask >> le) & 1;
   const T eta0 = (T)a.eta0;
-  const T em_e = homog_e ? (T)0 : F::expm1_((T)(-(ze - bot_e) * a.invH[le]));
+  const T em_e = homog_e ? (T)0 : F::expm1_((T)(-(ze - bot_e) * L.invH[le]));
   const T rho_e = (T)rho_bot_e * ((T)1 + em_e);
   const T eps_e = eta0 * rho_e;
   const T ne = (T)1 + eps_e;
@@ -357,7 +357,7 @@ __device__ bool adjoint_photon(const AtmDev& a, const SegRaw& sg, uint32_t j, ui
   const double C2d = (ced * ced / (1.0 + sed) - epsd * sed) * (1.0 + (1.0 + epsd) * sed);
   if constexpr (sizeof(T) == 4) {
     if (!(C2d > (double)kNearHorizonC2))
-      return adjoint_photon<double, Gt>(a, sg, j, k0, k1, K, inv_l1, inv_dl, g, G, acc, dd);
+      return adjoint_photon<double, Gt>(a, L, sg, j, k0, k1, K, inv_l1, inv_dl, g, G, acc, dd);
   }
   const T C2 = (T)C2d;
   const T S = ne * (T)sed;
@@ -459,8 +459,8 @@ __device__ bool adjoint_photon(const AtmDev& a, const SegRaw& sg, uint32_t j, ui
   {
     const double t = (double)(rhoe_b * rho_e);
     add_at(acc.lnrb, le, t);
-    add_at(acc.H, le, t * (ze - a.hb[le]) * a.invH[le] * a.invH[le]);
-    ze_b -= t * a.invH[le];
+    add_at(acc.H, le, t * (ze - L.hb[le]) * L.invH[le] * L.invH[le]);
+    ze_b -= t * L.invH[le];
   }
   // emission point x_e = x0 + s v (v the unit track direction)
   const double sd = (double)s;
@@ -485,8 +485,8 @@ __device__ bool adjoint_photon(const AtmDev& a, const SegRaw& sg, uint32_t j, ui
   acc.eta += nsb * rho_c;
   const double t = nsb * a.eta0 * rho_c;
   add_at(acc.lnrb, lc, t);
-  add_at(acc.H, lc, t * (zc - a.hb[lc]) * a.invH[lc] * a.invH[lc]);
-  vzb += 0.5 * sg.len * (-t * a.invH[lc]);
+  add_at(acc.H, lc, t * (zc - L.hb[lc]) * L.invH[lc] * L.invH[lc]);
+  vzb += 0.5 * sg.len * (-t * L.invH[lc]);
   // v = d/|d|
   const double vdot = vx * vxb + vy * vyb + vz * vzb;
   dd[0] = (vxb - vx * vdot) / dn;

@@ -421,40 +421,62 @@ __device__ __forceinline__ void piece_integrals(T rho_a, T em, T dh, T H, bool h
   o.col = -H * drho * two_e * inv_rs;
 }
 
+// Tables that photons index by their own layer or wavelength bin, mirrored
+// into LDS by every kernel that propagates (lane-indexed reads of a kernel
+// argument would be vector memory loads). abs_s[i] is the slope of the
+// absorption coefficient on [abs_l[i], abs_l[i+1]].
+struct AtmLane {
+  double hb[PHOTON_MAX_LAYERS], rb[PHOTON_MAX_LAYERS], invH[PHOTON_MAX_LAYERS];
+  double abs_l[PHOTON_MAX_ABS], abs_k[PHOTON_MAX_ABS], abs_s[PHOTON_MAX_ABS];
+};
+
+// Block-cooperative copy; the caller synchronises before use.
+__device__ __forceinline__ void atm_lane_fill(const AtmDev& a, AtmLane* L) {
+  for (int i = threadIdx.x; i < PHOTON_MAX_LAYERS; i += blockDim.x) {
+    L->hb[i] = a.hb[i];
+    L->rb[i] = a.rb[i];
+    L->invH[i] = a.invH[i];
+  }
+  for (int i = threadIdx.x; i < PHOTON_MAX_ABS; i += blockDim.x) {
+    L->abs_l[i] = a.abs_l[i];
+    L->abs_k[i] = a.abs_k[i];
+    L->abs_s[i] = (i + 1 < a.n_abs) ? (a.abs_k[i + 1] - a.abs_k[i]) / (a.abs_l[i + 1] - a.abs_l[i]) : 0.0;
+  }
+}
+
+// Absorption coefficient at rho/rho0 = 1: piecewise linear in lambda,
+// clamped to the end values outside the table.
 template <typename T>
-__device__ __forceinline__ T abs_coeff(const AtmDev& a, T lambda) {
+__device__ __forceinline__ T abs_coeff(const AtmDev& a, const AtmLane& L, T lambda) {
   if (a.n_abs <= 0) return (T)0;
   const double l = (double)lambda;
   if (l <= a.abs_l[0]) return (T)a.abs_k[0];
   if (l >= a.abs_l[a.n_abs - 1]) return (T)a.abs_k[a.n_abs - 1];
-  int lo, hi;
+  int lo;
   if (a.abs_uniform) {
     lo = (int)((l - a.abs_l0) * a.abs_inv_step);
     lo = lo < 0 ? 0 : (lo > a.n_abs - 2 ? a.n_abs - 2 : lo);
     // guard against the last bit of the index computation
-    if (l < a.abs_l[lo]) --lo;
-    else if (!(l < a.abs_l[lo + 1])) ++lo;
-    hi = lo + 1;
+    if (l < L.abs_l[lo]) --lo;
+    else if (!(l < L.abs_l[lo + 1])) ++lo;
   } else {
     lo = 0;
-    hi = a.n_abs - 1;  // abs_l[lo] <= l < abs_l[hi]
+    int hi = a.n_abs - 1;  // abs_l[lo] <= l < abs_l[hi]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (a.abs_l[mid] <= l) lo = mid; else hi = mid;
+      if (L.abs_l[mid] <= l) lo = mid; else hi = mid;
     }
   }
-  const double f = (l - a.abs_l[lo]) / (a.abs_l[hi] - a.abs_l[lo]);
-  return (T)(a.abs_k[lo] + f * (a.abs_k[hi] - a.abs_k[lo]));
+  return (T)(L.abs_k[lo] + (l - L.abs_l[lo]) * L.abs_s[lo]);
 }
 
-// Double square root and reciprocal square root for the float path: a
-// float seed refined by Newton steps in double (relative error ~1e-15), at a
-// fraction of the cost of the correctly rounded double routines.
+// Double square root and reciprocal square root for the float path: the
+// float hardware seed (about 1 ulp) refined by one Newton step in double
+// (relative error below 1e-13; the square root gets one more correction),
+// at a fraction of the cost of the correctly rounded double routines.
 __device__ __forceinline__ double rsqrt_refined(double x) {
-  double r = (double)__builtin_amdgcn_rsqf((float)x);
-  r = r * (1.5 - 0.5 * x * r * r);
-  r = r * (1.5 - 0.5 * x * r * r);
-  return r;
+  const double r = (double)__builtin_amdgcn_rsqf((float)x);
+  return r * (1.5 - 0.5 * x * r * r);
 }
 __device__ __forceinline__ double sqrt_refined(double x) {
   if (!(x > 0.0)) return 0.0;
@@ -486,9 +508,12 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C
   ne = (C)1 + eps_e;
   const C se = (C)sed;
   const C S = ne * se;
-  // 1 - S = ce^2/(1 + se) - eps_e se, free of cancellation for S well below 1
+  // C^2 = 1 - S^2. Double form: 1 - S = ce^2/(1 + se) - eps_e se, free of
+  // cancellation up to the horizon. Float form (rays with C^2 > 0.01 only):
+  // ce^2 - eps_e (2 + eps_e) se^2, whose terms differ by a factor of 16 or more.
   const double epsd = (double)eps_e;
-  const double C2d = (ced * ced / (1.0 + sed) - epsd * sed) * (1.0 + (1.0 + epsd) * sed);
+  const double C2d = sizeof(C) == 8 ? (ced * ced / (1.0 + sed) - epsd * sed) * (1.0 + (1.0 + epsd) * sed)
+                                    : ced * ced - epsd * (2.0 + epsd) * ((1.0 - ced) * (1.0 + ced));
   const C C2 = (C)C2d;
   const C Cc = C2 > (C)0 ? F::sqrt_(C2) : (C)0;
   const C invC = C2 > (C)0 ? F::rcp(Cc) : (C)0;
@@ -502,6 +527,7 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C
   opt = 0.0;
   // the layer index runs wave-uniformly (lanes above their emission layer
   // skip the iteration), so the layer constants stay in scalar registers
+#pragma unroll 1
   for (int l = a.nl - 1; l >= a.l_obs; --l) {
     if (l > le) continue;
     const double top = (l == le) ? ze : a.hb[l + 1];
@@ -528,7 +554,7 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C
 // DEFER (float only): a near-horizon ray is only marked kDeferred.
 // FORCE_FLOAT (float only): every ray is evaluated in float.
 template <typename T, bool DEFER = false, bool FORCE_FLOAT = false>
-__device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
+__device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Photon<T>& p) {
   using F = Fm<T>;
   if (p.status != PHOTON_LANDED) return;
   if (!(p.uz < (T)0)) {
@@ -549,8 +575,9 @@ __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
   const double sed = sizeof(T) == 8 ? sqrt((1.0 - ced) * (1.0 + ced)) : sqrt_refined((1.0 - ced) * (1.0 + ced));
   const T ce = (T)ced, se = (T)sed;
   const int le = layer_of(a, ze);
-  const double bot = (le == a.l_obs) ? a.hobs : a.hb[le];
-  const double rho_bot = (le == a.l_obs) ? a.rho_obs : a.rb[le];
+  const double bot = (le == a.l_obs) ? a.hobs : L.hb[le];
+  const double rho_bot = (le == a.l_obs) ? a.rho_obs : L.rb[le];
+  const double invH_e = L.invH[le];
   const bool homog_e = (a.homog_mask >> le) & 1;
 
   T col, ne, em_out;
@@ -558,7 +585,7 @@ __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
   bool done = false;
   if (sizeof(T) == 4) {
     // near the horizon the float closed forms lose digits: use double there
-    const T em_e = homog_e ? (T)0 : F::expm1_((T)(-(ze - bot) * a.invH[le]));
+    const T em_e = homog_e ? (T)0 : F::expm1_((T)(-(ze - bot) * invH_e));
     const T rho_e = (T)rho_bot * ((T)1 + em_e);
     const T eps_e = (T)a.eta0 * rho_e;
     const T S = ((T)1 + eps_e) * se;
@@ -574,7 +601,7 @@ __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
   }
   if (!done) {
     double cold, ned;
-    const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * a.invH[le]);
+    const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * invH_e);
     const double rho_e = rho_bot * (1.0 + em_e);
     ray_pieces<double>(a, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, cold, ned);
     col = (T)cold;
@@ -587,7 +614,7 @@ __device__ __forceinline__ void propagate(const AtmDev& a, Photon<T>& p) {
   p.z = a.hobs;
   p.t = p.t + opt * (1.0 / kC);
   p.path = pth;
-  const T tau = abs_coeff<T>(a, p.lambda) * col;
+  const T tau = abs_coeff<T>(a, L, p.lambda) * col;
   p.w = F::exp_(-tau);
   // arrival direction by Snell: horizontal part scaled by q = ne/n_obs and
   // u_z^2 = ce^2 + se^2 (1 - q)(1 + q), with 1 - q = eta0 (rho_obs - rho_e)/n_obs
