@@ -43,7 +43,7 @@ TUNING_CANDIDATES = [(256, 4096, 0), (256, 8192, 0), (256, 16384, 0), (512, 8192
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("photon.hip", "photon_device.hpp"):
+    for f in ("photon.hip", "photon_device.hpp", "photon_adjoint.hpp"):
         with open(os.path.join(ROOT, "paper_2309_15861_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -279,7 +279,7 @@ def main():
     achieved = SLOTS_PER_PHOTON["fp32"] * total / (r32["fused_ms"] * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=achieved / PEAK_SLOTS, traffic=traffic_per_launch(),
-                    kernel=f"k_fused<float,{r32['tuning'][0]}>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
+                    kernel=f"k_fused<float,{r32['tuning'][0]},false>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
                     fused_ms=r32["fused_ms"], tuning=r32["tuning"])
     r64 = results.get("fp64", r32)
     out = {
