@@ -340,10 +340,14 @@ int photon_means(const photon_segments* seg, const photon_atmosphere* atm,
    device, ny*nx values of the precision's type (double for PHOTON_FP64,
    float for PHOTON_FP32), overwritten. status_totals: optional device
    u64[PHOTON_N_STATUS]; landed photons with no cell in reach count as
-   OFFGRID. The FP32 form accumulates each block's density in LDS when it
-   has at most 16384 cells. Summation order varies between runs (atomic
-   adds). One call at a time per device. Errors: EINVAL (NULL pointers,
-   band, atmosphere, precision, grid). */
+   OFFGRID. Cells sum w exp(-d^2/(2 sigma^2)) in 64-bit fixed point (units
+   of 2^-32 of weight) before the normalisation, so the density does not
+   depend on the order of the additions (a cell overflows only beyond 2^32
+   in weight units); each block accumulates the whole grid in LDS when it
+   fits (16384 cells on gfx950). The library keeps a per-device accumulator
+   of 8 bytes per cell, grown on the first call with a larger grid. One call
+   at a time per device. Errors: EINVAL (NULL pointers, band, atmosphere,
+   precision, grid). */
 int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* atm,
                          double lambda_min_nm, double lambda_max_nm, uint64_t seed,
                          int32_t precision, const uint64_t* offsets, const double* mean0,

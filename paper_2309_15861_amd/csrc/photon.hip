@@ -102,10 +102,11 @@ struct SinkDev {
   double *pz, *pt, *ppath;
   uint32_t *pseg, *pj;
   int32_t* pstatus;
-  // SPLAT (differentiable form): density of the run's precision, frozen
-  // nominal means; splat_lds: accumulate in LDS first (float form)
+  // SPLAT (differentiable form): fixed-point accumulator of the whole grid
+  // (global), frozen nominal means; splat_lds: each block accumulates in LDS
+  // first and adds its grid to acc once
   SplatGeom sg;
-  void* density;
+  unsigned long long* splat_acc;
   const double* mu0;
   int32_t splat_lds;
 };
@@ -470,6 +471,17 @@ __device__ __forceinline__ void flush_hits(HitStage* st, const photon_hits& h) {
   if (threadIdx.x == 0) st->n = 0u;
 }
 
+// LDS of the hit stage; the splat variant has none (its LDS holds the grid).
+template <bool SPLAT>
+struct HitStageLds {
+  HitStage st;
+  __device__ HitStage* get() { return &st; }
+};
+template <>
+struct HitStageLds<true> {
+  __device__ HitStage* get() { return nullptr; }
+};
+
 // Applies the sink to one propagated photon (in the lanes that hold one);
 // returns the final status. Hit records are compacted per wave: one atomic
 // per wave reserves the slots, lanes write at their rank among the hits.
@@ -478,16 +490,13 @@ __device__ __forceinline__ void flush_hits(HitStage* st, const photon_hits& h) {
 template <typename T, bool SPLAT = false>
 __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], double n_obs, Photon<T>& p,
                                            uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q,
-                                           HitStage* stage, float* splat_lds, const uint32_t* cand) {
+                                           HitStage* stage, unsigned long long* splat_lds,
+                                           const uint32_t* cand) {
   int st = active ? p.status : -1;
   if constexpr (SPLAT) {
     if (active && st == PHOTON_LANDED) {
-      bool in;
-      if (sizeof(T) == 4 && splat_lds)
-        in = splat_add<T, float>(sk.sg, (double)p.x, (double)p.y, p.w, splat_lds);
-      else
-        in = splat_add<T, T>(sk.sg, (double)p.x, (double)p.y, p.w, (T*)sk.density);
-      if (!in) st = PHOTON_OFFGRID;
+      if (!splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, splat_lds ? splat_lds : sk.splat_acc))
+        st = PHOTON_OFFGRID;
     }
   } else if (sk.kind == PHOTON_SINK_PLANE) {
     if (active && slot_q < (uint64_t)sk.plane_capacity) {
@@ -650,37 +659,41 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // horizon are appended to a queue for the double pass instead.
 template <typename T, int BS, bool SPLAT = false>
 __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
-  __shared__ SegConst<T> s_seg[kWindow];
-  __shared__ uint64_t s_off[kWindow + 1];
+  // the double splat keeps a smaller window so that the whole grid fits in LDS beside it
+  constexpr int kWin = (SPLAT && sizeof(T) == 8) ? kWindow / 2 : kWindow;
+  __shared__ SegConst<T> s_seg[kWin];
+  __shared__ uint64_t s_off[kWin + 1];
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ T s_lines[PHOTON_MAX_LINES];
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ unsigned int s_dcount;
-  __shared__ HitStage s_hits;
-  __shared__ T s_wsc[SPLAT ? kWindow : 1];  // SPLAT: per-segment weight factors mu/mu0
+  __shared__ HitStageLds<SPLAT> s_hs;
+  __shared__ T s_wsc[SPLAT ? kWin : 1];  // SPLAT: per-segment weight factors mu/mu0
   __shared__ AtmLane s_lane;
   __shared__ uint32_t s_cand[kCandCells * kCandCells];
-  extern __shared__ float s_splat[];         // dynamic: the float density of the block (SPLAT)
+  extern __shared__ unsigned long long s_splat[];  // dynamic: the block's fixed-point grid (SPLAT)
   constexpr bool kDefer = sizeof(T) == 4;
   const bool stage_hits = !SPLAT && A.sk.kind == PHOTON_SINK_TELESCOPES;
-  float* splat_lds = (SPLAT && A.sk.splat_lds) ? s_splat : nullptr;
+  unsigned long long* splat_lds = (SPLAT && A.sk.splat_lds) ? s_splat : nullptr;
   const int n_cells = A.sk.sg.nx * A.sk.sg.ny;
 
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_dcount = 0u;
-    s_hits.n = 0u;
+    if constexpr (!SPLAT) s_hs.get()->n = 0u;
   }
   if (splat_lds)
-    for (int k = tid; k < n_cells; k += BS) splat_lds[k] = 0.0f;
+    for (int k = tid; k < n_cells; k += BS) splat_lds[k] = 0ull;
   if (tid < PHOTON_MAX_LINES) {
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = (T)A.g.line_nm[tid];
   }
-  for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
-  for (int k = tid; k < kCandCells * kCandCells; k += BS) s_cand[k] = A.sk.cand_mask[k];
+  if constexpr (!SPLAT) {
+    for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+    for (int k = tid; k < kCandCells * kCandCells; k += BS) s_cand[k] = A.sk.cand_mask[k];
+  }
   atm_lane_fill(A.atm, &s_lane);
   const bool cher = A.g.kind == PHOTON_CHERENKOV;
   const int64_t n_seg = A.n_seg;
@@ -718,7 +731,7 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
     // clamps keep every index in bounds for any offsets array
     const int64_t lo = min(s_lo, n_seg - 1);
     const int64_t W = min(s_hi, n_seg - 1) - lo + 1;
-    const bool win = W >= 1 && W <= kWindow;
+    const bool win = W >= 1 && W <= kWin;
     if (win) {
       for (int t = tid; t < W; t += BS) {
         seg_const<T>(A.seg, lo + t, A.atm, cher, s_seg[t]);
@@ -783,12 +796,14 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
         }
         if (!kDefer || p.status != kDeferred)
           st_out = sink_photon<T, SPLAT>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
-                                         stage_hits ? &s_hits : nullptr, splat_lds, s_cand);
+                                         stage_hits ? s_hs.get() : nullptr, splat_lds, s_cand);
       }
       ws.add(st_out);
       if (kDefer) ws.c[PHOTON_HORIZON_FLOAT] += (unsigned long long)__popcll(__ballot(forced));
     }
-    if (stage_hits) flush_hits(&s_hits, A.sk.hits);
+    if constexpr (!SPLAT) {
+      if (stage_hits) flush_hits(s_hs.get(), A.sk.hits);
+    }
     __syncthreads();
   }
   if (kDefer && tid == 0) {
@@ -796,11 +811,10 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
     A.defer_counts[blockIdx.x] = nd < (uint64_t)A.defer_cap ? nd : (uint64_t)A.defer_cap;
   }
   if (splat_lds) {
-    // the block's density into the output (the loop above ends with a barrier)
-    float* D = (float*)A.sk.density;
+    // the block's grid into the global accumulator (the loop above ends with a barrier)
     for (int k = tid; k < n_cells; k += BS) {
-      const float v = splat_lds[k];
-      if (v != 0.0f) atomicAdd(&D[k], v);
+      const unsigned long long v = splat_lds[k];
+      if (v) atomicAdd(&A.sk.splat_acc[k], v);
     }
   }
   if (A.sk.totals) flush_wave_status(ws, A.sk.totals);
@@ -1035,6 +1049,14 @@ __global__ __launch_bounds__(64) void k_adj_finalize(const double* __restrict__ 
     grad_H[k] = homog ? 0.0 : g;
   }
   if (k == 0) *grad_eta = s[2 * PHOTON_MAX_LAYERS];
+}
+
+// Density from the fixed-point accumulator: D = norm * acc * 2^-32.
+template <typename T>
+__global__ __launch_bounds__(256) void k_splat_finish(const unsigned long long* __restrict__ acc, int n, double norm,
+                                                      T* __restrict__ D) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) D[i] = (T)((double)acc[i] * (norm / kSplatUnit));
 }
 
 // Per-segment means (section 1.2 Frank-Tamm, section 1.1 yield), the same
@@ -1305,9 +1327,11 @@ struct DeviceState {
   unsigned long long* work = nullptr;  // [0] = fused work cursor, [kDeferCounts..] per-block deferred counts
   uint2* defer_q = nullptr;            // deferred (segment row, j), kDeferCap entries
   int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fused blocks per CU by [precision][block 128/256/512]
-  int occ_splat[3] = {0, 0, 0};             // splat fused blocks per CU (see launch_fused_bs)
+  int occ_splat[4] = {0, 0, 0, 0};          // splat fused blocks per CU (see launch_fused_bs)
   int occ_adj[2] = {0, 0};                  // adjoint blocks per CU by precision
   double* adj_part = nullptr;               // per-block partial sums of the adjoint
+  unsigned long long* splat_acc = nullptr;  // fixed-point grid of the splat
+  int64_t splat_cells = 0;
 };
 std::mutex g_mu;
 DeviceState g_dev[64];
@@ -1472,8 +1496,8 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   if (!SPLAT) {
     occ = fused_occupancy<T, BS>(dev);
   } else {
-    // splat variants: 0 float/1024 with the LDS density, 1 float/256, 2 double/256
-    int& o = dev->occ_splat[sizeof(T) == 8 ? 2 : (dyn_lds ? 0 : 1)];
+    // splat variants by precision and LDS grid
+    int& o = dev->occ_splat[(sizeof(T) == 8 ? 2 : 0) + (dyn_lds ? 0 : 1)];
     if (o == 0) {
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_fused<T, BS, true>, BS, dyn_lds) != hipSuccess || o < 1)
         o = 1;
@@ -1600,7 +1624,6 @@ int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const p
 }
 
 // ------------------------------------------------------ differentiable form --
-constexpr size_t kSplatLdsMax = 64 * 1024;  // LDS density of the float form (128 x 128 cells)
 constexpr int64_t kAdjChunk = 2048;
 
 int prep_splat_grid(const photon_splat_grid* gr, SplatGeom* g) {
@@ -1665,6 +1688,21 @@ int ensure_adj_partials(DeviceState* dev) {
     dev->adj_part = nullptr;
     return fail(PHOTON_EHIP, "adjoint partial-sum allocation failed");
   }
+  return PHOTON_OK;
+}
+
+// The splat's global fixed-point grid, grown on demand (not inside a capture).
+int ensure_splat_acc(DeviceState* dev, int64_t cells) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev->splat_cells >= cells) return PHOTON_OK;
+  if (dev->splat_acc) (void)hipFree(dev->splat_acc);
+  dev->splat_acc = nullptr;
+  dev->splat_cells = 0;
+  if (hipMalloc(&dev->splat_acc, sizeof(unsigned long long) * cells) != hipSuccess) {
+    dev->splat_acc = nullptr;
+    return fail(PHOTON_EHIP, "splat accumulator allocation failed");
+  }
+  dev->splat_cells = cells;
   return PHOTON_OK;
 }
 
@@ -1958,32 +1996,41 @@ int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* at
   if ((rc = current_device(&dev))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const int cells = c.sg.nx * c.sg.ny;
-  if (precision == PHOTON_FP64)
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st,
-                       (unsigned long long*)density, cells);
-  else
-    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, (uint32_t*)density, cells);
+  if ((rc = ensure_splat_acc(dev, cells))) return rc;
+  hipLaunchKernelGGL(k_zero64_n, dim3((unsigned)std::min<int64_t>(ceil_div(cells, 256), 4096)), dim3(256), 0, st,
+                     dev->splat_acc, (int64_t)cells);
   if (status_totals) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, status_totals, PHOTON_N_STATUS);
-  if (c.n == 0) return check_launch();
-  SinkDev sk;
-  std::memset(&sk, 0, sizeof sk);
-  sk.kind = kSinkSplat;
-  sk.totals = status_totals;
-  sk.sg = c.sg;
-  sk.density = density;
-  sk.mu0 = mean0;
-  const size_t lds = (size_t)cells * sizeof(float);
-  hipFuncAttributes fa;
-  const bool lds_fits = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<float, 1024, true>)) ==
-                            hipSuccess &&
-                        fa.sharedSizeBytes + lds <= dev->lds_per_block;
-  if (precision == PHOTON_FP32 && lds <= kSplatLdsMax && lds_fits) {
-    sk.splat_lds = 1;
-    return launch_fused_bs<float, 1024, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 8192, 0, sk, dev, st, lds);
+  if (c.n > 0) {
+    SinkDev sk;
+    std::memset(&sk, 0, sizeof sk);
+    sk.kind = kSinkSplat;
+    sk.totals = status_totals;
+    sk.sg = c.sg;
+    sk.splat_acc = dev->splat_acc;
+    sk.mu0 = mean0;
+    // each block accumulates the whole grid in LDS when it fits beside the kernel's own LDS
+    const size_t lds = (size_t)cells * sizeof(unsigned long long);
+    hipFuncAttributes fa;
+    const void* kf = precision == PHOTON_FP32 ? reinterpret_cast<const void*>(&k_fused<float, 1024, true>)
+                                              : reinterpret_cast<const void*>(&k_fused<double, 512, true>);
+    const bool fits = hipFuncGetAttributes(&fa, kf) == hipSuccess && fa.sharedSizeBytes + lds <= dev->lds_per_block;
+    sk.splat_lds = fits ? 1 : 0;
+    if (precision == PHOTON_FP32)
+      rc = fits ? launch_fused_bs<float, 1024, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 8192, 0, sk, dev, st, lds)
+                : launch_fused_bs<float, 256, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st);
+    else
+      rc = fits ? launch_fused_bs<double, 512, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st, lds)
+                : launch_fused_bs<double, 256, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st);
+    if (rc) return rc;
   }
-  if (precision == PHOTON_FP32)
-    return launch_fused_bs<float, 256, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st);
-  return launch_fused_bs<double, 256, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st);
+  const unsigned nb = (unsigned)ceil_div(cells, 256);
+  if (precision == PHOTON_FP64)
+    hipLaunchKernelGGL(k_splat_finish<double>, dim3(nb), dim3(256), 0, st, (const unsigned long long*)dev->splat_acc,
+                       cells, c.sg.norm, (double*)density);
+  else
+    hipLaunchKernelGGL(k_splat_finish<float>, dim3(nb), dim3(256), 0, st, (const unsigned long long*)dev->splat_acc,
+                       cells, c.sg.norm, (float*)density);
+  return check_launch();
 }
 
 int photon_splat_backward(const photon_segments* seg, const photon_atmosphere* atm, double lambda_min_nm,

@@ -61,10 +61,23 @@ __device__ __forceinline__ void gauss_start(const SplatGeom& g, double d0, T& e0
   r0 = Fm<T>::exp_((T)(-(2.0 * d0 * g.cell + g.cell * g.cell) * g.inv_2s2));
 }
 
-// Adds a photon of weight w landing at (x, y) to the density D (row-major,
-// ny rows of nx cells). Returns false when no cell is within reach.
-template <typename T, typename Acc>
-__device__ __forceinline__ bool splat_add(const SplatGeom& g, double x, double y, T w, Acc* D) {
+// Fixed point of the splat accumulation: every cell sums w exp(-d^2/(2 sigma^2))
+// (the density without its normalisation) in units of 2^-32 in a 64-bit
+// integer. Integer sums do not depend on the order of the additions, and
+// integer atomics are the fast ones in LDS. A cell overflows only beyond 2^32
+// in weight units.
+constexpr double kSplatUnit = 4294967296.0;  // 2^32
+
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+  return (unsigned long long)__float2ull_rn(v * (float)kSplatUnit);
+}
+__device__ __forceinline__ unsigned long long to_fixed(double v) { return __double2ull_rn(v * kSplatUnit); }
+
+// Adds a photon of weight w landing at (x, y) to the fixed-point
+// accumulator acc (row-major, ny rows of nx cells). Returns false when no
+// cell is within reach.
+template <typename T>
+__device__ __forceinline__ bool splat_add(const SplatGeom& g, double x, double y, T w, unsigned long long* acc) {
   int ix0, nxw, iy0, nyw;
   double dx0, dy0;
   splat_axis(g.x_min, g.cell, g.nx, g.reach, x, ix0, nxw, dx0);
@@ -74,13 +87,12 @@ __device__ __forceinline__ bool splat_add(const SplatGeom& g, double x, double y
   gauss_start<T>(g, dx0, ex0, rx0);
   gauss_start<T>(g, dy0, ey, ry);
   const T q = (T)g.q;
-  const T wn = w * (T)g.norm;
-  Acc* row = D + (int64_t)iy0 * g.nx + ix0;
+  unsigned long long* row = acc + (int64_t)iy0 * g.nx + ix0;
   for (int b = 0; b < nyw; ++b) {
-    const T wy = wn * ey;
+    const T wy = w * ey;
     T ex = ex0, rx = rx0;
     for (int a = 0; a < nxw; ++a) {
-      atomicAdd(&row[a], (Acc)(wy * ex));
+      atomicAdd(&row[a], to_fixed(wy * ex));
       ex *= rx;
       rx *= q;
     }
