@@ -891,9 +891,41 @@ struct AdjArgs {
   SplatGeom sg;
   const void* grad;          // dL/dD, the run's precision
   double *gdx, *gdy, *gdz;   // per-segment direction gradients (accumulated)
-  double* partials;          // kAdjWords per block
+  double* partials;          // kAdjWords per block (float form: then as many for the double pass)
   unsigned long long* cursor;
+  unsigned long long* defer_counts;  // float form: per block, rays near the horizon left to the double pass
+  uint2* defer_q;                    // their (segment row, j), defer_cap entries per block
+  int64_t defer_cap;
 };
+
+__device__ __forceinline__ SegRaw load_seg_raw(const AdjArgs& A, int64_t s) {
+  SegRaw sg;
+  sg.x0 = A.seg.x0[s];
+  sg.y0 = A.seg.y0[s];
+  sg.z0 = A.seg.z0[s];
+  sg.dx = A.seg.dx[s];
+  sg.dy = A.seg.dy[s];
+  sg.dz = A.seg.dz[s];
+  sg.len = A.seg.len[s];
+  sg.beta = A.seg.beta[s];
+  sg.zz = A.seg.charge ? (double)(A.seg.charge[s] * A.seg.charge[s]) : 1.0;
+  sg.mu0 = A.mu0[s];
+  sg.idx = seg_idx(A.seg, s);
+  sg.shower = seg_shower(A.seg, s);
+  return sg;
+}
+
+// Block sums of the lane-private accumulators, in thread order, into one
+// row of partials (the caller has synchronised the block).
+template <int BS>
+__device__ __forceinline__ void adj_block_sums(const double* s_acc, double* row) {
+  const int tid = threadIdx.x;
+  if (tid < kAdjWords) {
+    double t = 0.0;
+    for (int i = 0; i < BS; ++i) t += s_acc[tid * BS + i];
+    row[tid] = t;
+  }
+}
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -932,22 +964,26 @@ __device__ __forceinline__ void seg_reduce_add(long long key, double v0, double 
 // queue, the chunk's segment offsets staged in LDS. Every photon is
 // regenerated and carried forward and back (adjoint_photon); direction
 // gradients are reduced per segment over the wave, the global sums per block
-// into partials (summed in a fixed order by k_adj_finalize).
+// into partials (summed in a fixed order by k_adj_finalize). The float form
+// queues rays near the horizon for k_splat_adjoint_deferred.
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
   __shared__ uint64_t s_off[kWindow + 1];
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
-  __shared__ double s_red[BS / kWaveSize][kAdjWords];
+  __shared__ double s_acc[kAdjWords * BS];  // lane-private sums: word k of thread t at k * BS + t
   __shared__ AtmLane s_lane;
+  __shared__ unsigned int s_dcount;
+  constexpr bool kDefer = sizeof(T) == 4;
   const int tid = threadIdx.x;
+  if (tid == 0) s_dcount = 0u;
   atm_lane_fill(A.atm, &s_lane);
   const int64_t n_seg = A.n_seg;
   const uint64_t* __restrict__ offsets = A.offsets;
   const uint64_t total = offsets[n_seg];
   const T* G = (const T*)A.grad;
-  AdjSums acc;
-  adj_clear(acc);
+  for (int k = 0; k < kAdjWords; ++k) s_acc[k * BS + tid] = 0.0;
+  const AdjAcc acc{&s_acc[tid], BS};
   for (;;) {
     if (tid == 0) s_c0 = atomicAdd(A.cursor, (unsigned long long)A.chunk);
     __syncthreads();
@@ -990,39 +1026,75 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
           off_s = offsets[s];
         }
         key = s;
-        if (seg_ok(A.seg, s)) {
-          SegRaw sg;
-          sg.x0 = A.seg.x0[s];
-          sg.y0 = A.seg.y0[s];
-          sg.z0 = A.seg.z0[s];
-          sg.dx = A.seg.dx[s];
-          sg.dy = A.seg.dy[s];
-          sg.dz = A.seg.dz[s];
-          sg.len = A.seg.len[s];
-          sg.beta = A.seg.beta[s];
-          sg.zz = A.seg.charge ? (double)(A.seg.charge[s] * A.seg.charge[s]) : 1.0;
-          sg.mu0 = A.mu0[s];
-          sg.idx = seg_idx(A.seg, s);
-          sg.shower = seg_shower(A.seg, s);
-          adjoint_photon<T, T>(A.atm, s_lane, sg, (uint32_t)(q - off_s), A.k0, A.k1, A.K, A.inv_l1, A.inv_dl, A.sg,
-                               G, acc, dd);
+        const uint32_t j = (uint32_t)(q - off_s);
+        int out = kAdjNone;
+        SegRaw sg;
+        const bool ok = seg_ok(A.seg, s);
+        if (ok) {
+          sg = load_seg_raw(A, s);
+          out = adjoint_photon<T, T>(A.atm, s_lane, sg, j, A.k0, A.k1, A.K, A.inv_l1, A.inv_dl, A.sg, G, acc, dd);
+        }
+        if (kDefer) {
+          const bool defer = out == kAdjDeferred;
+          const unsigned long long m = __ballot(defer);
+          if (m) {
+            // the block's own queue: one LDS atomic per wave
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned int base = 0;
+            if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
+            base = __shfl(base, leader, kWaveSize);
+            if (defer) {
+              const uint64_t slot = (uint64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+              if (slot < (uint64_t)A.defer_cap)
+                A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
+              else  // queue full: evaluated in float after all
+                adjoint_photon<T, T, true>(A.atm, s_lane, sg, j, A.k0, A.k1, A.K, A.inv_l1, A.inv_dl, A.sg, G,
+                                           acc, dd);
+            }
+          }
         }
       }
       seg_reduce_add(key, dd[0], dd[1], dd[2], A.gdx, A.gdy, A.gdz);
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int k = 0; k < kAdjWords; ++k) {
-    const double v = wave_sum_d(adj_word(acc, k));
-    if (lane_id() == 0) s_red[tid / kWaveSize][k] = v;
+  if (kDefer && tid == 0) {
+    const uint64_t nd = s_dcount;
+    A.defer_counts[blockIdx.x] = nd < (uint64_t)A.defer_cap ? nd : (uint64_t)A.defer_cap;
+  }
+  adj_block_sums<BS>(s_acc, A.partials + (int64_t)blockIdx.x * kAdjWords);
+}
+
+// Double pass over the rays near the horizon queued by the float adjoint:
+// block b finishes the queue of block b and writes its sums to partial row
+// row0 + b; direction gradients are added per photon.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_splat_adjoint_deferred(AdjArgs A, int64_t row0) {
+  __shared__ double s_acc[kAdjWords * BS];
+  __shared__ AtmLane s_lane;
+  const int tid = threadIdx.x;
+  atm_lane_fill(A.atm, &s_lane);
+  for (int k = 0; k < kAdjWords; ++k) s_acc[k * BS + tid] = 0.0;
+  __syncthreads();
+  const AdjAcc acc{&s_acc[tid], BS};
+  const float* G = (const float*)A.grad;
+  const unsigned long long cnt = A.defer_counts[blockIdx.x];
+  const uint64_t n = cnt < (unsigned long long)A.defer_cap ? cnt : (uint64_t)A.defer_cap;
+  const uint2* q = A.defer_q + (uint64_t)blockIdx.x * (uint64_t)A.defer_cap;
+  for (uint64_t i = tid; i < n; i += BS) {
+    const uint2 e = q[i];
+    const int64_t s = e.x < (uint32_t)A.n_seg ? (int64_t)e.x : A.n_seg - 1;
+    const SegRaw sg = load_seg_raw(A, s);
+    double dd[3] = {0.0, 0.0, 0.0};
+    if (adjoint_photon<double, float>(A.atm, s_lane, sg, e.y, A.k0, A.k1, A.K, A.inv_l1, A.inv_dl, A.sg, G, acc,
+                                      dd) == kAdjDone) {
+      atomicAdd(&A.gdx[s], dd[0]);
+      atomicAdd(&A.gdy[s], dd[1]);
+      atomicAdd(&A.gdz[s], dd[2]);
+    }
   }
   __syncthreads();
-  if (tid < kAdjWords) {
-    double t = 0.0;
-    for (int w = 0; w < BS / kWaveSize; ++w) t += s_red[w][tid];
-    A.partials[(int64_t)blockIdx.x * kAdjWords + tid] = t;
-  }
+  adj_block_sums<BS>(s_acc, A.partials + (row0 + (int64_t)blockIdx.x) * kAdjWords);
 }
 
 // Sums the block partials in block order and maps them to the parameters:
@@ -1684,7 +1756,7 @@ int prep_splat_call(const photon_segments* seg, const photon_atmosphere* atm, do
 int ensure_adj_partials(DeviceState* dev) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (dev->adj_part) return PHOTON_OK;
-  if (hipMalloc(&dev->adj_part, sizeof(double) * kAdjWords * kMaxFusedGrid) != hipSuccess) {
+  if (hipMalloc(&dev->adj_part, sizeof(double) * kAdjWords * 2 * kMaxFusedGrid) != hipSuccess) {
     dev->adj_part = nullptr;
     return fail(PHOTON_EHIP, "adjoint partial-sum allocation failed");
   }
@@ -1720,6 +1792,8 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
   if (grid > kMaxFusedGrid) grid = kMaxFusedGrid;
   int rc;
   if ((rc = ensure_adj_partials(dev))) return rc;
+  constexpr bool defer = sizeof(T) == 4;
+  if (defer && (rc = ensure_defer_queue(dev))) return rc;
   if (c.n > 0) {
     const unsigned zb = (unsigned)std::min<int64_t>(ceil_div(c.n, 256), 4096);
     hipLaunchKernelGGL(k_zero64_n, dim3(zb), dim3(256), 0, st, (unsigned long long*)gdx, c.n);
@@ -1747,9 +1821,16 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
     A.gdz = gdz;
     A.partials = dev->adj_part;
     A.cursor = dev->work;
+    A.defer_counts = dev->work + kDeferCounts;
+    A.defer_q = dev->defer_q;
+    A.defer_cap = defer ? kDeferCap / grid : 0;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
     hipLaunchKernelGGL((k_splat_adjoint<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, A);
     nb = (int)grid;
+    if (defer) {
+      hipLaunchKernelGGL((k_splat_adjoint_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A, grid);
+      nb = 2 * (int)grid;
+    }
   }
   hipLaunchKernelGGL(k_adj_finalize, dim3(1), dim3(64), 0, st, (const double*)dev->adj_part, nb, c.ad, gH, geta);
   return check_launch();

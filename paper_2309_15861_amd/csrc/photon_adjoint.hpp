@@ -147,41 +147,21 @@ __device__ __forceinline__ bool splat_seeds(const SplatGeom& g, double x, double
 }
 
 // ---------------------------------------------------------------- adjoint --
-// Per-lane sums of the global adjoints: dL/d ln rb[m] (rb[m] = rho/rho0 at
-// the base of layer m, a function of the scale heights below it), the direct
-// dL/dH_l and dL/d(n0 - 1).
-struct AdjSums {
-  double lnrb[PHOTON_MAX_LAYERS];
-  double H[PHOTON_MAX_LAYERS];
-  double eta;
-};
+// Per-lane sums of the global adjoints, kept in lane-private LDS slots
+// (word k of lane i at p[k * stride]): dL/d ln rb[m] (rb[m] = rho/rho0 at the
+// base of layer m, a function of the scale heights below it) in words
+// 0..7, the direct dL/dH_l in words 8..15, dL/d(n0 - 1) in word 16.
 constexpr int kAdjWords = 2 * PHOTON_MAX_LAYERS + 1;
+constexpr int kAdjLnrb = 0, kAdjH = PHOTON_MAX_LAYERS, kAdjEta = 2 * PHOTON_MAX_LAYERS;
 
-__device__ __forceinline__ void adj_clear(AdjSums& s) {
-#pragma unroll
-  for (int l = 0; l < PHOTON_MAX_LAYERS; ++l) {
-    s.lnrb[l] = 0.0;
-    s.H[l] = 0.0;
-  }
-  s.eta = 0.0;
-}
-
-__device__ __forceinline__ double adj_word(const AdjSums& s, int k) {
-  double v = s.eta;
-#pragma unroll
-  for (int l = 0; l < PHOTON_MAX_LAYERS; ++l) {
-    if (k == l) v = s.lnrb[l];
-    if (k == PHOTON_MAX_LAYERS + l) v = s.H[l];
-  }
-  return v;
-}
-
-// Adds v to element l (a runtime index) of a register array.
-__device__ __forceinline__ void add_at(double (&arr)[PHOTON_MAX_LAYERS], int l, double v) {
-#pragma unroll
-  for (int m = 0; m < PHOTON_MAX_LAYERS; ++m)
-    if (m == l) arr[m] += v;
-}
+struct AdjAcc {
+  double* p;
+  int stride;
+  __device__ __forceinline__ void add(int k, double v) { p[k * stride] += v; }
+  __device__ __forceinline__ void lnrb(int l, double v) { add(kAdjLnrb + l, v); }
+  __device__ __forceinline__ void H(int l, double v) { add(kAdjH + l, v); }
+  __device__ __forceinline__ void eta(double v) { add(kAdjEta, v); }
+};
 
 // Raw segment record as read for the adjoint.
 struct SegRaw {
@@ -301,16 +281,20 @@ __device__ __forceinline__ void piece_d(T rho_a, T em, double dh, T H, bool homo
   }
 }
 
+// Outcome of adjoint_photon.
+constexpr int kAdjNone = 0, kAdjDone = 1, kAdjDeferred = 2;
+
 // Adjoint of one Cherenkov photon (segment sg, number j) of the splatted
 // density with gradient G. Adds its contributions to the global sums acc and
-// returns the segment-direction adjoint in dd. Returns false when the photon
-// contributes nothing (not landed, outside every cell's reach, or its segment
-// below threshold). The float form hands rays within about 6 degrees of the
-// horizontal to the double form.
-template <typename T, typename Gt>
-__device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& sg, uint32_t j, uint32_t k0,
-                               uint32_t k1, double K, double inv_l1, double inv_dl, const SplatGeom& g, const Gt* G,
-                               AdjSums& acc, double dd[3]) {
+// returns the segment-direction adjoint in dd (kAdjDone), or kAdjNone when
+// the photon contributes nothing (not landed, outside every cell's reach, or
+// its segment below threshold). The float form returns kAdjDeferred for rays
+// within about 6 degrees of the horizontal (C^2 <= 0.01), which the double
+// form finishes; with FORCE_FLOAT it evaluates them in float.
+template <typename T, typename Gt, bool FORCE_FLOAT = false>
+__device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& sg, uint32_t j, uint32_t k0,
+                              uint32_t k1, double K, double inv_l1, double inv_dl, const SplatGeom& g, const Gt* G,
+                              AdjAcc acc, double dd[3]) {
   using F = Fm<T>;
   dd[0] = dd[1] = dd[2] = 0.0;
   // segment (double): unit direction, index at the midpoint, cone, bisector
@@ -323,7 +307,7 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
   const double bn = sg.beta * ns;
   const double cc = 1.0 / bn;
   const double sc2 = (1.0 - cc) * (1.0 + cc);
-  if (!(sc2 > 0.0) || !(sg.mu0 > 0.0)) return false;
+  if (!(sc2 > 0.0) || !(sg.mu0 > 0.0)) return kAdjNone;
   const double sc = sqrt(sc2);
   const double kzl = (K * sg.zz) * sg.len;
   const double ratio = (kzl * (1.0 - 1.0 / (bn * bn))) / sg.mu0;
@@ -344,7 +328,7 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
   T ux = (T)2 * ap * Ax - px, uy = (T)2 * ap * Ay - py, uz = (T)2 * ap * Az - pz;
   const T s = u0 * (T)sg.len;
   const double ze = sg.z0 + (double)(s * (T)vz);
-  if (!(uz < (T)0) || !(ze >= a.hobs)) return false;
+  if (!(uz < (T)0) || !(ze >= a.hobs)) return kAdjNone;
   const double xe = sg.x0 + (double)(s * (T)vx), ye = sg.y0 + (double)(s * (T)vy);
   const T lambda = F::rcp((T)inv_l1 - u2 * (T)inv_dl);
   const T kabs = abs_coeff<T>(a, L, lambda);
@@ -367,9 +351,8 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
   const T ne = (T)1 + eps_e;
   const double epsd = (double)eps_e;
   const double C2d = (ced * ced / (1.0 + sed) - epsd * sed) * (1.0 + (1.0 + epsd) * sed);
-  if constexpr (sizeof(T) == 4) {
-    if (!(C2d > (double)kNearHorizonC2))
-      return adjoint_photon<double, Gt>(a, L, sg, j, k0, k1, K, inv_l1, inv_dl, g, G, acc, dd);
+  if constexpr (sizeof(T) == 4 && !FORCE_FLOAT) {
+    if (!(C2d > (double)kNearHorizonC2)) return kAdjDeferred;
   }
   const T C2 = (T)C2d;
   const T S = ne * (T)sed;
@@ -406,7 +389,7 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
 
   // seeds from the density gradient
   T xb, yb, Wb;
-  if (!splat_seeds<T, Gt>(g, xl, yl, W, G, xb, yb, Wb)) return false;
+  if (!splat_seeds<T, Gt>(g, xl, yl, W, G, xb, yb, Wb)) return kAdjNone;
   const T ratio_b = Wb * w;
   const T col_b = -kabs * w * (T)ratio * Wb;
   const T g0t = (T)g0;
@@ -439,8 +422,8 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
       const T eb_b = g0_b * o.g_eb + col_b * o.c_eb;
       T ra_b = col_b * o.c_ra + eta0 * ea_b;
       T rb_b = col_b * o.c_rb + eta0 * eb_b;
-      acc.eta += (double)(ea_b * rho_a + eb_b * rho_b);
-      if (!homog) add_at(acc.H, l, (double)(g0_b * o.g_H + col_b * o.c_H));
+      acc.eta((double)(ea_b * rho_a + eb_b * rho_b));
+      if (!homog) acc.H(l, (double)(g0_b * o.g_H + col_b * o.c_H));
       const T dh_b = g0_b * o.g_dh + col_b * o.c_dh;
       if (homog) {
         ra_b += rb_b;  // the density is the same at both ends
@@ -449,14 +432,14 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
       // density at the bottom of the piece: rb[l], or at h_obs
       // rho_obs = rb[l_obs] exp(-(h_obs - hb[l_obs])/H[l_obs])
       const double tb = (double)(ra_b * rho_a);
-      add_at(acc.lnrb, l, tb);
-      if (l == a.l_obs) add_at(acc.H, l, tb * (a.hobs - a.hb[l]) * a.invH[l] * a.invH[l]);
+      acc.lnrb(l, tb);
+      if (l == a.l_obs) acc.H(l, tb * (a.hobs - a.hb[l]) * a.invH[l] * a.invH[l]);
       // density at the top: rb[l + 1], or rho_e for the emission piece
       if (l == le) {
         rhoe_b += rb_b;
         ze_b += (double)dh_b;
       } else {
-        add_at(acc.lnrb, l + 1, (double)(rb_b * rho_b));
+        acc.lnrb(l + 1, (double)(rb_b * rho_b));
       }
       r_top = ra;
     }
@@ -465,13 +448,13 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
   const T se2 = (T)((1.0 - ced) * (1.0 + ced));
   uz_b += C2_b * (T)2 * ne * ne * uz;
   ne_b += -C2_b * (T)2 * ne * se2;
-  acc.eta += (double)(ne_b * rho_e);
+  acc.eta((double)(ne_b * rho_e));
   rhoe_b += ne_b * eta0;
   // rho_e = rb[le] exp(-(ze - hb[le])/H[le])
   {
     const double t = (double)(rhoe_b * rho_e);
-    add_at(acc.lnrb, le, t);
-    add_at(acc.H, le, t * (ze - L.hb[le]) * L.invH[le] * L.invH[le]);
+    acc.lnrb(le, t);
+    acc.H(le, t * (ze - L.hb[le]) * L.invH[le] * L.invH[le]);
     ze_b -= t * L.invH[le];
   }
   // emission point x_e = x0 + s v (v the unit track direction)
@@ -494,17 +477,17 @@ __device__ bool adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& 
   ccb += (double)ratio_b * (-2.0 * cc * kzl / sg.mu0);
   // cos Tc = 1/(beta ns), ns = 1 + eta0 rho_c, rho_c = rb[lc] exp(-(zc - hb[lc])/H[lc])
   const double nsb = -ccb * cc / ns;
-  acc.eta += nsb * rho_c;
+  acc.eta(nsb * rho_c);
   const double t = nsb * a.eta0 * rho_c;
-  add_at(acc.lnrb, lc, t);
-  add_at(acc.H, lc, t * (zc - L.hb[lc]) * L.invH[lc] * L.invH[lc]);
+  acc.lnrb(lc, t);
+  acc.H(lc, t * (zc - L.hb[lc]) * L.invH[lc] * L.invH[lc]);
   vzb += 0.5 * sg.len * (-t * L.invH[lc]);
   // v = d/|d|
   const double vdot = vx * vxb + vy * vyb + vz * vzb;
   dd[0] = (vxb - vx * vdot) / dn;
   dd[1] = (vyb - vy * vdot) / dn;
   dd[2] = (vzb - vz * vdot) / dn;
-  return true;
+  return kAdjDone;
 }
 
 }  // namespace ph
