@@ -197,7 +197,7 @@ typedef struct {
 } photon_sink;
 
 /* Launch shape of the fused kernel: threads per block (64..1024, multiple
-   of 64), photons per work chunk (multiple of block), blocks per CU
+   of 64), photons per work chunk (multiple of block, at most 16384), blocks per CU
    (0 = as many as fit). NULL = defaults. */
 typedef struct {
   int32_t block;

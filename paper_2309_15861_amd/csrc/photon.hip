@@ -623,7 +623,9 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
 }
 
 // ------------------------------------------------------------ fused kernel --
-constexpr int kWindow = 256;  // segments staged in LDS per work chunk
+constexpr int kWindow = 256;        // segments staged in LDS per work chunk
+constexpr int kMaxChunk = 16384;     // photons per work chunk (the slot map's size)
+constexpr int kMaxChunkSplat = 8192;
 
 // Everything the fused kernels take, as one kernel argument.
 struct FusedArgs {
@@ -658,7 +660,7 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // propagated and collected in registers. In the float form, rays near the
 // horizon are appended to a queue for the double pass instead.
 template <typename T, int BS, bool SPLAT = false>
-__global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !SPLAT) ? 4 : 1))) void k_fused(FusedArgs A) {
   // the double splat keeps a smaller window so that the whole grid fits in LDS beside it
   constexpr int kWin = (SPLAT && sizeof(T) == 8) ? kWindow / 2 : kWindow;
   __shared__ SegConst<T> s_seg[kWin];
@@ -673,6 +675,13 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
   __shared__ T s_wsc[SPLAT ? kWin : 1];  // SPLAT: per-segment weight factors mu/mu0
   __shared__ AtmLane s_lane;
   __shared__ uint32_t s_cand[kCandCells * kCandCells];
+  // slot map of a chunk: bit i of s_bits is set where a segment of the window
+  // starts at photon c0 + i; s_pre holds the set bits before each word and
+  // s_slot[r] the window slot of the r-th start (r = 0: the segment holding c0)
+  constexpr int kMapWords = (SPLAT ? kMaxChunkSplat : kMaxChunk) / 64;
+  __shared__ unsigned long long s_bits[kMapWords];
+  __shared__ uint32_t s_pre[kMapWords];
+  __shared__ uint16_t s_slot[kWin];
   extern __shared__ unsigned long long s_splat[];  // dynamic: the block's fixed-point grid (SPLAT)
   constexpr bool kDefer = sizeof(T) == 4;
   const bool stage_hits = !SPLAT && A.sk.kind == PHOTON_SINK_TELESCOPES;
@@ -741,6 +750,39 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
       if (tid == 0) s_off[W] = offsets[lo + W];
     }
     __syncthreads();
+    if (win) {
+      // chunks start at multiples of the chunk size (a multiple of 64), so the
+      // 64 photons of a wave share one word of the map
+      const int nw = (int)((v1 - c0 + 63) >> 6);
+      for (int k = tid; k < nw; k += BS) s_bits[k] = 0ull;
+      __syncthreads();
+      for (int t = tid + 1; t < W; t += BS) {
+        const uint64_t st = s_off[t];
+        if (st < v1 && s_off[t + 1] > st) atomicOr(&s_bits[(st - c0) >> 6], 1ull << ((st - c0) & 63));
+      }
+      __syncthreads();
+      if (wave == 0) {
+        uint32_t carry = 0;
+        for (int base = 0; base < nw; base += kWaveSize) {
+          const int k = base + lane_id();
+          const uint32_t cnt = k < nw ? (uint32_t)__popcll(s_bits[k]) : 0u;
+          const uint32_t inc = (uint32_t)wave_incl_scan((unsigned long long)cnt);
+          if (k < nw) s_pre[k] = carry + inc - cnt;
+          carry += (uint32_t)__shfl(inc, kWaveSize - 1, kWaveSize);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_slot[0] = 0;
+      for (int t = tid + 1; t < W; t += BS) {
+        const uint64_t st = s_off[t];
+        if (st < v1 && s_off[t + 1] > st) {
+          const uint64_t i = st - c0;
+          const uint32_t r = s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull));
+          s_slot[r] = (uint16_t)t;
+        }
+      }
+      __syncthreads();
+    }
     // every lane runs the same number of iterations (the status ballots)
     for (uint64_t qb = c0; qb < v1; qb += BS) {
       const uint64_t q = qb + tid;
@@ -752,11 +794,9 @@ __global__ __launch_bounds__(BS) void k_fused(FusedArgs A) {
         int64_t s;
         T wsc = (T)1;
         if (win) {
-          int a = 0, b = (int)W;  // s_off[a] <= q < s_off[b]
-          while (b - a > 1) {
-            const int mid = (a + b) >> 1;
-            if (s_off[mid] <= q) a = mid; else b = mid;
-          }
+          // starts at or before q, counted from the map
+          const uint64_t i = q - c0;
+          const int a = s_slot[s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull))];
           c = s_seg[a];
           if constexpr (SPLAT) wsc = s_wsc[a];
           off_s = s_off[a];
@@ -1617,7 +1657,8 @@ int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParam
   int64_t chunk = tun ? tun->chunk : 4096;
   int bpc = tun ? tun->blocks_per_cu : 0;
   if (bs != 128 && bs != 256 && bs != 512) return fail(PHOTON_EINVAL, "tuning.block must be 128, 256 or 512");
-  if (chunk < bs || chunk % bs) return fail(PHOTON_EINVAL, "tuning.chunk must be a positive multiple of block");
+  if (chunk < bs || chunk % bs || chunk > kMaxChunk)
+    return fail(PHOTON_EINVAL, "tuning.chunk must be a multiple of block, at most %d", kMaxChunk);
   if (bpc < 0) return fail(PHOTON_EINVAL, "tuning.blocks_per_cu must be >= 0");
   switch (bs) {
     case 128: return launch_fused_bs<T, 128>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st);
@@ -1629,7 +1670,8 @@ int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParam
 int validate_tuning(const photon_tuning* t) {
   if (!t) return PHOTON_OK;
   if (t->block != 128 && t->block != 256 && t->block != 512) return fail(PHOTON_EINVAL, "tuning.block must be 128, 256 or 512");
-  if (t->chunk < t->block || t->chunk % t->block) return fail(PHOTON_EINVAL, "tuning.chunk must be a positive multiple of block");
+  if (t->chunk < t->block || t->chunk % t->block || t->chunk > kMaxChunk)
+    return fail(PHOTON_EINVAL, "tuning.chunk must be a multiple of block, at most %d", kMaxChunk);
   if (t->blocks_per_cu < 0) return fail(PHOTON_EINVAL, "tuning.blocks_per_cu must be >= 0");
   return PHOTON_OK;
 }

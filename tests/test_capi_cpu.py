@@ -187,3 +187,20 @@ def test_splat_validation_errors(ph):
         assert fwd(grid()) == ph.ENODEV
         assert bwd(grid()) == ph.ENODEV
         assert L.photon_means(C.byref(seg), C.byref(atm), C.byref(em), 0x4000, None) == ph.ENODEV
+
+
+def test_tuning_validation(ph):
+    """Launch shapes are checked before any device work: block 128/256/512,
+    chunk a multiple of block and at most 16384, blocks per CU >= 0."""
+    L = ph.lib()
+    atm = _valid_atm(ph)
+    seg = _fake_segments(ph)
+    em = ph.emission_cherenkov()
+    sink = ph.Sink()
+    sink.kind = ph.SINK_STATUS
+    for b, c, o in ((100, 400, 0), (256, 300, 0), (256, 16384 + 256, 0), (512, 0, 0), (256, 4096, -1)):
+        t = ph.tuning(b, c, o)
+        rc = L.photon_run_fused(C.byref(seg), C.byref(atm), C.byref(em), 1, 1, 0x3000, -1, C.byref(sink),
+                                C.byref(t), None)
+        assert rc == ph.EINVAL, (b, c, o)
+        assert "tuning" in L.photon_last_error().decode()

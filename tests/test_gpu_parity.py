@@ -285,7 +285,7 @@ def test_fused_launch_shapes_agree(plain_run):
     a, seg, d, atm, em, offsets, total, ref = plain_run
     tel = W.telescopes_16(radius=40.0)
     base = None
-    for block, chunk, bpc in ((256, 4096, 0), (128, 128, 1), (512, 512 * 37, 2), (256, 256, 0)):
+    for block, chunk, bpc in ((256, 4096, 0), (128, 128, 1), (512, 512 * 31, 2), (256, 256, 0), (256, 16384, 0)):
         hits = ph.HitBuffer(total)
         totals = ph.status_totals()
         ph.run_fused(d, atm, em, 1, ph.FP64, offsets, total, ph.sink_telescopes(tel, hits, totals),
