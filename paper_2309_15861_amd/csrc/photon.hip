@@ -495,8 +495,10 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
   int st = active ? p.status : -1;
   if constexpr (SPLAT) {
     if (active && st == PHOTON_LANDED) {
-      if (!splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, splat_lds ? splat_lds : sk.splat_acc))
-        st = PHOTON_OFFGRID;
+      // one call per address space (no generic pointer)
+      const bool in = splat_lds ? splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, splat_lds)
+                                : splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, sk.splat_acc);
+      if (!in) st = PHOTON_OFFGRID;
     }
   } else if (sk.kind == PHOTON_SINK_PLANE) {
     if (active && slot_q < (uint64_t)sk.plane_capacity) {
@@ -642,6 +644,8 @@ struct FusedArgs {
   unsigned long long* defer_counts;   // per block: near-horizon rays handed to the double pass
   uint2* defer_q;                     // their (segment row, j), defer_cap entries per block
   int64_t defer_cap;
+  unsigned long long* defer_pref;     // exclusive prefix sums of the clamped counts (n_defer_blocks + 1)
+  int32_t n_defer_blocks;             // blocks of the float kernel
 };
 static_assert(sizeof(FusedArgs) <= 4000, "fused kernel arguments must stay below 4 KB");
 
@@ -660,7 +664,7 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // propagated and collected in registers. In the float form, rays near the
 // horizon are appended to a queue for the double pass instead.
 template <typename T, int BS, bool SPLAT = false>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !SPLAT) ? 4 : 1))) void k_fused(FusedArgs A) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !SPLAT && BS >= 256) ? 4 : 1))) void k_fused(FusedArgs A) {
   // the double splat keeps a smaller window so that the whole grid fits in LDS beside it
   constexpr int kWin = (SPLAT && sizeof(T) == 8) ? kWindow / 2 : kWindow;
   __shared__ SegConst<T> s_seg[kWin];
@@ -860,9 +864,48 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   if (A.sk.totals) flush_wave_status(ws, A.sk.totals);
 }
 
+// Exclusive prefix sums of the per-block queue lengths (each clamped to the
+// queue capacity), pref[0..nb]; one block, nb <= 8192.
+__global__ __launch_bounds__(1024) void k_defer_scan(const unsigned long long* __restrict__ counts, int nb,
+                                                     int64_t cap, unsigned long long* __restrict__ pref) {
+  __shared__ unsigned long long s_w[1024 / kWaveSize];
+  constexpr int P = 8;
+  const int t = threadIdx.x;
+  unsigned long long v[P], sum = 0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int i = t * P + k;
+    const unsigned long long c = i < nb ? counts[i] : 0ull;
+    v[k] = c < (unsigned long long)cap ? c : (unsigned long long)cap;
+    sum += v[k];
+  }
+  const unsigned long long inc = wave_incl_scan(sum);
+  if (lane_id() == kWaveSize - 1) s_w[t / kWaveSize] = inc;
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long run = 0;
+    for (int w = 0; w < 1024 / kWaveSize; ++w) {
+      const unsigned long long x = s_w[w];
+      s_w[w] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  unsigned long long base = s_w[t / kWaveSize] + inc - sum;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int i = t * P + k;
+    if (i < nb) pref[i] = base;
+    base += v[k];
+    if (i == nb - 1) pref[nb] = base;
+  }
+}
+
 // Double pass over the near-horizon rays queued by the float kernel: each is
 // regenerated in double from its counter-based random numbers and carried
-// through propagation and collection in double.
+// through propagation and collection in double. The queues of all blocks
+// are taken as one list (numbered through defer_pref), spread evenly over
+// the threads.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
@@ -882,12 +925,16 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
   const bool cher = A.g.kind == PHOTON_CHERENKOV;
   StatusCounter sc;
   sc.clear();
-  // block b finishes the queue of the float kernel's block b
-  const unsigned long long cnt = A.defer_counts[blockIdx.x];
-  const uint64_t n = cnt < (unsigned long long)A.defer_cap ? cnt : (uint64_t)A.defer_cap;
-  const uint2* q = A.defer_q + (uint64_t)blockIdx.x * (uint64_t)A.defer_cap;
-  for (uint64_t i = tid; i < n; i += BS) {
-    const uint2 e = q[i];
+  const unsigned long long* __restrict__ pref = A.defer_pref;
+  const int nb = A.n_defer_blocks;
+  const uint64_t total = pref[nb];
+  for (uint64_t g = (uint64_t)blockIdx.x * BS + tid; g < total; g += (uint64_t)gridDim.x * BS) {
+    int lo = 0, hi = nb;  // pref[lo] <= g < pref[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pref[mid] <= g) lo = mid; else hi = mid;
+    }
+    const uint2 e = A.defer_q[(uint64_t)lo * (uint64_t)A.defer_cap + (g - pref[lo])];
     const int64_t s = e.x < (uint32_t)A.n_seg ? (int64_t)e.x : A.n_seg - 1;
     SegConst<double> c;
     seg_const<double>(A.seg, s, A.atm, cher, c);
@@ -936,6 +983,8 @@ struct AdjArgs {
   unsigned long long* defer_counts;  // float form: per block, rays near the horizon left to the double pass
   uint2* defer_q;                    // their (segment row, j), defer_cap entries per block
   int64_t defer_cap;
+  unsigned long long* defer_pref;    // exclusive prefix sums of the clamped counts (n_defer_blocks + 1)
+  int32_t n_defer_blocks;
 };
 
 __device__ __forceinline__ SegRaw load_seg_raw(const AdjArgs& A, int64_t s) {
@@ -1106,8 +1155,9 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
 }
 
 // Double pass over the rays near the horizon queued by the float adjoint:
-// block b finishes the queue of block b and writes its sums to partial row
-// row0 + b; direction gradients are added per photon.
+// the queues of all blocks are taken as one list (numbered through
+// defer_pref) spread evenly over the threads; block b writes its sums to
+// partial row row0 + b; direction gradients are added per photon.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_splat_adjoint_deferred(AdjArgs A, int64_t row0) {
   __shared__ double s_acc[kAdjWords * BS];
@@ -1118,11 +1168,16 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint_deferred(AdjArgs A, int64_
   __syncthreads();
   const AdjAcc acc{&s_acc[tid], BS};
   const float* G = (const float*)A.grad;
-  const unsigned long long cnt = A.defer_counts[blockIdx.x];
-  const uint64_t n = cnt < (unsigned long long)A.defer_cap ? cnt : (uint64_t)A.defer_cap;
-  const uint2* q = A.defer_q + (uint64_t)blockIdx.x * (uint64_t)A.defer_cap;
-  for (uint64_t i = tid; i < n; i += BS) {
-    const uint2 e = q[i];
+  const unsigned long long* __restrict__ pref = A.defer_pref;
+  const int nb = A.n_defer_blocks;
+  const uint64_t total = pref[nb];
+  for (uint64_t g = (uint64_t)blockIdx.x * BS + tid; g < total; g += (uint64_t)gridDim.x * BS) {
+    int lo = 0, hi = nb;  // pref[lo] <= g < pref[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pref[mid] <= g) lo = mid; else hi = mid;
+    }
+    const uint2 e = A.defer_q[(uint64_t)lo * (uint64_t)A.defer_cap + (g - pref[lo])];
     const int64_t s = e.x < (uint32_t)A.n_seg ? (int64_t)e.x : A.n_seg - 1;
     const SegRaw sg = load_seg_raw(A, s);
     double dd[3] = {0.0, 0.0, 0.0};
@@ -1207,7 +1262,8 @@ int prep_atm(const photon_atmosphere* a, AtmDev* d) {
   d->n_abs = a->n_abs;
   for (int i = 0; i < PHOTON_MAX_LAYERS; ++i) {
     const int k = i < a->n_layers ? i : a->n_layers - 1;
-    d->hb[i] = a->h_base[k];
+    // bases beyond the last layer are +inf: layer_of needs no layer count
+    d->hb[i] = i < a->n_layers ? a->h_base[k] : HUGE_VAL;
     d->H[i] = a->scale_height[k];
     if (std::isinf(a->scale_height[k]) && i < a->n_layers) d->homog_mask |= 1 << i;
   }
@@ -1438,6 +1494,7 @@ struct DeviceState {
   size_t lds_per_block = 0;             // largest LDS allocation of one workgroup
   unsigned long long* work = nullptr;  // [0] = fused work cursor, [kDeferCounts..] per-block deferred counts
   uint2* defer_q = nullptr;            // deferred (segment row, j), kDeferCap entries
+  unsigned long long* defer_pref = nullptr;  // prefix sums of the per-block deferred counts
   int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fused blocks per CU by [precision][block 128/256/512]
   int occ_splat[4] = {0, 0, 0, 0};          // splat fused blocks per CU (see launch_fused_bs)
   int occ_adj[2] = {0, 0};                  // adjoint blocks per CU by precision
@@ -1597,6 +1654,12 @@ int ensure_defer_queue(DeviceState* dev) {
     dev->defer_q = nullptr;
     return fail(PHOTON_EHIP, "deferral queue allocation failed");
   }
+  if (hipMalloc(&dev->defer_pref, sizeof(unsigned long long) * (kMaxFusedGrid + 1)) != hipSuccess) {
+    (void)hipFree(dev->defer_q);
+    dev->defer_q = nullptr;
+    dev->defer_pref = nullptr;
+    return fail(PHOTON_EHIP, "deferral queue allocation failed");
+  }
   return PHOTON_OK;
 }
 
@@ -1643,9 +1706,15 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   A.defer_counts = dev->work + kDeferCounts;
   A.defer_q = dev->defer_q;
   A.defer_cap = defer ? kDeferCap / grid : 0;
+  A.defer_pref = dev->defer_pref;
+  A.n_defer_blocks = (int32_t)grid;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
   hipLaunchKernelGGL((k_fused<T, BS, SPLAT>), dim3((unsigned)grid), dim3(BS), dyn_lds, st, A);
-  if (defer) hipLaunchKernelGGL((k_fused_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A);
+  if (defer) {
+    hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
+                       (int)grid, A.defer_cap, dev->defer_pref);
+    hipLaunchKernelGGL((k_fused_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A);
+  }
   return check_launch();
 }
 
@@ -1866,10 +1935,14 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
     A.defer_counts = dev->work + kDeferCounts;
     A.defer_q = dev->defer_q;
     A.defer_cap = defer ? kDeferCap / grid : 0;
+    A.defer_pref = dev->defer_pref;
+    A.n_defer_blocks = (int32_t)grid;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
     hipLaunchKernelGGL((k_splat_adjoint<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, A);
     nb = (int)grid;
     if (defer) {
+      hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
+                         (int)grid, A.defer_cap, dev->defer_pref);
       hipLaunchKernelGGL((k_splat_adjoint_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A, grid);
       nb = 2 * (int)grid;
     }

@@ -35,6 +35,10 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) {
+      // the keys are wave-uniform: bumped per round with scalar adds (an
+      // empty asm keeps the compiler from precomputing all ten round keys,
+      // which would occupy scalar registers through the whole photon loop)
+      asm volatile("" : "+s"(k0), "+s"(k1));
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
@@ -86,11 +90,13 @@ struct AtmDev {
   double abs_k[PHOTON_MAX_ABS];
 };
 
+// Layer of height h: the last k with hb[k] <= h (hb is +inf beyond the last
+// layer; layer 0 also extends below hb[0]).
 __device__ __forceinline__ int layer_of(const AtmDev& a, double h) {
   int l = 0;
 #pragma unroll
   for (int k = 1; k < PHOTON_MAX_LAYERS; ++k)
-    if (k < a.nl && a.hb[k] <= h) l = k;
+    if (a.hb[k] <= h) l = k;
   return l;
 }
 
