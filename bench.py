@@ -133,6 +133,49 @@ def batched_showers(args):
                 tuning=[best.block, best.chunk, best.blocks_per_cu])
 
 
+def angular_cut(args, d, atm, tel, seed, best, uncut):
+    """The shower step with the Cherenkov angular particle cut at 6 degrees,
+    to the array centre and to each telescope: emitting segments, photons and
+    hits kept, and the step time against the uncut step (same launch shape)."""
+    import numpy as np
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+
+    em0 = ph.emission_cherenkov(300.0, 600.0)
+    emitting0 = int((ph.means(d, atm, em0) > 0).sum().item())
+    out = dict(cut_deg=6.0, uncut=dict(emitting_segments=emitting0, photons=uncut["photons"],
+                                       hits=uncut["hits"], ms_per_step=uncut["ms_per_step"]))
+    for name, pts in (("centre", np.array([[0.0, 0.0, W.H_OBS]])), ("telescopes", tel[:, :3])):
+        em = ph.emission_cherenkov(300.0, 600.0, cut_points=pts, cut_angle_deg=6.0)
+        emitting = int((ph.means(d, atm, em) > 0).sum().item())
+        counts = torch.empty(d.n, dtype=torch.int32, device="cuda")
+        offsets = torch.empty(d.n + 1, dtype=torch.int64, device="cuda")
+        hits = ph.HitBuffer(max(uncut["photons"] // 8, 1024))
+        totals = ph.status_totals()
+        plan = ph.Plan(d, atm, em, seed, ph.FP32, counts, offsets, ph.sink_telescopes(tel, hits, totals), best)
+        for _ in range(args.warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            plan.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        photons = int(offsets[-1].item())
+        assert int(totals.cpu().numpy()[:7].sum()) == photons
+        nh = hits.count()
+        plan.close()
+        out[name] = dict(emitting_segments=emitting, segments_kept_frac=emitting / max(emitting0, 1),
+                         photons=photons, photons_kept_frac=photons / uncut["photons"], hits=nh,
+                         hits_kept_frac=nh / max(uncut["hits"], 1), ms_per_step=ms,
+                         speedup=uncut["ms_per_step"] / ms)
+    return out
+
+
 def differentiable(args):
     """The differentiable form at 1e6 segments: splatted ground density
     (128 x 128 cells of 5 m, sigma 5 m) with counts frozen at the nominal
@@ -195,6 +238,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="block,chunk,blocks_per_cu of the fused kernel instead of the autotuner's choice "
                          "(profiling runs)")
+    ap.add_argument("--cut", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the shower step with the 6 degree Cherenkov angular particle cut")
     ap.add_argument("--adjoint", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the differentiable form (splat forward and adjoint, 1e6 segments)")
     args = ap.parse_args()
@@ -295,6 +340,9 @@ def main():
                  "frac": SLOTS_PER_PHOTON["fp64"] * total / (r64["fused_ms"] * 1e-3) / PEAK_SLOTS},
         "hits": r32["hits"],
     }
+    if args.cut:
+        out["angular_cut"] = angular_cut(args, d, atm, tel, seed, ph.tuning(*r32["tuning"]),
+                                         dict(photons=total, hits=r32["hits"], ms_per_step=r32["ms_per_step"]))
     if args.batched:
         out["batched"] = batched_showers(args)
     if args.adjoint:

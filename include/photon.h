@@ -86,6 +86,7 @@ extern "C" {
 #define PHOTON_MAX_ABS 40
 #define PHOTON_MAX_LINES 32
 #define PHOTON_MAX_TELESCOPES 32
+#define PHOTON_MAX_CUT_POINTS 32
 
 /* Plane-parallel atmosphere (host struct). Layer i covers
    [h_base[i], h_base[i+1]); layer 0 extends below h_base[0] = 0 and the top
@@ -128,7 +129,15 @@ typedef struct {
    Cherenkov: wavelength band [lambda_min_nm, lambda_max_nm], 0 < min < max.
    Fluorescence: total yield [photons/MeV] >= 0 and n_lines (1..32) lines
    with wavelengths line_nm and relative yields line_rel_yield (>= 0, not
-   all zero); a photon takes line k with probability rel[k]/sum(rel). */
+   all zero); a photon takes line k with probability rel[k]/sum(rel).
+   Cherenkov angular particle cut (the optimisation of section 1.2.1): with
+   n_cut_points in 1..32, a segment emits no photons unless, for at least one
+   point P, the angle between its unit direction d and v = P - m (m its
+   midpoint) is at most the cut angle: d.v >= cut_cos |v|, evaluated in FP64
+   without contraction. One point is the array centre; the telescope centres
+   give the per-telescope form. n_cut_points = 0: no cut (zero-initialise).
+   Photons of the remaining segments are unchanged (their random numbers
+   depend only on their own ids). */
 typedef struct {
   int32_t kind;                       /* PHOTON_CHERENKOV / PHOTON_FLUORESCENCE */
   double lambda_min_nm, lambda_max_nm;
@@ -136,6 +145,9 @@ typedef struct {
   int32_t n_lines;
   double line_nm[PHOTON_MAX_LINES];
   double line_rel_yield[PHOTON_MAX_LINES];
+  int32_t n_cut_points;
+  double cut_cos;
+  double cut_points[PHOTON_MAX_CUT_POINTS][3];
 } photon_emission;
 
 /* The common photon block (section 1: photons of both generators are
@@ -324,9 +336,18 @@ typedef struct {
   double sigma, trunc;
 } photon_splat_grid;
 
+/* Per-segment counts and offsets for an emission model (as the generation
+   calls with out == NULL), honouring the Cherenkov angular particle cut of
+   `em`. counts: device u32[n]; offsets: device u64[n+1], offsets[n] = total.
+   Errors: EINVAL (as photon_gen_cherenkov / photon_gen_fluor, plus
+   n_cut_points outside 0..32, cut_cos outside [-1, 1], non-finite points). */
+int photon_count(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                 uint64_t seed, uint32_t* counts, uint64_t* offsets, void* stream);
+
 /* Per-segment means (device f64, n) exactly as the count step evaluates
    them: Frank-Tamm (section 1.2) or Y dE/dx L (section 1.1); 0 for
-   invalid segments. Errors: EINVAL. */
+   invalid segments and for segments removed by the angular cut.
+   Errors: EINVAL. */
 int photon_means(const photon_segments* seg, const photon_atmosphere* atm,
                  const photon_emission* em, double* mean, void* stream);
 

@@ -82,6 +82,9 @@ def lib():
         L.or_poisson.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, P]
         L.or_poisson.restype = C.c_uint32
         L.or_counts.argtypes = [P, P, C.c_int, P, C.c_uint64, P, P, P]
+        L.or_counts_cut.argtypes = [P, P, C.c_int, P, C.c_uint64, C.c_int32, C.c_double, P, P, P, P]
+        L.or_passes_cut.argtypes = [P, C.c_int64, C.c_int32, C.c_double, P]
+        L.or_passes_cut.restype = C.c_int
         L.or_rotation_matrix.argtypes = [C.c_double, C.c_double, C.c_double, P]
         L.or_line_cdf.argtypes = [P, C.c_int32, P]
         L.or_ray_integrals.argtypes = [P, C.c_double, C.c_double, C.c_double, P]
@@ -210,8 +213,9 @@ def poisson(mu, seed, idx, shower):
 
 
 def counts(seg: dict, atm: Atmosphere, kind: str, seed: int, *, lambda_nm=(300.0, 600.0),
-           yield_per_MeV=10.0):
-    """Per-segment (counts u32, mean f64, decision margin f64)."""
+           yield_per_MeV=10.0, cut=None):
+    """Per-segment (counts u32, mean f64, decision margin f64). cut = (points
+    (k, 3), cos of the cut angle) applies the Cherenkov angular particle cut."""
     S = Segments(seg)
     n = S.n
     cnt = np.zeros(n, np.uint32)
@@ -223,9 +227,22 @@ def counts(seg: dict, atm: Atmosphere, kind: str, seed: int, *, lambda_nm=(300.0
     else:
         par = np.array([yield_per_MeV], dtype=np.float64)
         kd = 1
-    lib().or_counts(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), int(seed), _ptr(cnt), _ptr(mu),
-                    _ptr(mg))
+    if cut is None:
+        lib().or_counts(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), int(seed), _ptr(cnt), _ptr(mu),
+                        _ptr(mg))
+    else:
+        pts = np.ascontiguousarray(cut[0], dtype=np.float64).reshape(-1, 3)
+        lib().or_counts_cut(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), int(seed), len(pts), float(cut[1]),
+                            _ptr(pts), _ptr(cnt), _ptr(mu), _ptr(mg))
     return cnt, mu, mg
+
+
+def passes_cut(seg: dict, points, cos_cut) -> np.ndarray:
+    """Per segment: kept by the Cherenkov angular particle cut."""
+    S = Segments(seg)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    return np.array([bool(lib().or_passes_cut(C.byref(S.c), i, len(pts), float(cos_cut), _ptr(pts)))
+                     for i in range(S.n)])
 
 
 def offsets_of(cnt: np.ndarray) -> np.ndarray:

@@ -170,7 +170,7 @@ __device__ __forceinline__ int64_t lane_upper_index(const uint64_t* off, int64_t
 // with LDS atomics (integer sums: the order does not matter).
 template <int KIND>
 __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, AtmDev atm, double K, uint32_t k0,
-                                                      uint32_t k1, uint32_t* __restrict__ counts,
+                                                      uint32_t k1, CutDev cut, uint32_t* __restrict__ counts,
                                                       uint64_t* __restrict__ offsets) {
   __shared__ unsigned long long part[kScanBlock / kWaveSize];
   __shared__ double rk[kPoissonKmax + 1];
@@ -184,7 +184,8 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
   uint32_t idx = 0, sh = 0;
   if (i < n) {
 #pragma clang fp contract(off)
-    const double mu = (KIND == PHOTON_CHERENKOV) ? mean_cherenkov(seg, i, atm, K) : mean_fluor(seg, i, K);
+    const double mu = (KIND == PHOTON_CHERENKOV) ? (passes_cut(seg, i, cut) ? mean_cherenkov(seg, i, atm, K) : 0.0)
+                                                 : mean_fluor(seg, i, K);
     m = poisson_chunks(mu);
     if (m) {
       mc = mu / (double)m;
@@ -1229,10 +1230,12 @@ __global__ __launch_bounds__(256) void k_splat_finish(const unsigned long long* 
 // Per-segment means (section 1.2 Frank-Tamm, section 1.1 yield), the same
 // evaluation as the count kernel's.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_means(SegView seg, int64_t n, AtmDev atm, double K, double* mean) {
+__global__ __launch_bounds__(256) void k_means(SegView seg, int64_t n, AtmDev atm, double K, CutDev cut,
+                                               double* mean) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  mean[i] = KIND == PHOTON_CHERENKOV ? mean_cherenkov(seg, i, atm, K) : mean_fluor(seg, i, K);
+  mean[i] = KIND == PHOTON_CHERENKOV ? (passes_cut(seg, i, cut) ? mean_cherenkov(seg, i, atm, K) : 0.0)
+                                     : mean_fluor(seg, i, K);
 }
 
 // ------------------------------------------------------------ host helpers --
@@ -1313,6 +1316,23 @@ int prep_seg(const photon_segments* s, SegView* v, bool need_dedx) {
   }
   *v = SegView{s->x0, s->y0, s->z0, s->dx, s->dy, s->dz, s->length, s->beta, s->t0, s->dedx,
                s->charge, s->shower, s->index_in_shower};
+  return PHOTON_OK;
+}
+
+int prep_cut(const photon_emission* em, CutDev* c) {
+  std::memset(c, 0, sizeof *c);
+  if (em->n_cut_points < 0 || em->n_cut_points > PHOTON_MAX_CUT_POINTS)
+    return fail(PHOTON_EINVAL, "n_cut_points = %d outside 0..%d", em->n_cut_points, PHOTON_MAX_CUT_POINTS);
+  if (em->n_cut_points == 0 || em->kind != PHOTON_CHERENKOV) return PHOTON_OK;
+  if (!finite(em->cut_cos) || em->cut_cos < -1.0 || em->cut_cos > 1.0)
+    return fail(PHOTON_EINVAL, "cut_cos must lie in [-1, 1]");
+  c->n = em->n_cut_points;
+  c->cos_cut = em->cut_cos;
+  for (int k = 0; k < em->n_cut_points; ++k)
+    for (int d = 0; d < 3; ++d) {
+      if (!finite(em->cut_points[k][d])) return fail(PHOTON_EINVAL, "cut point %d not finite", k);
+      c->pts[k][d] = em->cut_points[k][d];
+    }
   return PHOTON_OK;
 }
 
@@ -1539,8 +1559,8 @@ int check_launch() {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int count_and_scan(const SegView& sv, int64_t n, const AtmDev& atm, int kind, double K, uint64_t seed,
-                   uint32_t* counts, uint64_t* offsets, hipStream_t st) {
+int count_and_scan(const SegView& sv, int64_t n, const AtmDev& atm, int kind, double K, const CutDev& cut,
+                   uint64_t seed, uint32_t* counts, uint64_t* offsets, hipStream_t st) {
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   if (n == 0) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)offsets, 1);
@@ -1549,10 +1569,10 @@ int count_and_scan(const SegView& sv, int64_t n, const AtmDev& atm, int kind, do
   const int64_t nb = ceil_div(n, kScanBlock);
   if (kind == PHOTON_CHERENKOV)
     hipLaunchKernelGGL(k_count<PHOTON_CHERENKOV>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0, k1,
-                       counts, offsets);
+                       cut, counts, offsets);
   else
     hipLaunchKernelGGL(k_count<PHOTON_FLUORESCENCE>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0,
-                       k1, counts, offsets);
+                       k1, cut, counts, offsets);
   hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(1024), 0, st, offsets, n, nb);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanBlock), 0, st, (const uint32_t*)counts, offsets, n);
   return check_launch();
@@ -1581,6 +1601,8 @@ int generate_common(const photon_segments* seg, const photon_atmosphere* atm, co
   if ((rc = prep_seg(seg, &sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
   if ((rc = prep_atm(atm, &ad))) return rc;
   if ((rc = prep_emission(em, &g))) return rc;
+  CutDev cut;
+  if ((rc = prep_cut(em, &cut))) return rc;
   if ((rc = prep_precision(precision))) return rc;
   if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
   if (!out && !counts) return fail(PHOTON_EINVAL, "counts is NULL");
@@ -1593,7 +1615,7 @@ int generate_common(const photon_segments* seg, const photon_atmosphere* atm, co
     const double K = (em->kind == PHOTON_CHERENKOV)
                          ? (2.0 * kPi * kAlpha) * ((1e9 / em->lambda_min_nm) - (1e9 / em->lambda_max_nm))
                          : em->yield_per_MeV;
-    return count_and_scan(sv, seg->n, ad, em->kind, K, seed, counts, offsets, st);
+    return count_and_scan(sv, seg->n, ad, em->kind, K, cut, seed, counts, offsets, st);
   }
   return precision == PHOTON_FP64 ? launch_gen<double>(sv, seg->n, ad, g, seed, offsets, out, st)
                                   : launch_gen<float>(sv, seg->n, ad, g, seed, offsets, out, st);
@@ -1754,6 +1776,7 @@ struct StepArgs {
   SinkDev sk;
   int kind = 0;
   double K = 0.0;
+  CutDev cut;
   uint64_t seed = 0;
   int32_t precision = 0;
 };
@@ -1765,6 +1788,7 @@ int prep_step(const photon_segments* seg, const photon_atmosphere* atm, const ph
   if ((rc = prep_seg(seg, &a->sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
   if ((rc = prep_atm(atm, &a->ad))) return rc;
   if ((rc = prep_emission(em, &a->g))) return rc;
+  if ((rc = prep_cut(em, &a->cut))) return rc;
   if ((rc = prep_precision(precision))) return rc;
   if ((rc = prep_sink(sink, &a->sk, a->ad.hobs, precision))) return rc;
   if ((rc = validate_tuning(tuning))) return rc;
@@ -1801,7 +1825,7 @@ int enqueue_fused(const StepArgs& a, const uint64_t* offsets, int64_t n_ph, cons
 int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const photon_tuning* tun,
                  DeviceState* dev, hipStream_t st) {
   int rc;
-  if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.seed, counts, offsets, st))) return rc;
+  if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.cut, a.seed, counts, offsets, st))) return rc;
   if ((rc = clear_sink(a.sk, st))) return rc;
   return enqueue_fused(a, offsets, -1, tun, dev, st);
 }
@@ -2153,6 +2177,12 @@ int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm, co
   return PHOTON_OK;
 }
 
+int photon_count(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                 uint64_t seed, uint32_t* counts, uint64_t* offsets, void* stream) {
+  if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
+  return generate_common(seg, atm, em, seed, PHOTON_FP64, counts, offsets, nullptr, stream);
+}
+
 int photon_means(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em, double* mean,
                  void* stream) {
   SegView sv;
@@ -2163,6 +2193,8 @@ int photon_means(const photon_segments* seg, const photon_atmosphere* atm, const
   if ((rc = prep_seg(seg, &sv, em->kind == PHOTON_FLUORESCENCE))) return rc;
   if ((rc = prep_atm(atm, &ad))) return rc;
   if ((rc = prep_emission(em, &g))) return rc;
+  CutDev cut;
+  if ((rc = prep_cut(em, &cut))) return rc;
   if (!mean && seg->n > 0) return fail(PHOTON_EINVAL, "mean is NULL");
   DeviceState* dev;
   if ((rc = current_device(&dev))) return rc;
@@ -2171,9 +2203,9 @@ int photon_means(const photon_segments* seg, const photon_atmosphere* atm, const
   const unsigned nb = (unsigned)ceil_div(seg->n, 256);
   if (em->kind == PHOTON_CHERENKOV) {
     const double K = (2.0 * kPi * kAlpha) * ((1e9 / em->lambda_min_nm) - (1e9 / em->lambda_max_nm));
-    hipLaunchKernelGGL(k_means<PHOTON_CHERENKOV>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, K, mean);
+    hipLaunchKernelGGL(k_means<PHOTON_CHERENKOV>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, K, cut, mean);
   } else {
-    hipLaunchKernelGGL(k_means<PHOTON_FLUORESCENCE>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, em->yield_per_MeV,
+    hipLaunchKernelGGL(k_means<PHOTON_FLUORESCENCE>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, em->yield_per_MeV, cut,
                        mean);
   }
   return check_launch();

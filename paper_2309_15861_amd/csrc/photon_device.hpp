@@ -161,6 +161,34 @@ __device__ __forceinline__ double mean_fluor(const SegView& s, int64_t i, double
   return (Y * e) * s.len[i];
 }
 
+// Cherenkov angular particle cut (the optimisation of section 1.2.1): a
+// segment passes when the angle between its unit direction and the vector
+// from its midpoint to one of the points is at most the cut angle,
+// d.v >= cos_cut |v|. FP64 without contraction in a fixed order, so that any
+// IEEE evaluation of the same steps decides alike.
+struct CutDev {
+  int32_t n;  // 0: no cut
+  double cos_cut;
+  double pts[PHOTON_MAX_CUT_POINTS][3];
+};
+
+__device__ __forceinline__ bool passes_cut(const SegView& s, int64_t i, const CutDev& c) {
+#pragma clang fp contract(off)
+  if (c.n <= 0) return true;
+  const double dx = s.dx[i], dy = s.dy[i], dz = s.dz[i];
+  const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
+  const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+  const double hl = 0.5 * s.len[i];
+  const double mx = s.x0[i] + hl * ux, my = s.y0[i] + hl * uy, mz = s.z0[i] + hl * uz;
+  for (int k = 0; k < c.n && k < PHOTON_MAX_CUT_POINTS; ++k) {
+    const double vx = c.pts[k][0] - mx, vy = c.pts[k][1] - my, vz = c.pts[k][2] - mz;
+    const double dot = (ux * vx + uy * vy) + uz * vz;
+    const double nv = sqrt((vx * vx + vy * vy) + vz * vz);
+    if (dot >= c.cos_cut * nv) return true;
+  }
+  return false;
+}
+
 // Chunking of a mean for the Poisson draw: m chunks of mean mc (m = 0 when
 // the segment emits nothing).
 __device__ __forceinline__ uint32_t poisson_chunks(double mu) {

@@ -23,7 +23,7 @@ LANDED, HIT, UP, BELOW, OFFGRID, ABSORBED, INVALID = 0, 1, 2, 3, 4, 5, 6
 HORIZON_FLOAT = 7          # totals slot: near-horizon rays evaluated in float (queue full)
 N_STATUS = 8
 SINK_STATUS, SINK_TELESCOPES, SINK_GRID, SINK_PLANE = 0, 1, 2, 3
-MAX_LAYERS, MAX_ABS, MAX_LINES, MAX_TELESCOPES = 8, 40, 32, 32
+MAX_LAYERS, MAX_ABS, MAX_LINES, MAX_TELESCOPES, MAX_CUT_POINTS = 8, 40, 32, 32, 32
 
 P = C.c_void_p
 
@@ -44,7 +44,9 @@ class Segments(C.Structure):
 class Emission(C.Structure):
     _fields_ = [("kind", C.c_int32), ("lambda_min_nm", C.c_double), ("lambda_max_nm", C.c_double),
                 ("yield_per_MeV", C.c_double), ("n_lines", C.c_int32),
-                ("line_nm", C.c_double * MAX_LINES), ("line_rel_yield", C.c_double * MAX_LINES)]
+                ("line_nm", C.c_double * MAX_LINES), ("line_rel_yield", C.c_double * MAX_LINES),
+                ("n_cut_points", C.c_int32), ("cut_cos", C.c_double),
+                ("cut_points", (C.c_double * 3) * MAX_CUT_POINTS)]
 
 
 class Block(C.Structure):
@@ -104,12 +106,14 @@ def lib():
         L.photon_plan_destroy.argtypes = [P]
         L.photon_autotune.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P, C.c_int32, C.c_int32, P, P, P]
         L.photon_means.argtypes = [P, P, P, P, P]
+        L.photon_count.argtypes = [P, P, P, C.c_uint64, P, P, P]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
                   "photon_run_fused", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
-                  "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward"):
+                  "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward",
+                  "photon_count"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -299,10 +303,20 @@ def sink_plane(block: PhotonBlock, totals=None) -> Sink:
     return s
 
 
-def emission_cherenkov(lmin=300.0, lmax=600.0) -> Emission:
+def emission_cherenkov(lmin=300.0, lmax=600.0, cut_points=None, cut_angle_deg=6.0) -> Emission:
+    """Cherenkov emission; cut_points (k x 3) enables the angular particle cut
+    (a segment emits only if its direction is within cut_angle_deg of the
+    direction from its midpoint to one of the points)."""
     e = Emission()
     e.kind = CHERENKOV
     e.lambda_min_nm, e.lambda_max_nm = float(lmin), float(lmax)
+    if cut_points is not None:
+        pts = np.asarray(cut_points, np.float64).reshape(-1, 3)
+        e.n_cut_points = len(pts)
+        e.cut_cos = float(np.cos(np.radians(cut_angle_deg)))
+        for k in range(min(len(pts), MAX_CUT_POINTS)):
+            for d in range(3):
+                e.cut_points[k][d] = float(pts[k, d])
     return e
 
 
@@ -339,14 +353,13 @@ def gen_fluor(seg: DeviceSegments, atm: Atmosphere, line_nm, line_rel, yield_per
 
 
 def count(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, device="cuda"):
-    """Counts (u32 as int32 tensor) and offsets (u64 as int64 tensor)."""
+    """Counts (u32 as int32 tensor) and offsets (u64 as int64 tensor) for an
+    emission model (honouring its angular cut)."""
     counts = torch.empty(max(seg.n, 1), dtype=torch.int32, device=device)
     offsets = torch.empty(seg.n + 1, dtype=torch.int64, device=device)
-    if em.kind == CHERENKOV:
-        gen_cherenkov(seg, atm, em.lambda_min_nm, em.lambda_max_nm, seed, FP64, counts, offsets)
-    else:
-        gen_fluor(seg, atm, list(em.line_nm)[:em.n_lines], list(em.line_rel_yield)[:em.n_lines],
-                  em.yield_per_MeV, seed, FP64, counts, offsets)
+    s = seg.struct()
+    _check(lib().photon_count(C.byref(s), C.byref(atm), C.byref(em), int(seed), _ptr(counts), _ptr(offsets),
+                              _stream()))
     return counts[:seg.n], offsets
 
 

@@ -204,3 +204,28 @@ def test_tuning_validation(ph):
                                 C.byref(t), None)
         assert rc == ph.EINVAL, (b, c, o)
         assert "tuning" in L.photon_last_error().decode()
+
+
+def test_cut_validation(ph):
+    """The angular particle cut is validated before any device work."""
+    L = ph.lib()
+    atm = _valid_atm(ph)
+    seg = _fake_segments(ph)
+
+    def count(em):
+        return L.photon_count(C.byref(seg), C.byref(atm), C.byref(em), 1, 0x2000, 0x3000, None)
+
+    em = ph.emission_cherenkov(cut_points=[[0.0, 0.0, 2200.0]])
+    assert count(em) == ph.ENODEV
+    em.n_cut_points = ph.MAX_CUT_POINTS + 1
+    assert count(em) == ph.EINVAL
+    em.n_cut_points = -1
+    assert count(em) == ph.EINVAL
+    em = ph.emission_cherenkov(cut_points=[[0.0, 0.0, 2200.0]])
+    em.cut_cos = 1.5
+    assert count(em) == ph.EINVAL
+    em.cut_cos = float("nan")
+    assert count(em) == ph.EINVAL
+    em = ph.emission_cherenkov(cut_points=[[0.0, float("inf"), 2200.0]])
+    assert count(em) == ph.EINVAL
+    assert b"not finite" in L.photon_last_error()
