@@ -176,6 +176,51 @@ def angular_cut(args, d, atm, tel, seed, best, uncut):
     return out
 
 
+def fluorescence_beaming(args, best):
+    """The fluorescence step (1e5 segments, 21 lines, 16 telescopes R = 6 m)
+    with isotropic and with beamed emission (a cone per segment around a
+    sphere enclosing the array, 1 degree margin): photons, hits and step time."""
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+
+    seg = W.fluorescence()
+    a = W.default_atmosphere(absorption=True)
+    tel = W.telescopes_16()
+    d = ph.DeviceSegments(seg)
+    atm = ph.atmosphere(a)
+    lam, rel = W.fluorescence_lines()
+    out = dict(workload="1e5 fluorescence segments 5..30 km, dE/dx 1..10 MeV/m, 21 lines, 10 photons/MeV; "
+                        "16 telescopes R=6 m", margin_deg=1.0)
+    for name, area in (("isotropic", None), ("beamed", ph.enclosing_sphere(tel))):
+        em = ph.emission_fluor(lam, rel, W.FLUOR_YIELD_PER_MEV, beam_area=area, beam_margin_deg=1.0)
+        counts = torch.empty(d.n, dtype=torch.int32, device="cuda")
+        offsets = torch.empty(d.n + 1, dtype=torch.int64, device="cuda")
+        hits = ph.HitBuffer(1 << 16)
+        totals = ph.status_totals()
+        plan = ph.Plan(d, atm, em, 3, ph.FP32, counts, offsets, ph.sink_telescopes(tel, hits, totals), best)
+        for _ in range(args.warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            plan.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        photons = int(offsets[-1].item())
+        tot = totals.cpu().numpy()
+        assert int(tot[:7].sum()) == photons
+        plan.close()
+        out[name] = dict(photons=photons, hits=int(tot[ph.HIT]), ms_per_step=ms,
+                         photons_per_s=photons / (ms * 1e-3))
+    out["photons_kept_frac"] = out["beamed"]["photons"] / out["isotropic"]["photons"]
+    out["speedup"] = out["isotropic"]["ms_per_step"] / out["beamed"]["ms_per_step"]
+    return out
+
+
 def differentiable(args):
     """The differentiable form at 1e6 segments: splatted ground density
     (128 x 128 cells of 5 m, sigma 5 m) with counts frozen at the nominal
@@ -240,6 +285,8 @@ def main():
                          "(profiling runs)")
     ap.add_argument("--cut", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the shower step with the 6 degree Cherenkov angular particle cut")
+    ap.add_argument("--beam", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the fluorescence step with isotropic and beamed emission")
     ap.add_argument("--adjoint", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the differentiable form (splat forward and adjoint, 1e6 segments)")
     args = ap.parse_args()
@@ -343,6 +390,8 @@ def main():
     if args.cut:
         out["angular_cut"] = angular_cut(args, d, atm, tel, seed, ph.tuning(*r32["tuning"]),
                                          dict(photons=total, hits=r32["hits"], ms_per_step=r32["ms_per_step"]))
+    if args.beam:
+        out["fluorescence_beaming"] = fluorescence_beaming(args, ph.tuning(*r32["tuning"]))
     if args.batched:
         out["batched"] = batched_showers(args)
     if args.adjoint:

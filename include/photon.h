@@ -137,7 +137,18 @@ typedef struct {
    without contraction. One point is the array centre; the telescope centres
    give the per-telescope form. n_cut_points = 0: no cut (zero-initialise).
    Photons of the remaining segments are unchanged (their random numbers
-   depend only on their own ids). */
+   depend only on their own ids). Ignored for fluorescence.
+   Fluorescence beaming (the optimisation of section 1.1.1), beam = 1: each
+   segment emits into a cone that contains the emission area, a sphere of
+   centre beam_center and radius beam_radius enclosing every telescope, and
+   its mean photon number is scaled by the cone's solid-angle fraction
+   (1 - cos(half angle))/2. Seen from the segment midpoint m at distance D
+   from the centre, the half angle is asin((beam_radius + L/2)/D) plus
+   beam_margin_rad (in [0, pi/2]; a margin for refractive bending), about
+   the direction from m to the centre; directions are uniform on the cone.
+   A segment with beam_radius + L/2 >= D stays isotropic. beam = 0: isotropic
+   emission. Ignored for Cherenkov. Expected telescope hits are unchanged as
+   long as every photon that can reach a telescope leaves within the cone. */
 typedef struct {
   int32_t kind;                       /* PHOTON_CHERENKOV / PHOTON_FLUORESCENCE */
   double lambda_min_nm, lambda_max_nm;
@@ -148,6 +159,10 @@ typedef struct {
   int32_t n_cut_points;
   double cut_cos;
   double cut_points[PHOTON_MAX_CUT_POINTS][3];
+  int32_t beam;
+  double beam_center[3];
+  double beam_radius;
+  double beam_margin_rad;
 } photon_emission;
 
 /* The common photon block (section 1: photons of both generators are
@@ -340,13 +355,24 @@ typedef struct {
    calls with out == NULL), honouring the Cherenkov angular particle cut of
    `em`. counts: device u32[n]; offsets: device u64[n+1], offsets[n] = total.
    Errors: EINVAL (as photon_gen_cherenkov / photon_gen_fluor, plus
-   n_cut_points outside 0..32, cut_cos outside [-1, 1], non-finite points). */
+   n_cut_points outside 0..32, cut_cos outside [-1, 1], non-finite points,
+   beam not 0 or 1, a non-finite beam centre, a negative beam radius, or a
+   margin outside [0, pi/2]). */
 int photon_count(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
                  uint64_t seed, uint32_t* counts, uint64_t* offsets, void* stream);
 
+/* Fills a photon block for an emission model (as the generation calls with
+   a block), with the model's fluorescence beaming; offsets from photon_count
+   with the same model, seed and segments. Errors: EINVAL (as photon_count,
+   plus a NULL, mismatched or too small block). */
+int photon_generate(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                    uint64_t seed, int32_t precision, const uint64_t* offsets, photon_block* out,
+                    void* stream);
+
 /* Per-segment means (device f64, n) exactly as the count step evaluates
    them: Frank-Tamm (section 1.2) or Y dE/dx L (section 1.1); 0 for
-   invalid segments and for segments removed by the angular cut.
+   invalid segments and for segments removed by the angular cut; beamed
+   fluorescence means include the solid-angle fraction.
    Errors: EINVAL. */
 int photon_means(const photon_segments* seg, const photon_atmosphere* atm,
                  const photon_emission* em, double* mean, void* stream);

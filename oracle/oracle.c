@@ -301,18 +301,60 @@ int or_passes_cut(const or_segments* s, int64_t i, int32_t n_pts, double cos_cut
   return 0;
 }
 
-/* Counts with the angular cut applied to Cherenkov segments. */
-void or_counts_cut(const or_segments* s, const or_atmosphere* a, int kind, const double* params, uint64_t seed,
-                   int32_t n_pts, double cos_cut, const double* pts, uint32_t* counts, double* mu_out,
-                   double* margin_out) {
+/* Fluorescence beaming (section 1.1.1, optimisation): instead of emitting
+   isotropically, a track emits into a cone that contains an emission area
+   enclosing every telescope, and its photon number is scaled by the cone's
+   solid-angle fraction. The area is a sphere beam = (cx, cy, cz, R); the
+   margin beam[4] (radians) widens the cone for the bending of rays by
+   refraction. Seen from the track midpoint m, at distance D from the
+   centre, the sphere grown by half the track length subtends the half
+   angle alpha with sin(alpha) = (R + L/2)/D; the grown sphere seen from m
+   contains the sphere seen from every point of the track. The cone has half
+   angle alpha + margin about the unit vector from m to the centre; om is
+   1 - cos(alpha + margin) and the solid-angle fraction om/2. A track inside
+   the grown sphere (R + L/2 >= D) stays isotropic: om = 2, axis straight
+   down. Returns 1 when beamed. */
+int or_beam_cap(const or_segments* s, int64_t i, const double* beam, double* om, double* axis) {
+  double dx = s->dx[i], dy = s->dy[i], dz = s->dz[i];
+  double dn = sqrt((dx * dx + dy * dy) + dz * dz);
+  double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+  double hl = 0.5 * s->length[i];
+  double mx = s->x0[i] + hl * ux, my = s->y0[i] + hl * uy, mz = s->z0[i] + hl * uz;
+  double vx = beam[0] - mx, vy = beam[1] - my, vz = beam[2] - mz;
+  double D = sqrt((vx * vx + vy * vy) + vz * vz);
+  double reach = beam[3] + hl;
+  if (!(reach < D)) {
+    *om = 2.0;
+    axis[0] = 0.0; axis[1] = 0.0; axis[2] = -1.0;
+    return 0;
+  }
+  double sa = reach / D;
+  double ca = sqrt((1.0 - sa) * (1.0 + sa));
+  double cb = ca * cos(beam[4]) - sa * sin(beam[4]);
+  *om = 1.0 - cb;
+  axis[0] = vx / D; axis[1] = vy / D; axis[2] = vz / D;
+  return 1;
+}
+
+/* Counts with the angular cut applied to Cherenkov segments (n_pts > 0)
+   and beaming applied to fluorescence segments (beam != NULL). */
+void or_counts_ex(const or_segments* s, const or_atmosphere* a, int kind, const double* params, uint64_t seed,
+                  int32_t n_pts, double cos_cut, const double* pts, const double* beam, uint32_t* counts,
+                  double* mu_out, double* margin_out) {
   double K = (kind == 0) ? or_frank_tamm_K(params[0], params[1]) : 0.0;
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t i = 0; i < s->n; ++i) {
     double mu;
-    if (kind == 0)
+    if (kind == 0) {
       mu = or_passes_cut(s, i, n_pts, cos_cut, pts) ? or_mean_cherenkov(s, i, a, K) : 0.0;
-    else
+    } else {
       mu = or_mean_fluor(s, i, params[0]);
+      if (beam && mu > 0.0) {
+        double om, ax[3];
+        or_beam_cap(s, i, beam, &om, ax);
+        mu = mu * (0.5 * om);
+      }
+    }
     double mg;
     counts[i] = or_poisson(mu, seed, seg_index(s, i), seg_shower(s, i), &mg);
     if (mu_out) mu_out[i] = mu;
@@ -408,19 +450,35 @@ void or_line_cdf(const double* rel_yield, int32_t n_lines, double* cdf) {
 
 /* j-th fluorescence photon of segment i (section 1.1): isotropic direction,
    emission point uniform along the track, emission line drawn with
-   probability proportional to its relative yield. */
+   probability proportional to its relative yield. With beaming (beam !=
+   NULL, section 1.1.1) the direction is uniform on the cone of or_beam_cap:
+   1 - cos(theta) = u1 om from the cone axis, azimuth 2 pi u2, generated
+   about the downward normal and turned onto the axis by the half turn of
+   or_rotation_matrix (which maps (0,0,-1) onto the axis). */
 void or_gen_fluor_one(const or_segments* s, int64_t i, uint32_t j, const double* line_nm,
-                      const double* cdf, int32_t n_lines, uint64_t seed, or_photon* p) {
+                      const double* cdf, int32_t n_lines, uint64_t seed, const double* beam, or_photon* p) {
   memset(p, 0, sizeof(*p));
   double u[4];
   draw4(seed, j, seg_index(s, i), seg_shower(s, i), OR_DOM_FLUO, u, 0);
   emission_point(s, i, u[0], p);
-  double ct = 1.0 - 2.0 * u[1];
-  double st = sqrt((1.0 - ct) * (1.0 + ct));
-  double ph = 2.0 * OR_PI * u[2];
-  p->ue[0] = st * cos(ph);
-  p->ue[1] = st * sin(ph);
-  p->ue[2] = ct;
+  if (beam) {
+    double om, ax[3], M[9];
+    or_beam_cap(s, i, beam, &om, ax);
+    double v = u[1] * om;
+    double ct = 1.0 - v;
+    double st = sqrt(v * (2.0 - v));
+    double ph = 2.0 * OR_PI * u[2];
+    double pv[3] = {st * cos(ph), st * sin(ph), -ct};
+    or_rotation_matrix(ax[0], ax[1], ax[2], M);
+    for (int r = 0; r < 3; ++r) p->ue[r] = M[3 * r] * pv[0] + M[3 * r + 1] * pv[1] + M[3 * r + 2] * pv[2];
+  } else {
+    double ct = 1.0 - 2.0 * u[1];
+    double st = sqrt((1.0 - ct) * (1.0 + ct));
+    double ph = 2.0 * OR_PI * u[2];
+    p->ue[0] = st * cos(ph);
+    p->ue[1] = st * sin(ph);
+    p->ue[2] = ct;
+  }
   int k = 0;
   while (k < n_lines - 1 && !(u[3] < cdf[k])) ++k;
   p->lambda = line_nm[k];
@@ -660,7 +718,8 @@ int32_t or_grid_cell(const or_photon* p, double x_min, double y_min, double cell
 /* Generates and propagates photons (s_list[q], j_list[q]) for q < count. */
 void or_photons(const or_segments* s, const or_atmosphere* a, int kind, const double* params,
                 const double* line_nm, const double* line_rel, int32_t n_lines, uint64_t seed,
-                const int64_t* s_list, const uint32_t* j_list, int64_t count, or_photon* out) {
+                const double* beam, const int64_t* s_list, const uint32_t* j_list, int64_t count,
+                or_photon* out) {
   double cdf[64];
   if (kind == 1) or_line_cdf(line_rel, n_lines, cdf);
 #pragma omp parallel for schedule(dynamic, 1024)
@@ -669,7 +728,7 @@ void or_photons(const or_segments* s, const or_atmosphere* a, int kind, const do
     if (kind == 0)
       or_gen_cherenkov_one(s, i, j_list[q], a, params[0], params[1], seed, &out[q]);
     else
-      or_gen_fluor_one(s, i, j_list[q], line_nm, cdf, n_lines, seed, &out[q]);
+      or_gen_fluor_one(s, i, j_list[q], line_nm, cdf, n_lines, seed, beam, &out[q]);
     or_propagate_one(&out[q], a);
   }
 }
@@ -677,7 +736,7 @@ void or_photons(const or_segments* s, const or_atmosphere* a, int kind, const do
 /* Every photon of every segment, in slot order given by offsets (n+1). */
 void or_photons_all(const or_segments* s, const or_atmosphere* a, int kind, const double* params,
                     const double* line_nm, const double* line_rel, int32_t n_lines,
-                    uint64_t seed, const uint64_t* offsets, or_photon* out) {
+                    uint64_t seed, const double* beam, const uint64_t* offsets, or_photon* out) {
   double cdf[64];
   if (kind == 1) or_line_cdf(line_rel, n_lines, cdf);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -687,7 +746,7 @@ void or_photons_all(const or_segments* s, const or_atmosphere* a, int kind, cons
       if (kind == 0)
         or_gen_cherenkov_one(s, i, j, a, params[0], params[1], seed, &out[q]);
       else
-        or_gen_fluor_one(s, i, j, line_nm, cdf, n_lines, seed, &out[q]);
+        or_gen_fluor_one(s, i, j, line_nm, cdf, n_lines, seed, beam, &out[q]);
       or_propagate_one(&out[q], a);
     }
   }

@@ -82,14 +82,16 @@ def lib():
         L.or_poisson.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, P]
         L.or_poisson.restype = C.c_uint32
         L.or_counts.argtypes = [P, P, C.c_int, P, C.c_uint64, P, P, P]
-        L.or_counts_cut.argtypes = [P, P, C.c_int, P, C.c_uint64, C.c_int32, C.c_double, P, P, P, P]
+        L.or_counts_ex.argtypes = [P, P, C.c_int, P, C.c_uint64, C.c_int32, C.c_double, P, P, P, P, P]
+        L.or_beam_cap.argtypes = [P, C.c_int64, P, P, P]
+        L.or_beam_cap.restype = C.c_int
         L.or_passes_cut.argtypes = [P, C.c_int64, C.c_int32, C.c_double, P]
         L.or_passes_cut.restype = C.c_int
         L.or_rotation_matrix.argtypes = [C.c_double, C.c_double, C.c_double, P]
         L.or_line_cdf.argtypes = [P, C.c_int32, P]
         L.or_ray_integrals.argtypes = [P, C.c_double, C.c_double, C.c_double, P]
-        L.or_photons.argtypes = [P, P, C.c_int, P, P, P, C.c_int32, C.c_uint64, P, P, C.c_int64, P]
-        L.or_photons_all.argtypes = [P, P, C.c_int, P, P, P, C.c_int32, C.c_uint64, P, P]
+        L.or_photons.argtypes = [P, P, C.c_int, P, P, P, C.c_int32, C.c_uint64, P, P, P, C.c_int64, P]
+        L.or_photons_all.argtypes = [P, P, C.c_int, P, P, P, C.c_int32, C.c_uint64, P, P, P]
         L.or_telescopes.argtypes = [P, C.c_int64, P, C.c_int32, C.c_double, P, P]
         L.or_grid.argtypes = [P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32,
                               C.c_int32, P]
@@ -212,10 +214,19 @@ def poisson(mu, seed, idx, shower):
     return int(k), m.value
 
 
+def _beam_arr(beam):
+    """beam = (centre (3,), radius, margin in radians) or None."""
+    if beam is None:
+        return None
+    c, r, m = beam
+    return np.array([c[0], c[1], c[2], r, m], dtype=np.float64)
+
+
 def counts(seg: dict, atm: Atmosphere, kind: str, seed: int, *, lambda_nm=(300.0, 600.0),
-           yield_per_MeV=10.0, cut=None):
+           yield_per_MeV=10.0, cut=None, beam=None):
     """Per-segment (counts u32, mean f64, decision margin f64). cut = (points
-    (k, 3), cos of the cut angle) applies the Cherenkov angular particle cut."""
+    (k, 3), cos of the cut angle) applies the Cherenkov angular particle cut;
+    beam = (centre, radius, margin rad) the fluorescence beaming."""
     S = Segments(seg)
     n = S.n
     cnt = np.zeros(n, np.uint32)
@@ -227,14 +238,33 @@ def counts(seg: dict, atm: Atmosphere, kind: str, seed: int, *, lambda_nm=(300.0
     else:
         par = np.array([yield_per_MeV], dtype=np.float64)
         kd = 1
-    if cut is None:
+    if cut is None and beam is None:
         lib().or_counts(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), int(seed), _ptr(cnt), _ptr(mu),
                         _ptr(mg))
     else:
-        pts = np.ascontiguousarray(cut[0], dtype=np.float64).reshape(-1, 3)
-        lib().or_counts_cut(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), int(seed), len(pts), float(cut[1]),
-                            _ptr(pts), _ptr(cnt), _ptr(mu), _ptr(mg))
+        pts = (np.zeros((0, 3)) if cut is None else
+               np.ascontiguousarray(cut[0], dtype=np.float64).reshape(-1, 3))
+        cos_cut = 1.0 if cut is None else float(cut[1])
+        b = _beam_arr(beam)
+        lib().or_counts_ex(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), int(seed), len(pts), cos_cut,
+                           _ptr(pts), _ptr(b), _ptr(cnt), _ptr(mu), _ptr(mg))
     return cnt, mu, mg
+
+
+def beam_cap(seg: dict, beam):
+    """Per segment (beamed?, 1 - cos of the cone half angle, unit axis (n, 3))."""
+    S = Segments(seg)
+    b = _beam_arr(beam)
+    om = np.zeros(1)
+    ax = np.zeros(3)
+    on = np.zeros(S.n, bool)
+    oms = np.zeros(S.n)
+    axes = np.zeros((S.n, 3))
+    for i in range(S.n):
+        on[i] = bool(lib().or_beam_cap(C.byref(S.c), i, _ptr(b), _ptr(om), _ptr(ax)))
+        oms[i] = om[0]
+        axes[i] = ax
+    return on, oms, axes
 
 
 def passes_cut(seg: dict, points, cos_cut) -> np.ndarray:
@@ -260,27 +290,29 @@ def _gen_args(kind, lambda_nm, yield_per_MeV, lines_nm, line_rel):
 
 
 def photons(seg: dict, atm: Atmosphere, kind: str, seed: int, s_list, j_list, *,
-            lambda_nm=(300.0, 600.0), yield_per_MeV=10.0, lines_nm=None, line_rel=None):
+            lambda_nm=(300.0, 600.0), yield_per_MeV=10.0, lines_nm=None, line_rel=None, beam=None):
     """Generated + propagated photons for the listed (segment, j) pairs."""
     S = Segments(seg)
     kd, par, ln, lr, nl = _gen_args(kind, lambda_nm, yield_per_MeV, lines_nm, line_rel)
     s_list = np.ascontiguousarray(s_list, dtype=np.int64)
     j_list = np.ascontiguousarray(j_list, dtype=np.uint32)
     out = np.zeros(len(s_list), PHOTON_DTYPE)
+    b = _beam_arr(beam)
     lib().or_photons(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), _ptr(ln), _ptr(lr), nl,
-                     int(seed), _ptr(s_list), _ptr(j_list), len(s_list), _ptr(out))
+                     int(seed), _ptr(b), _ptr(s_list), _ptr(j_list), len(s_list), _ptr(out))
     return out
 
 
 def photons_all(seg: dict, atm: Atmosphere, kind: str, seed: int, offsets, *,
-                lambda_nm=(300.0, 600.0), yield_per_MeV=10.0, lines_nm=None, line_rel=None):
+                lambda_nm=(300.0, 600.0), yield_per_MeV=10.0, lines_nm=None, line_rel=None, beam=None):
     """Every photon in slot order (offsets has n+1 entries)."""
     S = Segments(seg)
     kd, par, ln, lr, nl = _gen_args(kind, lambda_nm, yield_per_MeV, lines_nm, line_rel)
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     out = np.zeros(int(off[-1]), PHOTON_DTYPE)
+    b = _beam_arr(beam)
     lib().or_photons_all(C.byref(S.c), C.byref(atm.c), kd, _ptr(par), _ptr(ln), _ptr(lr), nl,
-                         int(seed), _ptr(off), _ptr(out))
+                         int(seed), _ptr(b), _ptr(off), _ptr(out))
     return out
 
 

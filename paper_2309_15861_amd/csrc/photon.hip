@@ -72,6 +72,7 @@ struct GenParams {
   double K;                             // Frank-Tamm prefactor (Cherenkov) or yield per MeV
   uint64_t thr[PHOTON_MAX_LINES];       // fluorescence line thresholds on the 32-bit word
   double line_nm[PHOTON_MAX_LINES];
+  BeamDev beam;                         // fluorescence beaming (on = 0: isotropic)
 };
 
 // Candidate grid of the telescope test: a landed photon whose arrival
@@ -170,7 +171,8 @@ __device__ __forceinline__ int64_t lane_upper_index(const uint64_t* off, int64_t
 // with LDS atomics (integer sums: the order does not matter).
 template <int KIND>
 __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, AtmDev atm, double K, uint32_t k0,
-                                                      uint32_t k1, CutDev cut, uint32_t* __restrict__ counts,
+                                                      uint32_t k1, CutDev cut, BeamDev beam,
+                                                      uint32_t* __restrict__ counts,
                                                       uint64_t* __restrict__ offsets) {
   __shared__ unsigned long long part[kScanBlock / kWaveSize];
   __shared__ double rk[kPoissonKmax + 1];
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
   if (i < n) {
 #pragma clang fp contract(off)
     const double mu = (KIND == PHOTON_CHERENKOV) ? (passes_cut(seg, i, cut) ? mean_cherenkov(seg, i, atm, K) : 0.0)
-                                                 : mean_fluor(seg, i, K);
+                                                 : beamed_mean(seg, i, beam, mean_fluor(seg, i, K));
     m = poisson_chunks(mu);
     if (m) {
       mc = mu / (double)m;
@@ -296,7 +298,7 @@ __device__ __forceinline__ void generate(const SegConst<T>& c, uint32_t j, const
   if (g.kind == PHOTON_CHERENKOV)
     gen_cherenkov<T>(c, j, k0, k1, (T)g.inv_l1, (T)g.inv_dl, p);
   else
-    gen_fluor<T>(c, j, k0, k1, thr, lines, g.n_lines, p);
+    gen_fluor<T>(c, j, k0, k1, thr, lines, g.n_lines, g.beam.on != 0, p);
 }
 
 template <typename T>
@@ -317,7 +319,7 @@ __global__ __launch_bounds__(256) void k_gen(SegView seg, int64_t n_seg, AtmDev 
   if ((uint64_t)q < offsets[n_seg]) {
     const int64_t s = lane_upper_index(offsets, n_seg, (uint64_t)q);
     SegConst<T> c;
-    seg_const<T>(seg, s, atm, g.kind == PHOTON_CHERENKOV, c);
+    seg_const<T>(seg, s, atm, g.kind == PHOTON_CHERENKOV, g.beam, c);
     j = (uint32_t)((uint64_t)q - offsets[s]);
     generate<T>(c, j, g, k0, k1, s_thr, s_lines, p);
     s32 = (uint32_t)s;
@@ -748,7 +750,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
     const bool win = W >= 1 && W <= kWin;
     if (win) {
       for (int t = tid; t < W; t += BS) {
-        seg_const<T>(A.seg, lo + t, A.atm, cher, s_seg[t]);
+        seg_const<T>(A.seg, lo + t, A.atm, cher, A.g.beam, s_seg[t]);
         if constexpr (SPLAT) s_wsc[t] = splat_wscale<T>(A, lo + t);
         s_off[t] = offsets[lo + t];
       }
@@ -808,7 +810,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
           s = lo + a;
         } else {
           s = lane_upper_index(offsets, n_seg, q);
-          seg_const<T>(A.seg, s, A.atm, cher, c);
+          seg_const<T>(A.seg, s, A.atm, cher, A.g.beam, c);
           if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
           off_s = offsets[s];
         }
@@ -938,7 +940,7 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     const uint2 e = A.defer_q[(uint64_t)lo * (uint64_t)A.defer_cap + (g - pref[lo])];
     const int64_t s = e.x < (uint32_t)A.n_seg ? (int64_t)e.x : A.n_seg - 1;
     SegConst<double> c;
-    seg_const<double>(A.seg, s, A.atm, cher, c);
+    seg_const<double>(A.seg, s, A.atm, cher, A.g.beam, c);
     Photon<double> p;
     generate<double>(c, e.y, A.g, A.k0, A.k1, s_thr, s_lines, p);
     propagate<double>(A.atm, s_lane, p);
@@ -1231,11 +1233,11 @@ __global__ __launch_bounds__(256) void k_splat_finish(const unsigned long long* 
 // evaluation as the count kernel's.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_means(SegView seg, int64_t n, AtmDev atm, double K, CutDev cut,
-                                               double* mean) {
+                                               BeamDev beam, double* mean) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   mean[i] = KIND == PHOTON_CHERENKOV ? (passes_cut(seg, i, cut) ? mean_cherenkov(seg, i, atm, K) : 0.0)
-                                     : mean_fluor(seg, i, K);
+                                     : beamed_mean(seg, i, beam, mean_fluor(seg, i, K));
 }
 
 // ------------------------------------------------------------ host helpers --
@@ -1369,6 +1371,22 @@ int prep_emission(const photon_emission* em, GenParams* g) {
     // u3 < cdf[k]  <=>  (w + 1/2) 2^-32 < cdf[k]  <=>  w < ceil(cdf[k] 2^32 - 1/2)
     g->thr[k] = (uint64_t)std::ceil(std::ldexp(cdf[kk], 32) - 0.5);
     g->line_nm[k] = em->line_nm[kk];
+  }
+  if (em->beam != 0) {
+    if (em->beam != 1) return fail(PHOTON_EINVAL, "beam must be 0 or 1");
+    for (int d = 0; d < 3; ++d)
+      if (!finite(em->beam_center[d])) return fail(PHOTON_EINVAL, "beam_center not finite");
+    if (!(em->beam_radius >= 0.0) || !finite(em->beam_radius))
+      return fail(PHOTON_EINVAL, "beam_radius must be finite and >= 0");
+    if (!(em->beam_margin_rad >= 0.0) || !(em->beam_margin_rad <= 0.5 * kPi))
+      return fail(PHOTON_EINVAL, "beam_margin_rad must lie in [0, pi/2]");
+    g->beam.on = 1;
+    g->beam.cx = em->beam_center[0];
+    g->beam.cy = em->beam_center[1];
+    g->beam.cz = em->beam_center[2];
+    g->beam.r = em->beam_radius;
+    g->beam.cos_m = std::cos(em->beam_margin_rad);
+    g->beam.sin_m = std::sin(em->beam_margin_rad);
   }
   return PHOTON_OK;
 }
@@ -1560,7 +1578,7 @@ int check_launch() {
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int count_and_scan(const SegView& sv, int64_t n, const AtmDev& atm, int kind, double K, const CutDev& cut,
-                   uint64_t seed, uint32_t* counts, uint64_t* offsets, hipStream_t st) {
+                   const BeamDev& beam, uint64_t seed, uint32_t* counts, uint64_t* offsets, hipStream_t st) {
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   if (n == 0) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)offsets, 1);
@@ -1569,10 +1587,10 @@ int count_and_scan(const SegView& sv, int64_t n, const AtmDev& atm, int kind, do
   const int64_t nb = ceil_div(n, kScanBlock);
   if (kind == PHOTON_CHERENKOV)
     hipLaunchKernelGGL(k_count<PHOTON_CHERENKOV>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0, k1,
-                       cut, counts, offsets);
+                       cut, beam, counts, offsets);
   else
     hipLaunchKernelGGL(k_count<PHOTON_FLUORESCENCE>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0,
-                       k1, cut, counts, offsets);
+                       k1, cut, beam, counts, offsets);
   hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(1024), 0, st, offsets, n, nb);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanBlock), 0, st, (const uint32_t*)counts, offsets, n);
   return check_launch();
@@ -1615,7 +1633,7 @@ int generate_common(const photon_segments* seg, const photon_atmosphere* atm, co
     const double K = (em->kind == PHOTON_CHERENKOV)
                          ? (2.0 * kPi * kAlpha) * ((1e9 / em->lambda_min_nm) - (1e9 / em->lambda_max_nm))
                          : em->yield_per_MeV;
-    return count_and_scan(sv, seg->n, ad, em->kind, K, cut, seed, counts, offsets, st);
+    return count_and_scan(sv, seg->n, ad, em->kind, K, cut, g.beam, seed, counts, offsets, st);
   }
   return precision == PHOTON_FP64 ? launch_gen<double>(sv, seg->n, ad, g, seed, offsets, out, st)
                                   : launch_gen<float>(sv, seg->n, ad, g, seed, offsets, out, st);
@@ -1825,7 +1843,7 @@ int enqueue_fused(const StepArgs& a, const uint64_t* offsets, int64_t n_ph, cons
 int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const photon_tuning* tun,
                  DeviceState* dev, hipStream_t st) {
   int rc;
-  if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.cut, a.seed, counts, offsets, st))) return rc;
+  if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.cut, a.g.beam, a.seed, counts, offsets, st))) return rc;
   if ((rc = clear_sink(a.sk, st))) return rc;
   return enqueue_fused(a, offsets, -1, tun, dev, st);
 }
@@ -2183,6 +2201,13 @@ int photon_count(const photon_segments* seg, const photon_atmosphere* atm, const
   return generate_common(seg, atm, em, seed, PHOTON_FP64, counts, offsets, nullptr, stream);
 }
 
+int photon_generate(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                    uint64_t seed, int32_t precision, const uint64_t* offsets, photon_block* out, void* stream) {
+  if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
+  if (!out) return fail(PHOTON_EINVAL, "photon block is NULL");
+  return generate_common(seg, atm, em, seed, precision, nullptr, const_cast<uint64_t*>(offsets), out, stream);
+}
+
 int photon_means(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em, double* mean,
                  void* stream) {
   SegView sv;
@@ -2203,10 +2228,10 @@ int photon_means(const photon_segments* seg, const photon_atmosphere* atm, const
   const unsigned nb = (unsigned)ceil_div(seg->n, 256);
   if (em->kind == PHOTON_CHERENKOV) {
     const double K = (2.0 * kPi * kAlpha) * ((1e9 / em->lambda_min_nm) - (1e9 / em->lambda_max_nm));
-    hipLaunchKernelGGL(k_means<PHOTON_CHERENKOV>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, K, cut, mean);
+    hipLaunchKernelGGL(k_means<PHOTON_CHERENKOV>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, K, cut, g.beam, mean);
   } else {
     hipLaunchKernelGGL(k_means<PHOTON_FLUORESCENCE>, dim3(nb), dim3(256), 0, st, sv, seg->n, ad, em->yield_per_MeV, cut,
-                       mean);
+                       g.beam, mean);
   }
   return check_launch();
 }

@@ -189,6 +189,59 @@ __device__ __forceinline__ bool passes_cut(const SegView& s, int64_t i, const Cu
   return false;
 }
 
+// Fluorescence beaming (the optimisation of section 1.1.1): a track emits
+// into a cone that contains an emission area enclosing every telescope, a
+// sphere of centre c and radius r, and its photon number is scaled by the
+// cone's solid-angle fraction. Seen from the track midpoint m, at distance D
+// from c, the sphere grown by half the track length (which contains the
+// sphere as seen from every point of the track) subtends the half angle
+// alpha, sin(alpha) = (r + L/2)/D; the cone adds a margin for the bending of
+// rays by refraction. Returns om = 1 - cos(alpha + margin), so that the
+// solid-angle fraction is om/2, and the unit cone axis (m to c). A track
+// inside the grown sphere stays isotropic: om = 2, axis straight down. FP64
+// without contraction in a fixed order, like the angular cut.
+struct BeamDev {
+  int32_t on;
+  double cx, cy, cz, r;
+  double cos_m, sin_m;  // cosine and sine of the margin angle
+};
+
+__device__ __forceinline__ double beam_cap(const SegView& s, int64_t i, const BeamDev& b, double* ax, double* ay,
+                                           double* az) {
+#pragma clang fp contract(off)
+  const double dx = s.dx[i], dy = s.dy[i], dz = s.dz[i];
+  const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
+  const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+  const double hl = 0.5 * s.len[i];
+  const double mx = s.x0[i] + hl * ux, my = s.y0[i] + hl * uy, mz = s.z0[i] + hl * uz;
+  const double vx = b.cx - mx, vy = b.cy - my, vz = b.cz - mz;
+  const double D = sqrt((vx * vx + vy * vy) + vz * vz);
+  const double reach = b.r + hl;
+  if (!(reach < D)) {
+    *ax = 0.0;
+    *ay = 0.0;
+    *az = -1.0;
+    return 2.0;
+  }
+  const double sa = reach / D;
+  const double ca = sqrt((1.0 - sa) * (1.0 + sa));
+  const double cb = ca * b.cos_m - sa * b.sin_m;
+  *ax = vx / D;
+  *ay = vy / D;
+  *az = vz / D;
+  return 1.0 - cb;
+}
+
+// Mean photon number of a fluorescence segment with beaming: the isotropic
+// mean times the cone's solid-angle fraction.
+__device__ __forceinline__ double beamed_mean(const SegView& s, int64_t i, const BeamDev& b, double mu) {
+#pragma clang fp contract(off)
+  if (!b.on || !(mu > 0.0)) return mu;
+  double ax, ay, az;
+  const double om = beam_cap(s, i, b, &ax, &ay, &az);
+  return mu * (0.5 * om);
+}
+
 // Chunking of a mean for the Poisson draw: m chunks of mean mc (m = 0 when
 // the segment emits nothing).
 __device__ __forceinline__ uint32_t poisson_chunks(double mu) {
@@ -244,18 +297,37 @@ template <typename T>
 struct SegConst {
   double x0, y0, z0, t0, inv_bc;   // start point, start time, 1/(beta c)
   T dx, dy, dz, len;               // unit direction, length
-  T cos_c, sin_c;                  // Cherenkov cone (section 1.2)
-  T ax, ay, az;                    // unit bisector of direction and (0,0,-1)
+  T cos_c, sin_c;                  // Cherenkov cone (section 1.2); beamed fluorescence: cos_c = om
+  T ax, ay, az;                    // unit bisector of the cone axis and (0,0,-1)
   uint32_t idx, shower;
 };
 
-// Unit bisector A of the track direction d and the downward normal: M_Rod
+// Unit bisector A of a cone axis d and the downward normal: M_Rod
 // (section 1.2.1) is the half turn 2 A A^T - 1 about it, which maps the
 // downward axis onto d. For d straight up the bisector vanishes and the
 // half turn about x is used.
+__device__ __forceinline__ void rod_bisector(double ux, double uy, double uz, double* bx, double* by, double* bz) {
+  double x = ux, y = uy, z = uz - 1.0;
+  const double bn = sqrt((x * x + y * y) + z * z);
+  if (bn > 0.0) {
+    x /= bn;
+    y /= bn;
+    z /= bn;
+  } else {
+    x = 1.0;
+    y = 0.0;
+    z = 0.0;
+  }
+  *bx = x;
+  *by = y;
+  *bz = z;
+}
+
+// The cone axis is the track direction for Cherenkov light and the beaming
+// axis for beamed fluorescence.
 template <typename T>
 __device__ __forceinline__ void seg_const(const SegView& s, int64_t i, const AtmDev& a, bool cherenkov,
-                                          SegConst<T>& c) {
+                                          const BeamDev& beam, SegConst<T>& c) {
   const double dx = s.dx[i], dy = s.dy[i], dz = s.dz[i];
   const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
   const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
@@ -275,17 +347,16 @@ __device__ __forceinline__ void seg_const(const SegView& s, int64_t i, const Atm
     const double cc = 1.0 / (s.beta[i] * n);
     c.cos_c = (T)cc;
     c.sin_c = (T)sqrt((1.0 - cc) * (1.0 + cc));
-    double bx = ux, by = uy, bz = uz - 1.0;
-    const double bn = sqrt((bx * bx + by * by) + bz * bz);
-    if (bn > 0.0) {
-      bx /= bn;
-      by /= bn;
-      bz /= bn;
-    } else {
-      bx = 1.0;
-      by = 0.0;
-      bz = 0.0;
-    }
+    double bx, by, bz;
+    rod_bisector(ux, uy, uz, &bx, &by, &bz);
+    c.ax = (T)bx;
+    c.ay = (T)by;
+    c.az = (T)bz;
+  } else if (beam.on) {
+    double ax, ay, az, bx, by, bz;
+    c.cos_c = (T)beam_cap(s, i, beam, &ax, &ay, &az);
+    c.sin_c = (T)0;
+    rod_bisector(ax, ay, az, &bx, &by, &bz);
     c.ax = (T)bx;
     c.ay = (T)by;
     c.az = (T)bz;
@@ -349,10 +420,13 @@ __device__ __forceinline__ void gen_cherenkov(const SegConst<T>& c, uint32_t j, 
 // Photon j of a fluorescence segment (section 1.1): isotropic direction,
 // emission point u0 along the track, line k = smallest k with u3 < cdf[k],
 // decided exactly on the 32-bit word against integer thresholds
-// thr[k] = ceil(cdf[k] 2^32 - 1/2).
+// thr[k] = ceil(cdf[k] 2^32 - 1/2). Beamed (section 1.1.1): uniform on the
+// segment's cone, 1 - cos(theta) = u1 om from the axis and azimuth 2 pi u2,
+// generated about the downward normal and turned onto the axis by M_Rod.
 template <typename T>
 __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint32_t k0, uint32_t k1,
-                                          const uint64_t* thr, const T* line_nm, int n_lines, Photon<T>& p) {
+                                          const uint64_t* thr, const T* line_nm, int n_lines, bool beam,
+                                          Photon<T>& p) {
   const U4 r = philox(j, c.idx, c.shower, kDomFluo, k0, k1);
   const T u0 = u01<T>(r.w[0]), u1 = u01<T>(r.w[1]), u2 = u01<T>(r.w[2]);
   const T s = u0 * c.len;
@@ -360,19 +434,33 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
   p.y = (T)c.y0 + s * c.dy;
   p.z = c.z0 + (double)(s * c.dz);
   p.t = c.t0 + (double)s * c.inv_bc;
-  // cos = 1 - 2 u1 = -(w - 2^31 + 1/2) 2^-31, and 1 - u1 = u(~w): both taken
-  // from the 32-bit word, so rays near the horizon keep their relative
-  // precision in either arithmetic
-  const int32_t sw = (int32_t)(r.w[1] ^ 0x80000000u);
-  const double ctd = -((double)sw + 0.5) * 0x1p-31;
-  const T ct = (T)ctd;
-  const T st = (T)2 * sqrt(u01<T>(r.w[1]) * u01<T>(~r.w[1]));
-  T sp, cp;
-  sincos2pi(u2, &sp, &cp);
-  p.ux = st * cp;
-  p.uy = st * sp;
-  p.uz = ct;
-  p.uzd = ctd;
+  if (beam) {
+    const T v = u1 * c.cos_c;
+    const T ct = (T)1 - v;
+    const T st = sqrt(v * ((T)2 - v));
+    T sp, cp;
+    sincos2pi(u2, &sp, &cp);
+    const T px = st * cp, py = st * sp, pz = -ct;
+    const T ap2 = (T)2 * (c.ax * px + c.ay * py + c.az * pz);
+    p.ux = ap2 * c.ax - px;
+    p.uy = ap2 * c.ay - py;
+    p.uz = ap2 * c.az - pz;
+    p.uzd = (double)p.uz;
+  } else {
+    // cos = 1 - 2 u1 = -(w - 2^31 + 1/2) 2^-31, and 1 - u1 = u(~w): both
+    // taken from the 32-bit word, so rays near the horizon keep their
+    // relative precision in either arithmetic
+    const int32_t sw = (int32_t)(r.w[1] ^ 0x80000000u);
+    const double ctd = -((double)sw + 0.5) * 0x1p-31;
+    const T ct = (T)ctd;
+    const T st = (T)2 * sqrt(u01<T>(r.w[1]) * u01<T>(~r.w[1]));
+    T sp, cp;
+    sincos2pi(u2, &sp, &cp);
+    p.ux = st * cp;
+    p.uy = st * sp;
+    p.uz = ct;
+    p.uzd = ctd;
+  }
   int k = 0;
   const uint64_t w3 = r.w[3];
   while (k < n_lines - 1 && !(w3 < thr[k])) ++k;

@@ -46,7 +46,9 @@ class Emission(C.Structure):
                 ("yield_per_MeV", C.c_double), ("n_lines", C.c_int32),
                 ("line_nm", C.c_double * MAX_LINES), ("line_rel_yield", C.c_double * MAX_LINES),
                 ("n_cut_points", C.c_int32), ("cut_cos", C.c_double),
-                ("cut_points", (C.c_double * 3) * MAX_CUT_POINTS)]
+                ("cut_points", (C.c_double * 3) * MAX_CUT_POINTS),
+                ("beam", C.c_int32), ("beam_center", C.c_double * 3), ("beam_radius", C.c_double),
+                ("beam_margin_rad", C.c_double)]
 
 
 class Block(C.Structure):
@@ -107,6 +109,7 @@ def lib():
         L.photon_autotune.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P, C.c_int32, C.c_int32, P, P, P]
         L.photon_means.argtypes = [P, P, P, P, P]
         L.photon_count.argtypes = [P, P, P, C.c_uint64, P, P, P]
+        L.photon_generate.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
@@ -320,7 +323,10 @@ def emission_cherenkov(lmin=300.0, lmax=600.0, cut_points=None, cut_angle_deg=6.
     return e
 
 
-def emission_fluor(line_nm, line_rel, yield_per_MeV) -> Emission:
+def emission_fluor(line_nm, line_rel, yield_per_MeV, beam_area=None, beam_margin_deg=1.0) -> Emission:
+    """Fluorescence emission; beam_area = (centre (3,), radius) beams every
+    segment into the cone that contains that sphere (plus beam_margin_deg),
+    with the photon number scaled by the cone's solid-angle fraction."""
     e = Emission()
     e.kind = FLUORESCENCE
     e.yield_per_MeV = float(yield_per_MeV)
@@ -328,7 +334,22 @@ def emission_fluor(line_nm, line_rel, yield_per_MeV) -> Emission:
     for k in range(min(len(line_nm), MAX_LINES)):
         e.line_nm[k] = float(line_nm[k])
         e.line_rel_yield[k] = float(line_rel[k])
+    if beam_area is not None:
+        c, r = beam_area
+        e.beam = 1
+        for d in range(3):
+            e.beam_center[d] = float(c[d])
+        e.beam_radius = float(r)
+        e.beam_margin_rad = float(np.radians(beam_margin_deg))
     return e
+
+
+def enclosing_sphere(tel) -> tuple:
+    """(centre, radius) of a sphere around telescope spheres (rows x, y, z, R):
+    centred on the mean of their centres, reaching the far side of each."""
+    tel = np.asarray(tel, np.float64).reshape(-1, 4)
+    c = tel[:, :3].mean(axis=0)
+    return c, float(np.max(np.linalg.norm(tel[:, :3] - c, axis=1) + tel[:, 3]))
 
 
 # --------------------------------------------------------------- entry points --
@@ -365,12 +386,10 @@ def count(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, device="cuda
 
 def generate(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precision, offsets,
              block: PhotonBlock):
-    dummy = offsets  # counts are not written when a block is given
-    if em.kind == CHERENKOV:
-        gen_cherenkov(seg, atm, em.lambda_min_nm, em.lambda_max_nm, seed, precision, dummy, offsets, block)
-    else:
-        gen_fluor(seg, atm, list(em.line_nm)[:em.n_lines], list(em.line_rel_yield)[:em.n_lines],
-                  em.yield_per_MeV, seed, precision, dummy, offsets, block)
+    """Fills the block for the emission model (beaming included)."""
+    s = seg.struct()
+    _check(lib().photon_generate(C.byref(s), C.byref(atm), C.byref(em), int(seed), int(precision),
+                                 _ptr(offsets), C.byref(block.struct()), _stream()))
 
 
 def propagate(block: PhotonBlock, atm: Atmosphere):

@@ -184,6 +184,26 @@ def fluorescence(n: int = 100_000, seed: int = 3) -> dict:
     return seg
 
 
+def fluorescence_near_array(n: int = 400, seed: int = 6) -> dict:
+    """Fluorescence tracks 0.3..2.8 km above the observation level within
+    800 m of the array centre, isotropic directions, lengths 5..30 m, dE/dx
+    log-uniform 1..10 MeV/m: close enough that isotropic emission hits the
+    telescopes often, for comparing beamed and isotropic emission."""
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(-800.0, 800.0, n)
+    y0 = rng.uniform(-800.0, 800.0, n)
+    z0 = H_OBS + rng.uniform(300.0, 2800.0, n)
+    ct = rng.uniform(-1.0, 1.0, n)
+    phi = rng.uniform(0.0, 2.0 * np.pi, n)
+    st = np.sqrt(1.0 - ct * ct)
+    d = np.stack([st * np.cos(phi), st * np.sin(phi), ct], axis=1)
+    length = rng.uniform(5.0, 30.0, n)
+    e = np.exp(rng.uniform(np.log(50.0), np.log(5000.0), n))
+    seg = _segments(n, x0, y0, z0, d, length, e, np.zeros(n))
+    seg["dedx"] = np.exp(rng.uniform(0.0, np.log(10.0), n))
+    return seg
+
+
 def fluorescence_lines(seed: int = 3, n_lines: int = 21):
     """21 emission lines, wavelengths sorted U(300,430) nm, relative yields
     U(0.05,1)."""

@@ -229,3 +229,32 @@ def test_cut_validation(ph):
     em = ph.emission_cherenkov(cut_points=[[0.0, float("inf"), 2200.0]])
     assert count(em) == ph.EINVAL
     assert b"not finite" in L.photon_last_error()
+
+
+def test_beam_validation(ph):
+    """Fluorescence beaming is validated before any device work."""
+    L = ph.lib()
+    atm = _valid_atm(ph)
+    seg = _fake_segments(ph)
+    seg.dedx = 0x1000
+
+    def count(em):
+        return L.photon_count(C.byref(seg), C.byref(atm), C.byref(em), 1, 0x2000, 0x3000, None)
+
+    def em(**kw):
+        e = ph.emission_fluor([391.0], [1.0], 10.0, beam_area=((0.0, 0.0, 2200.0), 200.0))
+        for k, v in kw.items():
+            setattr(e, k, v)
+        return e
+
+    assert count(em()) == ph.ENODEV
+    assert count(em(beam=2)) == ph.EINVAL
+    assert count(em(beam_radius=-1.0)) == ph.EINVAL
+    assert count(em(beam_radius=float("nan"))) == ph.EINVAL
+    assert count(em(beam_margin_rad=-0.1)) == ph.EINVAL
+    assert count(em(beam_margin_rad=2.0)) == ph.EINVAL
+    e = em()
+    e.beam_center[1] = float("inf")
+    assert count(e) == ph.EINVAL
+    # photon_generate needs a block
+    assert L.photon_generate(C.byref(seg), C.byref(atm), C.byref(em()), 1, 0, 0x3000, None, None) == ph.EINVAL
