@@ -221,6 +221,47 @@ def fluorescence_beaming(args, best):
     return out
 
 
+def radial_profile(args, d, atm, seed, best):
+    """The shower step collected as the radial profiles of section 3.1
+    (100 bins uniform in ln r from 1 m to 3 km about the core): step time and
+    a few points of the photon density and mean arrival time."""
+    import numpy as np
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+
+    em = ph.emission_cherenkov(300.0, 600.0)
+    prof = ph.RadialProfile(100, 1.0, 3000.0, log_bins=True, t_ref_ns=0.0)
+    counts = torch.empty(d.n, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(d.n + 1, dtype=torch.int64, device="cuda")
+    totals = ph.status_totals()
+    plan = ph.Plan(d, atm, em, seed, ph.FP32, counts, offsets, ph.sink_radial(prof, totals), best)
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    plan.close()
+    photons = int(offsets[-1].item())
+    dens, mt = (x.cpu().numpy() for x in ph.radial_profile(prof))
+    cnt = prof.count.cpu().numpy()
+    e = prof.edges()
+    mid = np.sqrt(e[:-1] * e[1:])
+    points = {}
+    for r in (30.0, 100.0, 150.0, 300.0, 1000.0):
+        k = int(np.searchsorted(e, r) - 1)
+        points[f"{r:g} m"] = dict(density_per_m2=float(dens[k]), mean_t_ns=float(mt[k]), photons=int(cnt[k]))
+    return dict(bins="100, uniform in ln r, 1 m..3 km", photons=photons, binned=int(cnt.sum()), ms_per_step=ms,
+                photons_per_s=photons / (ms * 1e-3), at_r=points,
+                peak_density_r_m=float(mid[int(np.argmax(dens))]))
+
+
 def differentiable(args):
     """The differentiable form at 1e6 segments: splatted ground density
     (128 x 128 cells of 5 m, sigma 5 m) with counts frozen at the nominal
@@ -285,6 +326,8 @@ def main():
                          "(profiling runs)")
     ap.add_argument("--cut", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the shower step with the 6 degree Cherenkov angular particle cut")
+    ap.add_argument("--radial", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the shower step collected as radial density and arrival-time profiles")
     ap.add_argument("--beam", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the fluorescence step with isotropic and beamed emission")
     ap.add_argument("--adjoint", action=argparse.BooleanOptionalAction, default=True,
@@ -371,7 +414,7 @@ def main():
     achieved = SLOTS_PER_PHOTON["fp32"] * total / (r32["fused_ms"] * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=achieved / PEAK_SLOTS, traffic=traffic_per_launch(),
-                    kernel=f"k_fused<float,{r32['tuning'][0]},false>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
+                    kernel=f"k_fused<float,{r32['tuning'][0]},false,false>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
                     fused_ms=r32["fused_ms"], tuning=r32["tuning"])
     r64 = results.get("fp64", r32)
     out = {
@@ -390,6 +433,8 @@ def main():
     if args.cut:
         out["angular_cut"] = angular_cut(args, d, atm, tel, seed, ph.tuning(*r32["tuning"]),
                                          dict(photons=total, hits=r32["hits"], ms_per_step=r32["ms_per_step"]))
+    if args.radial:
+        out["radial_profile"] = radial_profile(args, d, atm, seed, ph.tuning(*r32["tuning"]))
     if args.beam:
         out["fluorescence_beaming"] = fluorescence_beaming(args, ph.tuning(*r32["tuning"]))
     if args.batched:

@@ -81,12 +81,14 @@ extern "C" {
 #define PHOTON_SINK_TELESCOPES 1
 #define PHOTON_SINK_GRID 2
 #define PHOTON_SINK_PLANE 3     /* every photon written at its slot         */
+#define PHOTON_SINK_RADIAL 4    /* radial density and arrival-time profile  */
 
 #define PHOTON_MAX_LAYERS 8
 #define PHOTON_MAX_ABS 40
 #define PHOTON_MAX_LINES 32
 #define PHOTON_MAX_TELESCOPES 32
 #define PHOTON_MAX_CUT_POINTS 32
+#define PHOTON_MAX_RADIAL_BINS 1024
 
 /* Plane-parallel atmosphere (host struct). Layer i covers
    [h_base[i], h_base[i+1]); layer 0 extends below h_base[0] = 0 and the top
@@ -209,7 +211,15 @@ typedef struct {
    every photon's final state is written at its slot q = offsets[s] + j of
    `plane` (arrays of the run's precision, capacity >= number of photons;
    slots beyond the capacity are not written), as photon_propagate leaves a
-   photon block. */
+   photon block. RADIAL (the profiles of section 3.1): a landed photon at
+   distance r = |(x, y) - (core_x, core_y)| from the core falls in bin
+   k = floor((r - r_min) n_bins / (r_max - r_min)) (log_bins = 0) or
+   k = floor(ln(r / r_min) n_bins / ln(r_max / r_min)) (log_bins = 1,
+   r_min > 0), FP64, when 0 <= k < n_bins (1..1024 bins), else its status
+   becomes OFFGRID. Per bin, radial_count counts photons, radial_weight sums
+   their weights in units of 2^-32 and radial_wt sums w (t - t_ref_ns), each
+   term rounded to units of 2^-8 ns, as two's-complement int64 in the u64
+   array. Integer sums: the result does not depend on the order. */
 typedef struct {
   int32_t kind;
   unsigned long long *status_totals;
@@ -221,6 +231,9 @@ typedef struct {
   uint32_t *grid_count;
   unsigned long long *grid_weight;
   const photon_block *plane;
+  double core_x, core_y, r_min, r_max, t_ref_ns;
+  int32_t n_bins, log_bins;
+  unsigned long long *radial_count, *radial_weight, *radial_wt;
 } photon_sink;
 
 /* Launch shape of the fused kernel: threads per block (64..1024, multiple
@@ -350,6 +363,14 @@ typedef struct {
   int32_t nx, ny;
   double sigma, trunc;
 } photon_splat_grid;
+
+/* Radial profiles from the accumulators of a RADIAL sink (section 3.1):
+   density[k] = (sum of weights) / (pi (r_{k+1}^2 - r_k^2)) [photons/m^2]
+   and mean_t_ns[k] = t_ref_ns + (sum of w (t - t_ref)) / (sum of weights),
+   NaN where a bin holds no weight; bin edges r_k as the sink defines them.
+   density and mean_t_ns: device f64[n_bins]. Errors: EINVAL (the sink's
+   RADIAL fields as photon_run_fused checks them, NULL outputs). */
+int photon_radial_profile(const photon_sink* sink, double* density, double* mean_t_ns, void* stream);
 
 /* Per-segment counts and offsets for an emission model (as the generation
    calls with out == NULL), honouring the Cherenkov angular particle cut of

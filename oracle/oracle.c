@@ -752,6 +752,29 @@ void or_photons_all(const or_segments* s, const or_atmosphere* a, int kind, cons
   }
 }
 
+/* Radial profile bin of each photon (section 3.1: density and mean
+   arrival time in rings about the shower core): the k with
+   edges[k] <= r < edges[k+1], r the distance of the landing point from
+   (cx, cy); -1 for photons that did not land or fall outside the edges.
+   Found by bisection over the n_bins + 1 increasing edges. */
+void or_radial_bins(const or_photon* ph, int64_t count, double cx, double cy, const double* edges, int32_t n_bins,
+                    int32_t* bin) {
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < count; ++q) {
+    bin[q] = -1;
+    if (ph[q].status != OR_LANDED) continue;
+    double dx = ph[q].xl - cx, dy = ph[q].yl - cy;
+    double r = sqrt(dx * dx + dy * dy);
+    if (!(r >= edges[0]) || !(r < edges[n_bins])) continue;
+    int32_t lo = 0, hi = n_bins; /* edges[lo] <= r < edges[hi] */
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) / 2;
+      if (edges[mid] <= r) lo = mid; else hi = mid;
+    }
+    bin[q] = lo;
+  }
+}
+
 void or_telescopes(const or_photon* ph, int64_t count, const double* tel, int32_t n_tel,
                    double n_obs, int32_t* tel_id, double* hits /* 5 per photon */) {
 #pragma omp parallel for schedule(static)

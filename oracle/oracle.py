@@ -93,6 +93,7 @@ def lib():
         L.or_photons.argtypes = [P, P, C.c_int, P, P, P, C.c_int32, C.c_uint64, P, P, P, C.c_int64, P]
         L.or_photons_all.argtypes = [P, P, C.c_int, P, P, P, C.c_int32, C.c_uint64, P, P, P]
         L.or_telescopes.argtypes = [P, C.c_int64, P, C.c_int32, C.c_double, P, P]
+        L.or_radial_bins.argtypes = [P, C.c_int64, C.c_double, C.c_double, P, C.c_int32, P]
         L.or_grid.argtypes = [P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32,
                               C.c_int32, P]
         L.or_splat.argtypes = [P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
@@ -325,6 +326,38 @@ def telescopes(ph: np.ndarray, tel: np.ndarray, n_obs: float):
     lib().or_telescopes(_ptr(ph), len(ph), _ptr(tel), tel.shape[0], float(n_obs), _ptr(tid),
                         _ptr(hits))
     return tid, hits
+
+
+def radial_edges(n_bins, r_min, r_max, log_bins):
+    """Bin edges: uniform in r, or in ln r (r_min > 0); the last is r_max."""
+    k = np.arange(n_bins + 1) / n_bins
+    e = r_min * (r_max / r_min) ** k if log_bins else r_min + (r_max - r_min) * k
+    e[-1] = r_max
+    return e
+
+
+def radial_bins(ph: np.ndarray, core, edges):
+    """Bin per photon (-1: not landed or outside the edges)."""
+    ph = np.ascontiguousarray(ph)
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    out = np.zeros(len(ph), np.int32)
+    lib().or_radial_bins(_ptr(ph), len(ph), float(core[0]), float(core[1]), _ptr(e), len(e) - 1, _ptr(out))
+    return out
+
+
+def radial_profile(ph: np.ndarray, core, edges, t_ref=0.0):
+    """Section 3.1 profiles: per bin (count, sum of weights, density in
+    photons/m^2 = weight / ring area, mean arrival time weighted by w)."""
+    b = radial_bins(ph, core, edges)
+    n = len(edges) - 1
+    m = b >= 0
+    cnt = np.bincount(b[m], minlength=n)
+    w = np.bincount(b[m], weights=ph["weight"][m], minlength=n)
+    wt = np.bincount(b[m], weights=ph["weight"][m] * (ph["tl"][m] - t_ref), minlength=n)
+    area = np.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean_t = np.where(w > 0, t_ref + wt / w, np.nan)
+    return cnt, w, w / area, mean_t
 
 
 def grid(ph: np.ndarray, x_min, y_min, cell, nx, ny):

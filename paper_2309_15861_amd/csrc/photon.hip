@@ -110,6 +110,10 @@ struct SinkDev {
   unsigned long long* splat_acc;
   const double* mu0;
   int32_t splat_lds;
+  // RADIAL: profile bins about the core (r_inv = bins per unit of r or ln r)
+  double core_x, core_y, r_min, r_inv, t_ref;
+  int32_t n_bins, log_bins;
+  unsigned long long *rad_count, *rad_w, *rad_wt;
 };
 // Sink of the differentiable form (reached through photon_splat_forward only).
 constexpr int32_t kSinkSplat = 16;
@@ -474,6 +478,24 @@ __device__ __forceinline__ void flush_hits(HitStage* st, const photon_hits& h) {
   if (threadIdx.x == 0) st->n = 0u;
 }
 
+// Radial profile bin of a landing point, or -1 outside [r_min, r_max).
+__device__ __forceinline__ int radial_bin(const SinkDev& sk, double x, double y) {
+#pragma clang fp contract(off)
+  const double dx = x - sk.core_x, dy = y - sk.core_y;
+  const double r = sqrt(dx * dx + dy * dy);
+  const double f = sk.log_bins ? log(r / sk.r_min) * sk.r_inv : (r - sk.r_min) * sk.r_inv;
+  return (f >= 0.0 && f < (double)sk.n_bins) ? (int)f : -1;
+}
+
+// Fixed-point terms of one photon: weight in units of 2^-32 and
+// w (t - t_ref) in units of 2^-8 ns (two's complement).
+__device__ __forceinline__ unsigned long long radial_wfix(double w) {
+  return (unsigned long long)(w * 4294967296.0 + 0.5);
+}
+__device__ __forceinline__ unsigned long long radial_tfix(double w, double t, double t_ref) {
+  return (unsigned long long)(long long)rint(w * (t - t_ref) * 256.0);
+}
+
 // LDS of the hit stage; the splat variant has none (its LDS holds the grid).
 template <bool SPLAT>
 struct HitStageLds {
@@ -488,20 +510,43 @@ struct HitStageLds<true> {
 // Applies the sink to one propagated photon (in the lanes that hold one);
 // returns the final status. Hit records are compacted per wave: one atomic
 // per wave reserves the slots, lanes write at their rank among the hits.
-// SPLAT: the sink of the differentiable form only (a separate instantiation,
-// so that the other sinks' kernels carry none of its code).
-template <typename T, bool SPLAT = false>
+// SPLAT: the sink of the differentiable form only; RADIAL: the radial
+// profile only (separate instantiations, so that the other sinks' kernels
+// carry none of their code). lds_acc: the block's LDS accumulator (the
+// splat grid, or the radial bins as count, weight, w t), or NULL to add to
+// the global arrays directly.
+template <typename T, bool SPLAT = false, bool RADIAL = false>
 __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], double n_obs, Photon<T>& p,
                                            uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q,
-                                           HitStage* stage, unsigned long long* splat_lds,
+                                           HitStage* stage, unsigned long long* lds_acc,
                                            const uint32_t* cand) {
   int st = active ? p.status : -1;
   if constexpr (SPLAT) {
     if (active && st == PHOTON_LANDED) {
       // one call per address space (no generic pointer)
-      const bool in = splat_lds ? splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, splat_lds)
-                                : splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, sk.splat_acc);
+      const bool in = lds_acc ? splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, lds_acc)
+                              : splat_add<T>(sk.sg, (double)p.x, (double)p.y, p.w, sk.splat_acc);
       if (!in) st = PHOTON_OFFGRID;
+    }
+  } else if constexpr (RADIAL) {
+    if (active && st == PHOTON_LANDED) {
+      const int k = radial_bin(sk, (double)p.x, (double)p.y);
+      if (k >= 0) {
+        const unsigned long long wf = radial_wfix((double)p.w);
+        const unsigned long long tf = radial_tfix((double)p.w, p.t, sk.t_ref);
+        // one branch per address space (no generic pointer)
+        if (lds_acc) {
+          atomicAdd(&lds_acc[k], 1ull);
+          atomicAdd(&lds_acc[sk.n_bins + k], wf);
+          atomicAdd(&lds_acc[2 * sk.n_bins + k], tf);
+        } else {
+          atomicAdd(&sk.rad_count[k], 1ull);
+          atomicAdd(&sk.rad_w[k], wf);
+          atomicAdd(&sk.rad_wt[k], tf);
+        }
+      } else {
+        st = PHOTON_OFFGRID;
+      }
     }
   } else if (sk.kind == PHOTON_SINK_PLANE) {
     if (active && slot_q < (uint64_t)sk.plane_capacity) {
@@ -622,7 +667,10 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
     s = b.seg[q];
     j = b.j[q];
   }
-  const int st = sink_photon<T>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr, s_cand);
+  const int st = sk.kind == PHOTON_SINK_RADIAL
+                     ? sink_photon<T, false, true>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr,
+                                                   s_cand)
+                     : sink_photon<T>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr, s_cand);
   if (active) sc.add(st);
   if (sk.totals) flush_status(sc, sk.totals);
 }
@@ -666,7 +714,7 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // searches and their constants staged in LDS; every photon is generated,
 // propagated and collected in registers. In the float form, rays near the
 // horizon are appended to a queue for the double pass instead.
-template <typename T, int BS, bool SPLAT = false>
+template <typename T, int BS, bool SPLAT = false, bool RADIAL = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !SPLAT && BS >= 256) ? 4 : 1))) void k_fused(FusedArgs A) {
   // the double splat keeps a smaller window so that the whole grid fits in LDS beside it
   constexpr int kWin = (SPLAT && sizeof(T) == 8) ? kWindow / 2 : kWindow;
@@ -678,7 +726,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ unsigned int s_dcount;
-  __shared__ HitStageLds<SPLAT> s_hs;
+  __shared__ HitStageLds<SPLAT || RADIAL> s_hs;
   __shared__ T s_wsc[SPLAT ? kWin : 1];  // SPLAT: per-segment weight factors mu/mu0
   __shared__ AtmLane s_lane;
   __shared__ uint32_t s_cand[kCandCells * kCandCells];
@@ -691,17 +739,18 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   __shared__ uint16_t s_slot[kWin];
   extern __shared__ unsigned long long s_splat[];  // dynamic: the block's fixed-point grid (SPLAT)
   constexpr bool kDefer = sizeof(T) == 4;
-  const bool stage_hits = !SPLAT && A.sk.kind == PHOTON_SINK_TELESCOPES;
-  unsigned long long* splat_lds = (SPLAT && A.sk.splat_lds) ? s_splat : nullptr;
-  const int n_cells = A.sk.sg.nx * A.sk.sg.ny;
+  const bool stage_hits = !SPLAT && !RADIAL && A.sk.kind == PHOTON_SINK_TELESCOPES;
+  // the block's LDS accumulator: the splat grid, or the radial bins
+  unsigned long long* lds_acc = SPLAT ? (A.sk.splat_lds ? s_splat : nullptr) : (RADIAL ? s_splat : nullptr);
+  const int n_cells = SPLAT ? A.sk.sg.nx * A.sk.sg.ny : 3 * A.sk.n_bins;
 
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_dcount = 0u;
-    if constexpr (!SPLAT) s_hs.get()->n = 0u;
+    if constexpr (!SPLAT && !RADIAL) s_hs.get()->n = 0u;
   }
-  if (splat_lds)
-    for (int k = tid; k < n_cells; k += BS) splat_lds[k] = 0ull;
+  if (lds_acc)
+    for (int k = tid; k < n_cells; k += BS) lds_acc[k] = 0ull;
   if (tid < PHOTON_MAX_LINES) {
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = (T)A.g.line_nm[tid];
@@ -842,13 +891,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
           }
         }
         if (!kDefer || p.status != kDeferred)
-          st_out = sink_photon<T, SPLAT>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
-                                         stage_hits ? s_hs.get() : nullptr, splat_lds, s_cand);
+          st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
+                                         stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
       }
       ws.add(st_out);
       if (kDefer) ws.c[PHOTON_HORIZON_FLOAT] += (unsigned long long)__popcll(__ballot(forced));
     }
-    if constexpr (!SPLAT) {
+    if constexpr (!SPLAT && !RADIAL) {
       if (stage_hits) flush_hits(s_hs.get(), A.sk.hits);
     }
     __syncthreads();
@@ -857,11 +906,23 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
     const uint64_t nd = s_dcount;
     A.defer_counts[blockIdx.x] = nd < (uint64_t)A.defer_cap ? nd : (uint64_t)A.defer_cap;
   }
-  if (splat_lds) {
-    // the block's grid into the global accumulator (the loop above ends with a barrier)
-    for (int k = tid; k < n_cells; k += BS) {
-      const unsigned long long v = splat_lds[k];
-      if (v) atomicAdd(&A.sk.splat_acc[k], v);
+  if (lds_acc) {
+    // the block's accumulator into the global one (the loop above ends with a barrier)
+    if constexpr (SPLAT) {
+      for (int k = tid; k < n_cells; k += BS) {
+        const unsigned long long v = lds_acc[k];
+        if (v) atomicAdd(&A.sk.splat_acc[k], v);
+      }
+    } else {
+      const int nb = A.sk.n_bins;
+      for (int k = tid; k < nb; k += BS) {
+        const unsigned long long c = lds_acc[k];
+        if (c) {
+          atomicAdd(&A.sk.rad_count[k], c);
+          atomicAdd(&A.sk.rad_w[k], lds_acc[nb + k]);
+          atomicAdd(&A.sk.rad_wt[k], lds_acc[2 * nb + k]);
+        }
+      }
     }
   }
   if (A.sk.totals) flush_wave_status(ws, A.sk.totals);
@@ -959,10 +1020,16 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     pf.t = p.t;
     pf.path = p.path;
     pf.status = p.status;
-    const int st = splat ? sink_photon<float, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr,
-                                                    nullptr, s_cand)
-                         : sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y,
-                                              nullptr, nullptr, s_cand);
+    int st;
+    if (splat)
+      st = sink_photon<float, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr, nullptr,
+                                    s_cand);
+    else if (A.sk.kind == PHOTON_SINK_RADIAL)
+      st = sink_photon<float, false, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr,
+                                           nullptr, s_cand);
+    else
+      st = sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y, nullptr,
+                              nullptr, s_cand);
     sc.add(st);
   }
   if (A.sk.totals) flush_status(sc, A.sk.totals);
@@ -1240,6 +1307,29 @@ __global__ __launch_bounds__(256) void k_means(SegView seg, int64_t n, AtmDev at
                                      : beamed_mean(seg, i, beam, mean_fluor(seg, i, K));
 }
 
+// Radial profiles from the fixed-point sums, one thread per bin: density =
+// weight / annulus area, mean time = t_ref + sum w (t - t_ref) / sum w.
+__global__ __launch_bounds__(256) void k_radial_finish(SinkDev sk, double r_max, double* __restrict__ density,
+                                                       double* __restrict__ mean_t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= sk.n_bins) return;
+  const double n = (double)sk.n_bins;
+  double r0, r1;
+  if (sk.log_bins) {
+    const double q = r_max / sk.r_min;
+    r0 = sk.r_min * pow(q, (double)k / n);
+    r1 = k + 1 == sk.n_bins ? r_max : sk.r_min * pow(q, (double)(k + 1) / n);
+  } else {
+    const double span = r_max - sk.r_min;
+    r0 = sk.r_min + span * ((double)k / n);
+    r1 = k + 1 == sk.n_bins ? r_max : sk.r_min + span * ((double)(k + 1) / n);
+  }
+  const double w = (double)sk.rad_w[k] * 0x1p-32;
+  const double wt = (double)(long long)sk.rad_wt[k] * 0x1p-8;
+  density[k] = w / (kPi * (r1 * r1 - r0 * r0));
+  mean_t[k] = w > 0.0 ? sk.t_ref + wt / w : __builtin_nan("");
+}
+
 // ------------------------------------------------------------ host helpers --
 bool finite(double v) { return std::isfinite(v); }
 
@@ -1451,6 +1541,31 @@ void build_candidates(const photon_sink* s, double hobs, SinkDev* d) {
     }
 }
 
+// Radial profile geometry and accumulators of a sink.
+int prep_radial(const photon_sink* s, SinkDev* d) {
+  if (s->n_bins < 1 || s->n_bins > PHOTON_MAX_RADIAL_BINS)
+    return fail(PHOTON_EINVAL, "n_bins = %d outside 1..%d", s->n_bins, PHOTON_MAX_RADIAL_BINS);
+  if (s->log_bins != 0 && s->log_bins != 1) return fail(PHOTON_EINVAL, "log_bins must be 0 or 1");
+  if (!finite(s->core_x) || !finite(s->core_y) || !finite(s->t_ref_ns))
+    return fail(PHOTON_EINVAL, "radial core or t_ref not finite");
+  if (!finite(s->r_min) || !finite(s->r_max) || !(s->r_min >= 0.0) || !(s->r_max > s->r_min))
+    return fail(PHOTON_EINVAL, "radial range must satisfy 0 <= r_min < r_max");
+  if (s->log_bins && !(s->r_min > 0.0)) return fail(PHOTON_EINVAL, "log bins need r_min > 0");
+  if (!s->radial_count || !s->radial_weight || !s->radial_wt) return fail(PHOTON_EINVAL, "radial outputs are NULL");
+  d->core_x = s->core_x;
+  d->core_y = s->core_y;
+  d->r_min = s->r_min;
+  d->r_inv = s->log_bins ? (double)s->n_bins / std::log(s->r_max / s->r_min)
+                         : (double)s->n_bins / (s->r_max - s->r_min);
+  d->t_ref = s->t_ref_ns;
+  d->n_bins = s->n_bins;
+  d->log_bins = s->log_bins;
+  d->rad_count = s->radial_count;
+  d->rad_w = s->radial_weight;
+  d->rad_wt = s->radial_wt;
+  return PHOTON_OK;
+}
+
 int prep_sink(const photon_sink* s, SinkDev* d, double atm_hobs, int32_t precision) {
   if (!s) return fail(PHOTON_EINVAL, "sink is NULL");
   std::memset(d, 0, sizeof *d);
@@ -1513,6 +1628,9 @@ int prep_sink(const photon_sink* s, SinkDev* d, double atm_hobs, int32_t precisi
     d->pseg = b->segment;
     d->pj = b->j;
     d->pstatus = b->status;
+  } else if (s->kind == PHOTON_SINK_RADIAL) {
+    int rc = prep_radial(s, d);
+    if (rc) return rc;
   } else if (s->kind != PHOTON_SINK_STATUS) {
     return fail(PHOTON_EINVAL, "unknown sink kind %d", s->kind);
   }
@@ -1708,7 +1826,15 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
                     const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
                     DeviceState* dev, hipStream_t st, size_t dyn_lds = 0) {
   int occ;
-  if (!SPLAT) {
+  const bool radial = !SPLAT && sk.kind == PHOTON_SINK_RADIAL;
+  if (radial) {
+    // the radial bins live in dynamic LDS: count, weight and w t per bin
+    dyn_lds = (size_t)3 * sizeof(unsigned long long) * (size_t)sk.n_bins;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<T, BS, false, true>, BS, dyn_lds) !=
+            hipSuccess ||
+        occ < 1)
+      occ = 1;
+  } else if (!SPLAT) {
     occ = fused_occupancy<T, BS>(dev);
   } else {
     // splat variants by precision and LDS grid
@@ -1749,7 +1875,10 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   A.defer_pref = dev->defer_pref;
   A.n_defer_blocks = (int32_t)grid;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
-  hipLaunchKernelGGL((k_fused<T, BS, SPLAT>), dim3((unsigned)grid), dim3(BS), dyn_lds, st, A);
+  if (radial)
+    hipLaunchKernelGGL((k_fused<T, BS, false, true>), dim3((unsigned)grid), dim3(BS), dyn_lds, st, A);
+  else
+    hipLaunchKernelGGL((k_fused<T, BS, SPLAT>), dim3((unsigned)grid), dim3(BS), dyn_lds, st, A);
   if (defer) {
     hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
                        (int)grid, A.defer_cap, dev->defer_pref);
@@ -1827,6 +1956,12 @@ int clear_sink(const SinkDev& sk, hipStream_t st) {
     const int cells = sk.nx * sk.ny;
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, sk.grid_count, cells);
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, sk.grid_weight, cells);
+  }
+  if (sk.kind == PHOTON_SINK_RADIAL) {
+    const unsigned nb = (unsigned)ceil_div(sk.n_bins, 256);
+    hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, st, sk.rad_count, sk.n_bins);
+    hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, st, sk.rad_w, sk.n_bins);
+    hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, st, sk.rad_wt, sk.n_bins);
   }
   return check_launch();
 }
@@ -2199,6 +2334,22 @@ int photon_count(const photon_segments* seg, const photon_atmosphere* atm, const
                  uint64_t seed, uint32_t* counts, uint64_t* offsets, void* stream) {
   if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
   return generate_common(seg, atm, em, seed, PHOTON_FP64, counts, offsets, nullptr, stream);
+}
+
+int photon_radial_profile(const photon_sink* sink, double* density, double* mean_t_ns, void* stream) {
+  if (!sink) return fail(PHOTON_EINVAL, "sink is NULL");
+  if (sink->kind != PHOTON_SINK_RADIAL) return fail(PHOTON_EINVAL, "sink is not RADIAL");
+  SinkDev sk;
+  std::memset(&sk, 0, sizeof sk);
+  int rc;
+  if ((rc = prep_radial(sink, &sk))) return rc;
+  if (!density || !mean_t_ns) return fail(PHOTON_EINVAL, "profile outputs are NULL");
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_radial_finish, dim3((unsigned)ceil_div(sk.n_bins, 256)), dim3(256), 0, st, sk, sink->r_max,
+                     density, mean_t_ns);
+  return check_launch();
 }
 
 int photon_generate(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,

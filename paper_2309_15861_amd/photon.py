@@ -22,7 +22,8 @@ CHERENKOV, FLUORESCENCE = 0, 1
 LANDED, HIT, UP, BELOW, OFFGRID, ABSORBED, INVALID = 0, 1, 2, 3, 4, 5, 6
 HORIZON_FLOAT = 7          # totals slot: near-horizon rays evaluated in float (queue full)
 N_STATUS = 8
-SINK_STATUS, SINK_TELESCOPES, SINK_GRID, SINK_PLANE = 0, 1, 2, 3
+SINK_STATUS, SINK_TELESCOPES, SINK_GRID, SINK_PLANE, SINK_RADIAL = 0, 1, 2, 3, 4
+MAX_RADIAL_BINS = 1024
 MAX_LAYERS, MAX_ABS, MAX_LINES, MAX_TELESCOPES, MAX_CUT_POINTS = 8, 40, 32, 32, 32
 
 P = C.c_void_p
@@ -67,7 +68,10 @@ class Sink(C.Structure):
     _fields_ = [("kind", C.c_int32), ("status_totals", P), ("n_tel", C.c_int32),
                 ("tel", (C.c_double * 4) * MAX_TELESCOPES), ("hits", Hits), ("x_min", C.c_double),
                 ("y_min", C.c_double), ("cell", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
-                ("grid_count", P), ("grid_weight", P), ("plane", P)]
+                ("grid_count", P), ("grid_weight", P), ("plane", P),
+                ("core_x", C.c_double), ("core_y", C.c_double), ("r_min", C.c_double), ("r_max", C.c_double),
+                ("t_ref_ns", C.c_double), ("n_bins", C.c_int32), ("log_bins", C.c_int32),
+                ("radial_count", P), ("radial_weight", P), ("radial_wt", P)]
 
 
 class Tuning(C.Structure):
@@ -110,6 +114,7 @@ def lib():
         L.photon_means.argtypes = [P, P, P, P, P]
         L.photon_count.argtypes = [P, P, P, C.c_uint64, P, P, P]
         L.photon_generate.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P]
+        L.photon_radial_profile.argtypes = [P, P, P, P]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
@@ -294,6 +299,52 @@ def sink_grid(x_min, y_min, cell, nx, ny, grid_count, grid_weight, totals=None) 
     s.grid_count = grid_count.data_ptr()
     s.grid_weight = grid_weight.data_ptr()
     return s
+
+
+class RadialProfile:
+    """Accumulators of a radial profile sink on the GPU (count, weight in
+    units of 2^-32, w (t - t_ref) in units of 2^-8 ns) and its geometry."""
+
+    def __init__(self, n_bins, r_min, r_max, log_bins=False, core=(0.0, 0.0), t_ref_ns=0.0, device="cuda"):
+        self.n_bins, self.r_min, self.r_max = int(n_bins), float(r_min), float(r_max)
+        self.log_bins, self.core, self.t_ref_ns = bool(log_bins), (float(core[0]), float(core[1])), float(t_ref_ns)
+        n = max(self.n_bins, 1)
+        self.count = torch.zeros(n, dtype=torch.int64, device=device)
+        self.weight = torch.zeros(n, dtype=torch.int64, device=device)
+        self.wt = torch.zeros(n, dtype=torch.int64, device=device)
+
+    def edges(self) -> np.ndarray:
+        k = np.arange(self.n_bins + 1) / self.n_bins
+        if self.log_bins:
+            e = self.r_min * (self.r_max / self.r_min) ** k
+        else:
+            e = self.r_min + (self.r_max - self.r_min) * k
+        e[-1] = self.r_max
+        return e
+
+
+def sink_radial(prof: RadialProfile, totals=None) -> Sink:
+    """Radial photon-density and arrival-time profile about prof.core."""
+    s = Sink()
+    s.kind = SINK_RADIAL
+    s.status_totals = None if totals is None else totals.data_ptr()
+    s.core_x, s.core_y = prof.core
+    s.r_min, s.r_max, s.t_ref_ns = prof.r_min, prof.r_max, prof.t_ref_ns
+    s.n_bins, s.log_bins = prof.n_bins, int(prof.log_bins)
+    s.radial_count = prof.count.data_ptr()
+    s.radial_weight = prof.weight.data_ptr()
+    s.radial_wt = prof.wt.data_ptr()
+    return s
+
+
+def radial_profile(prof: RadialProfile):
+    """(density [photons/m^2], mean arrival time [ns]) per bin as float64
+    tensors; NaN time where a bin holds no weight."""
+    density = torch.empty(max(prof.n_bins, 1), dtype=torch.float64, device=prof.count.device)
+    mean_t = torch.empty_like(density)
+    s = sink_radial(prof)
+    _check(lib().photon_radial_profile(C.byref(s), _ptr(density), _ptr(mean_t), _stream()))
+    return density[:prof.n_bins], mean_t[:prof.n_bins]
 
 
 def sink_plane(block: PhotonBlock, totals=None) -> Sink:

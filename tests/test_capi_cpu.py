@@ -258,3 +258,29 @@ def test_beam_validation(ph):
     assert count(e) == ph.EINVAL
     # photon_generate needs a block
     assert L.photon_generate(C.byref(seg), C.byref(atm), C.byref(em()), 1, 0, 0x3000, None, None) == ph.EINVAL
+
+
+def test_radial_validation(ph):
+    """The radial profile sink and its finish validate before device work."""
+    L = ph.lib()
+
+    def sink(**kw):
+        s = ph.Sink()
+        s.kind = ph.SINK_RADIAL
+        s.core_x, s.core_y, s.r_min, s.r_max, s.t_ref_ns = 0.0, 0.0, 1.0, 1000.0, 0.0
+        s.n_bins, s.log_bins = 100, 1
+        s.radial_count, s.radial_weight, s.radial_wt = 0x1000, 0x2000, 0x3000
+        for k, v in kw.items():
+            setattr(s, k, v)
+        return s
+
+    def prof(s, out=0x4000):
+        return L.photon_radial_profile(C.byref(s), out, out, None)
+
+    assert prof(sink()) == ph.ENODEV
+    for bad in (dict(n_bins=0), dict(n_bins=ph.MAX_RADIAL_BINS + 1), dict(log_bins=2), dict(r_min=0.0),
+                dict(r_max=1.0), dict(r_min=-1.0, log_bins=0), dict(core_x=float("nan")),
+                dict(t_ref_ns=float("inf")), dict(radial_wt=None), dict(kind=ph.SINK_GRID)):
+        assert prof(sink(**bad)) == ph.EINVAL, bad
+    assert prof(sink(), out=None) == ph.EINVAL
+    assert prof(sink(r_min=0.0, log_bins=0)) == ph.ENODEV
