@@ -712,6 +712,125 @@ int32_t or_grid_cell(const or_photon* p, double x_min, double y_min, double cell
 }
 
 /* ------------------------------------------------------------------------ */
+/* Straight line plus correction factors (section 2): the fast propagation  */
+/* of the paper. A photon is carried to the observation level along a       */
+/* straight line at its emission zenith angle; tabulated corrections then   */
+/* move its landing point, path, optical path and column density to what   */
+/* the refracting atmosphere gives, and the arrival angle follows Snell.    */
+/*                                                                          */
+/* Tables, built from the exact integrals at their nodes:                   */
+/*  2-D over emission height h_i = h_obs + (h_max - h_obs) i/(n_h - 1) and  */
+/*  q_j = tan(zenith) = q_max j/(n_q - 1), three values per node:           */
+/*    g  = (D - dh q)/q  (horizontal displacement D; at q = 0 the limit,    */
+/*         taken at q = 1e-4 q_max),                                        */
+/*    dP = P - dh sec,   dX = X - sec VX(h_i)                               */
+/*  with dh = h_i - h_obs, sec = sqrt(1 + q^2), P the geometric path and X  */
+/*  the column (integral of rho/rho0 ds);                                   */
+/*  1-D over height v_k = h_obs + (h_max - h_obs) k/(n_v - 1): rho/rho0 and */
+/*  the vertical column VX(v_k) from h_obs.                                 */
+/* A photon then lands at x_e + ux (dh + g)/mu (mu = -uz), with path        */
+/* dh sec + dP, column sec VX(h_e) + dX, optical path path + eta0 column;    */
+/* values between nodes by bilinear (2-D) and linear (1-D) interpolation.    */
+/* Photons above h_max or steeper than q_max take the exact integrals.      */
+/* ------------------------------------------------------------------------ */
+
+static void node_integrals(const or_atmosphere* a, double h, double q, double G[4], double* D) {
+  double ce = 1.0 / sqrt(1.0 + q * q);
+  double se = q * ce;
+  or_ray_integrals(a, h, ce, a->h_obs, G);
+  *D = or_index(a, h) * se * G[0];
+}
+
+void or_table_build(const or_atmosphere* a, int32_t n_h, int32_t n_q, double h_max, double q_max, int32_t n_v,
+                    double* corr, double* vert) {
+  double span = h_max - a->h_obs;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int32_t i = 0; i < n_h; ++i) {
+    double h = a->h_obs + span * ((double)i / (double)(n_h - 1));
+    double dh = h - a->h_obs;
+    double Gv[4], Dv;
+    node_integrals(a, h, 0.0, Gv, &Dv);
+    double VX = Gv[3];
+    for (int32_t j = 0; j < n_q; ++j) {
+      double q = q_max * ((double)j / (double)(n_q - 1));
+      double G[4], D, *c = corr + 3 * ((int64_t)i * n_q + j);
+      if (dh <= 0.0) { c[0] = c[1] = c[2] = 0.0; continue; }
+      if (j == 0) {
+        double qs = 1e-4 * q_max, G2[4], D2;
+        node_integrals(a, h, qs, G2, &D2);
+        c[0] = (D2 - dh * qs) / qs;
+      }
+      node_integrals(a, h, q, G, &D);
+      double sec = sqrt(1.0 + q * q);
+      if (j > 0) c[0] = (D - dh * q) / q;
+      c[1] = G[1] - dh * sec;
+      c[2] = G[3] - sec * VX;
+    }
+  }
+  for (int32_t k = 0; k < n_v; ++k) {
+    double h = a->h_obs + span * ((double)k / (double)(n_v - 1));
+    double G[4], D;
+    node_integrals(a, h, 0.0, G, &D);
+    vert[2 * k] = or_density(a, h);
+    vert[2 * k + 1] = (h > a->h_obs) ? G[3] : 0.0;
+  }
+}
+
+static double lerp(double a, double b, double t) { return a + (b - a) * t; }
+
+void or_propagate_table_one(or_photon* p, const or_atmosphere* a, int32_t n_h, int32_t n_q, double h_max,
+                            double q_max, int32_t n_v, const double* corr, const double* vert) {
+  if (p->status == OR_INVALID) return;
+  double un = sqrt((p->ue[0] * p->ue[0] + p->ue[1] * p->ue[1]) + p->ue[2] * p->ue[2]);
+  double ux = p->ue[0] / un, uy = p->ue[1] / un, uz = p->ue[2] / un;
+  if (!(uz < 0.0)) { p->status = OR_UP; return; }
+  if (p->ze < a->h_obs) { p->status = OR_BELOW; return; }
+  double mu = -uz;
+  double se = sqrt(ux * ux + uy * uy);
+  double q = se / mu;
+  if (p->ze > h_max || q > q_max) { or_propagate_one(p, a); return; }
+  double span = h_max - a->h_obs;
+  double dh = p->ze - a->h_obs;
+  double sec = 1.0 / mu;
+  /* cell and weights */
+  double fi = dh / span * (double)(n_h - 1), fj = q / q_max * (double)(n_q - 1);
+  int32_t i = (int32_t)floor(fi), j = (int32_t)floor(fj);
+  if (i > n_h - 2) i = n_h - 2;
+  if (j > n_q - 2) j = n_q - 2;
+  double ta = fi - i, tb = fj - j;
+  double val[3];
+  for (int c = 0; c < 3; ++c) {
+    double v00 = corr[3 * ((int64_t)i * n_q + j) + c], v01 = corr[3 * ((int64_t)i * n_q + j + 1) + c];
+    double v10 = corr[3 * ((int64_t)(i + 1) * n_q + j) + c], v11 = corr[3 * ((int64_t)(i + 1) * n_q + j + 1) + c];
+    val[c] = lerp(lerp(v00, v01, tb), lerp(v10, v11, tb), ta);
+  }
+  double fk = dh / span * (double)(n_v - 1);
+  int32_t k = (int32_t)floor(fk);
+  if (k > n_v - 2) k = n_v - 2;
+  double tk = fk - k;
+  double rho_e = lerp(vert[2 * k], vert[2 * k + 2], tk);
+  double VX = lerp(vert[2 * k + 1], vert[2 * k + 3], tk);
+  double P = dh * sec + val[1];
+  double X = sec * VX + val[2];
+  double O = P + a->eta0 * X;
+  p->xl = p->xe + ux * (dh + val[0]) / mu;
+  p->yl = p->ye + uy * (dh + val[0]) / mu;
+  p->zl = a->h_obs;
+  p->tl = p->te + O / OR_C_M_PER_NS;
+  p->path = P;
+  p->tau = or_abs_k(a, p->lambda) * X;
+  p->weight = exp(-p->tau);
+  /* arrival direction: Snell with the interpolated emission index */
+  double ne = 1.0 + a->eta0 * rho_e, nobs = or_index(a, a->h_obs);
+  double r = ne / nobs;
+  double sl = r * se;
+  p->ul[0] = ux * r;
+  p->ul[1] = uy * r;
+  p->ul[2] = -sqrt((1.0 - sl) * (1.0 + sl));
+  p->status = OR_LANDED;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Batch drivers.                                                           */
 /* ------------------------------------------------------------------------ */
 
@@ -772,6 +891,16 @@ void or_radial_bins(const or_photon* ph, int64_t count, double cx, double cy, co
       if (edges[mid] <= r) lo = mid; else hi = mid;
     }
     bin[q] = lo;
+  }
+}
+
+/* Propagates generated photons (emission fields set) by the table method. */
+void or_propagate_table(or_photon* ph, int64_t count, const or_atmosphere* a, int32_t n_h, int32_t n_q, double h_max,
+                        double q_max, int32_t n_v, const double* corr, const double* vert) {
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t q = 0; q < count; ++q) {
+    if (ph[q].status != OR_INVALID) ph[q].status = OR_LANDED;
+    or_propagate_table_one(&ph[q], a, n_h, n_q, h_max, q_max, n_v, corr, vert);
   }
 }
 

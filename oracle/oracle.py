@@ -94,6 +94,9 @@ def lib():
         L.or_photons_all.argtypes = [P, P, C.c_int, P, P, P, C.c_int32, C.c_uint64, P, P, P]
         L.or_telescopes.argtypes = [P, C.c_int64, P, C.c_int32, C.c_double, P, P]
         L.or_radial_bins.argtypes = [P, C.c_int64, C.c_double, C.c_double, P, C.c_int32, P]
+        L.or_table_build.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, P, P]
+        L.or_propagate_table.argtypes = [P, C.c_int64, P, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                         C.c_int32, P, P]
         L.or_grid.argtypes = [P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32,
                               C.c_int32, P]
         L.or_splat.argtypes = [P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
@@ -326,6 +329,26 @@ def telescopes(ph: np.ndarray, tel: np.ndarray, n_obs: float):
     lib().or_telescopes(_ptr(ph), len(ph), _ptr(tel), tel.shape[0], float(n_obs), _ptr(tid),
                         _ptr(hits))
     return tid, hits
+
+
+class Table:
+    """Correction tables of the straight-line propagation (section 2):
+    corr (n_h, n_q, 3) = (g, dP, dX) and vert (n_v, 2) = (rho/rho0, VX)."""
+
+    def __init__(self, atm: Atmosphere, n_h: int, n_q: int, h_max: float, q_max: float, n_v: int):
+        self.n_h, self.n_q, self.h_max, self.q_max, self.n_v = int(n_h), int(n_q), float(h_max), float(q_max), int(n_v)
+        self.corr = np.zeros((self.n_h, self.n_q, 3))
+        self.vert = np.zeros((self.n_v, 2))
+        lib().or_table_build(C.byref(atm.c), self.n_h, self.n_q, self.h_max, self.q_max, self.n_v,
+                             _ptr(self.corr), _ptr(self.vert))
+
+
+def propagate_table(ph: np.ndarray, atm: Atmosphere, table: Table) -> np.ndarray:
+    """A copy of generated photons carried to the ground by the table method."""
+    out = np.ascontiguousarray(ph).copy()
+    lib().or_propagate_table(_ptr(out), len(out), C.byref(atm.c), table.n_h, table.n_q, table.h_max,
+                             table.q_max, table.n_v, _ptr(table.corr), _ptr(table.vert))
+    return out
 
 
 def radial_edges(n_bins, r_min, r_max, log_bins):
