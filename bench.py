@@ -262,6 +262,39 @@ def radial_profile(args, d, atm, seed, best):
                 peak_density_r_m=float(mid[int(np.argmax(dens))]))
 
 
+def table_propagation(args, d, atm, tel, seed, best, exact_ms):
+    """The shower step with the straight-line propagation and tabulated
+    refraction corrections of section 2 (257 x 257 nodes up to 40 km and
+    80 degrees, FP32): step time against the exact closed forms."""
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+
+    tab = ph.PropagationTable(atm)
+    atm_t = tab.attach(atm)
+    em = ph.emission_cherenkov(300.0, 600.0)
+    counts = torch.empty(d.n, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(d.n + 1, dtype=torch.int64, device="cuda")
+    hits = ph.HitBuffer(1 << 20)
+    totals = ph.status_totals()
+    plan = ph.Plan(d, atm_t, em, seed, ph.FP32, counts, offsets, ph.sink_telescopes(tel, hits, totals), best)
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    photons = int(offsets[-1].item())
+    plan.close()
+    return dict(table="257 x 257 nodes, h_obs..40 km, tan(zenith) 0..tan(80 deg); 4097 vertical nodes",
+                photons=photons, hits=hits.count(), ms_per_step=ms, photons_per_s=photons / (ms * 1e-3),
+                speedup_vs_exact=exact_ms / ms)
+
+
 def differentiable(args):
     """The differentiable form at 1e6 segments: splatted ground density
     (128 x 128 cells of 5 m, sigma 5 m) with counts frozen at the nominal
@@ -326,6 +359,8 @@ def main():
                          "(profiling runs)")
     ap.add_argument("--cut", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the shower step with the 6 degree Cherenkov angular particle cut")
+    ap.add_argument("--table", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the shower step with the straight-line + correction-table propagation")
     ap.add_argument("--radial", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the shower step collected as radial density and arrival-time profiles")
     ap.add_argument("--beam", action=argparse.BooleanOptionalAction, default=True,
@@ -433,6 +468,9 @@ def main():
     if args.cut:
         out["angular_cut"] = angular_cut(args, d, atm, tel, seed, ph.tuning(*r32["tuning"]),
                                          dict(photons=total, hits=r32["hits"], ms_per_step=r32["ms_per_step"]))
+    if args.table:
+        out["table_propagation"] = table_propagation(args, d, atm, tel, seed, ph.tuning(*r32["tuning"]),
+                                                     r32["ms_per_step"])
     if args.radial:
         out["radial_profile"] = radial_profile(args, d, atm, seed, ph.tuning(*r32["tuning"]))
     if args.beam:

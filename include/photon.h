@@ -97,9 +97,15 @@ extern "C" {
    constant density). n(h) = 1 + n0_minus_1 * rho(h)/rho0. Absorption
    coefficient k(lambda) * rho/rho0 [1/m], k piecewise linear in lambda
    between the table nodes and clamped outside; n_abs = 0: no absorption.
+   table: NULL for the exact propagation (the closed-form layer integrals);
+   else the straight-line propagation with that correction table (built by
+   photon_table_build for this atmosphere) for every call that propagates.
    Errors: n_layers outside 1..8, h_base[0] != 0 or not strictly increasing,
    scale_height <= 0 or NaN, n0_minus_1 < 0 or not finite, h_obs not finite,
-   n_abs outside 0..40, abs_lambda_nm not strictly increasing, abs_k < 0. */
+   n_abs outside 0..40, abs_lambda_nm not strictly increasing, abs_k < 0, a
+   table built for another atmosphere (layers, scale heights, n0_minus_1 or
+   h_obs differ) or not built. */
+struct photon_table;
 typedef struct {
   int32_t n_layers;
   double h_base[PHOTON_MAX_LAYERS];
@@ -109,7 +115,35 @@ typedef struct {
   int32_t n_abs;
   double abs_lambda_nm[PHOTON_MAX_ABS];
   double abs_k_per_m[PHOTON_MAX_ABS];
+  const struct photon_table* table;
 } photon_atmosphere;
+
+/* Correction tables of the straight-line propagation (section 2: photons
+   are carried to the ground on a straight line and correction factors then
+   change arrival position, time and angle for refraction). With
+   dh = h_e - h_obs, mu = cos(zenith), q = tan(zenith), sec = 1/mu:
+     landing point  x_e + ux (dh + g)/mu   (ux, uy: unit direction)
+     path           P = dh sec + dP
+     column         X = sec VX(h_e) + dX   (VX: vertical column from h_obs,
+                                            column = integral of rho/rho0 ds)
+     time           t_e + (P + n0_minus_1 X)/c,   weight exp(-k(lambda) X)
+     direction      Snell: horizontal part times n(h_e)/n(h_obs)
+   g, dP, dX are the exact integrals minus the straight line, tabulated at
+   heights h_i = h_obs + (h_max - h_obs) i/(n_h - 1) and q_j = q_max j/(n_q - 1)
+   (g at q = 0: its limit, taken at q = 1e-4 q_max) and interpolated
+   bilinearly; rho/rho0 and VX at v_k = h_obs + (h_max - h_obs) k/(n_v - 1),
+   interpolated linearly. Photons above h_max or with q > q_max, and every
+   photon of the differentiable form, take the exact integrals.
+   Caller-owned device arrays: corr float[4 n_h n_q], node (i, j) at
+   4 (i n_q + j) as (g, dP, dX, 0); vert float[2 n_v] as (rho/rho0, VX).
+   atm_hash is written by photon_table_build. */
+typedef struct photon_table {
+  int32_t n_h, n_q, n_v;
+  double h_max, q_max;
+  float* corr;
+  float* vert;
+  uint64_t atm_hash;
+} photon_table;
 
 /* Track segments, structure of arrays of length n (device pointers).
    Start point (x0,y0,z0) [m], direction (dx,dy,dz) (normalised inside),
@@ -371,6 +405,12 @@ typedef struct {
    density and mean_t_ns: device f64[n_bins]. Errors: EINVAL (the sink's
    RADIAL fields as photon_run_fused checks them, NULL outputs). */
 int photon_radial_profile(const photon_sink* sink, double* density, double* mean_t_ns, void* stream);
+
+/* Fills a correction table for an atmosphere (its `table` field is
+   ignored) from the exact FP64 integrals at every node, and stamps it with
+   the atmosphere's hash. n_h, n_q in 2..4096, n_v in 2..65536,
+   h_max > h_obs, 0 < q_max <= 1e3, corr and vert non-NULL. Errors: EINVAL. */
+int photon_table_build(const photon_atmosphere* atm, photon_table* table, void* stream);
 
 /* Per-segment counts and offsets for an emission model (as the generation
    calls with out == NULL), honouring the Cherenkov angular particle cut of

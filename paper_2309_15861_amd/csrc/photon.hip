@@ -367,7 +367,10 @@ __global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, i
   p.path = b.path[q];
   p.status = b.status[q];
   p.uzd = (double)p.uz;
-  propagate<T>(atm, s_lane, p);
+  if (atm.tcorr)
+    propagate<T, false, false, true>(atm, s_lane, p);
+  else
+    propagate<T>(atm, s_lane, p);
   b.x[q] = p.x;
   b.y[q] = p.y;
   b.z[q] = p.z;
@@ -714,7 +717,7 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // searches and their constants staged in LDS; every photon is generated,
 // propagated and collected in registers. In the float form, rays near the
 // horizon are appended to a queue for the double pass instead.
-template <typename T, int BS, bool SPLAT = false, bool RADIAL = false>
+template <typename T, int BS, bool SPLAT = false, bool RADIAL = false, bool TABLE = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !SPLAT && BS >= 256) ? 4 : 1))) void k_fused(FusedArgs A) {
   // the double splat keeps a smaller window so that the whole grid fits in LDS beside it
   constexpr int kWin = (SPLAT && sizeof(T) == 8) ? kWindow / 2 : kWindow;
@@ -866,7 +869,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
         const uint32_t j = (uint32_t)(q - off_s);
         Photon<T> p;
         generate<T>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
-        propagate<T, kDefer>(A.atm, s_lane, p);
+        propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p);
         if constexpr (SPLAT) p.w *= wsc;
         if (kDefer) {
           const bool defer = p.status == kDeferred;
@@ -1330,8 +1333,81 @@ __global__ __launch_bounds__(256) void k_radial_finish(SinkDev sk, double r_max,
   mean_t[k] = w > 0.0 ? sk.t_ref + wt / w : __builtin_nan("");
 }
 
+// Correction tables of the straight-line propagation, one thread per node:
+// the exact integrals in double at (h_i, q_j) minus the straight line; the
+// threads past the 2-D nodes fill the 1-D table of density and vertical
+// column.
+__global__ __launch_bounds__(256) void k_table_build(AtmDev a, int n_h, int n_q, int n_v, double h_max, double q_max,
+                                                     float4* __restrict__ corr, float2* __restrict__ vert) {
+  __shared__ AtmLane s_lane;
+  atm_lane_fill(a, &s_lane);
+  __syncthreads();
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n2 = (int64_t)n_h * n_q;
+  const double span = h_max - a.hobs;
+  double g0, pth, opt, col, ne, em, rb;
+  if (idx < n2) {
+    const int i = (int)(idx / n_q), j = (int)(idx % n_q);
+    const double h = a.hobs + span * ((double)i / (double)(n_h - 1));
+    const double dh = h - a.hobs;
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (dh > 0.0) {
+      exact_ray_double(a, s_lane, h, 0.0, 1.0, g0, pth, opt, col, ne, em, rb);
+      const double VX = col;
+      const double pv = pth;
+      // g at q = 0 is the limit, taken at q = 1e-4 q_max
+      const double q = q_max * ((double)j / (double)(n_q - 1));
+      const double qg = j == 0 ? 1e-4 * q_max : q;
+      const double ce = 1.0 / sqrt(1.0 + qg * qg), se = qg * ce;
+      exact_ray_double(a, s_lane, h, se, ce, g0, pth, opt, col, ne, em, rb);
+      const double g = (ne * se * g0 - dh * qg) / qg;
+      double dP, dX;
+      if (j == 0) {
+        dP = pv - dh;
+        dX = 0.0;
+      } else {
+        const double sec = sqrt(1.0 + q * q);
+        dP = pth - dh * sec;
+        dX = col - sec * VX;
+      }
+      out = make_float4((float)g, (float)dP, (float)dX, 0.f);
+    }
+    corr[idx] = out;
+  } else if (idx < n2 + n_v) {
+    const int k = (int)(idx - n2);
+    const double h = a.hobs + span * ((double)k / (double)(n_v - 1));
+    exact_ray_double(a, s_lane, h, 0.0, 1.0, g0, pth, opt, col, ne, em, rb);
+    vert[k] = make_float2((float)(rb * (1.0 + em)), (float)(h > a.hobs ? col : 0.0));
+  }
+}
+
 // ------------------------------------------------------------ host helpers --
 bool finite(double v) { return std::isfinite(v); }
+
+// Fingerprint of what a correction table depends on (FNV-1a over the
+// layers, scale heights, n0 - 1 and h_obs); never 0.
+uint64_t atm_hash(const photon_atmosphere* a) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&a->n_layers, sizeof a->n_layers);
+  mix(a->h_base, sizeof(double) * (size_t)a->n_layers);
+  mix(a->scale_height, sizeof(double) * (size_t)a->n_layers);
+  mix(&a->n0_minus_1, sizeof a->n0_minus_1);
+  mix(&a->h_obs, sizeof a->h_obs);
+  return h ? h : 1ull;
+}
+
+int check_table_shape(const photon_atmosphere* a, const photon_table* t) {
+  if (t->n_h < 2 || t->n_h > 4096 || t->n_q < 2 || t->n_q > 4096 || t->n_v < 2 || t->n_v > 65536)
+    return fail(PHOTON_EINVAL, "table nodes n_h = %d, n_q = %d, n_v = %d out of range", t->n_h, t->n_q, t->n_v);
+  if (!std::isfinite(t->h_max) || !(t->h_max > a->h_obs)) return fail(PHOTON_EINVAL, "table h_max must exceed h_obs");
+  if (!(t->q_max > 0.0) || !(t->q_max <= 1e3)) return fail(PHOTON_EINVAL, "table q_max must lie in (0, 1e3]");
+  if (!t->corr || !t->vert) return fail(PHOTON_EINVAL, "table arrays are NULL");
+  return PHOTON_OK;
+}
 
 int prep_atm(const photon_atmosphere* a, AtmDev* d) {
   if (!a) return fail(PHOTON_EINVAL, "atmosphere is NULL");
@@ -1391,6 +1467,22 @@ int prep_atm(const photon_atmosphere* a, AtmDev* d) {
     d->abs_uniform = uni ? 1 : 0;
     d->abs_l0 = a->abs_lambda_nm[0];
     d->abs_inv_step = uni ? 1.0 / step : 0.0;
+  }
+  if (a->table) {
+    const photon_table* t = a->table;
+    int rc = check_table_shape(a, t);
+    if (rc) return rc;
+    if (t->atm_hash != atm_hash(a)) return fail(PHOTON_EINVAL, "correction table not built for this atmosphere");
+    d->tcorr = (const float4*)t->corr;
+    d->tvert = (const float2*)t->vert;
+    d->tn_h = t->n_h;
+    d->tn_q = t->n_q;
+    d->tn_v = t->n_v;
+    d->t_hmax = t->h_max;
+    d->t_qmax = t->q_max;
+    d->t_fi = (double)(t->n_h - 1) / (t->h_max - a->h_obs);
+    d->t_fj = (double)(t->n_q - 1) / t->q_max;
+    d->t_fk = (double)(t->n_v - 1) / (t->h_max - a->h_obs);
   }
   return PHOTON_OK;
 }
@@ -1827,13 +1919,15 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
                     DeviceState* dev, hipStream_t st, size_t dyn_lds = 0) {
   int occ;
   const bool radial = !SPLAT && sk.kind == PHOTON_SINK_RADIAL;
-  if (radial) {
+  const bool table = !SPLAT && atm.tcorr != nullptr;
+  // the kernel instance: sink (generic, radial) and propagation (exact, table)
+  const void* kfn = (const void*)k_fused<T, BS, SPLAT>;
+  if (radial) kfn = table ? (const void*)k_fused<T, BS, false, true, true> : (const void*)k_fused<T, BS, false, true>;
+  else if (table) kfn = (const void*)k_fused<T, BS, false, false, true>;
+  if (radial || table) {
     // the radial bins live in dynamic LDS: count, weight and w t per bin
-    dyn_lds = (size_t)3 * sizeof(unsigned long long) * (size_t)sk.n_bins;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<T, BS, false, true>, BS, dyn_lds) !=
-            hipSuccess ||
-        occ < 1)
-      occ = 1;
+    if (radial) dyn_lds = (size_t)3 * sizeof(unsigned long long) * (size_t)sk.n_bins;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, BS, dyn_lds) != hipSuccess || occ < 1) occ = 1;
   } else if (!SPLAT) {
     occ = fused_occupancy<T, BS>(dev);
   } else {
@@ -1875,10 +1969,9 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   A.defer_pref = dev->defer_pref;
   A.n_defer_blocks = (int32_t)grid;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
-  if (radial)
-    hipLaunchKernelGGL((k_fused<T, BS, false, true>), dim3((unsigned)grid), dim3(BS), dyn_lds, st, A);
-  else
-    hipLaunchKernelGGL((k_fused<T, BS, SPLAT>), dim3((unsigned)grid), dim3(BS), dyn_lds, st, A);
+  void* kargs[] = {&A};
+  if (hipLaunchKernel(kfn, dim3((unsigned)grid), dim3(BS), kargs, dyn_lds, st) != hipSuccess)
+    return fail(PHOTON_EHIP, "fused kernel launch failed");
   if (defer) {
     hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
                        (int)grid, A.defer_cap, dev->defer_pref);
@@ -2029,6 +2122,7 @@ int prep_splat_call(const photon_segments* seg, const photon_atmosphere* atm, do
   em.lambda_max_nm = lambda_max_nm;
   if ((rc = prep_seg(seg, &c->sv, false))) return rc;
   if ((rc = prep_atm(atm, &c->ad))) return rc;
+  if (c->ad.tcorr) return fail(PHOTON_EINVAL, "the differentiable form takes the exact propagation: atmosphere.table must be NULL");
   if ((rc = prep_emission(&em, &c->g))) return rc;
   if ((rc = prep_precision(precision))) return rc;
   if ((rc = prep_splat_grid(grid, &c->sg))) return rc;
@@ -2334,6 +2428,25 @@ int photon_count(const photon_segments* seg, const photon_atmosphere* atm, const
                  uint64_t seed, uint32_t* counts, uint64_t* offsets, void* stream) {
   if (!em) return fail(PHOTON_EINVAL, "emission is NULL");
   return generate_common(seg, atm, em, seed, PHOTON_FP64, counts, offsets, nullptr, stream);
+}
+
+int photon_table_build(const photon_atmosphere* atm, photon_table* table, void* stream) {
+  if (!atm || !table) return fail(PHOTON_EINVAL, "atmosphere or table is NULL");
+  photon_atmosphere a = *atm;
+  a.table = nullptr;
+  AtmDev ad;
+  int rc;
+  if ((rc = prep_atm(&a, &ad))) return rc;
+  if ((rc = check_table_shape(&a, table))) return rc;
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  const int64_t n = (int64_t)table->n_h * table->n_q + table->n_v;
+  hipLaunchKernelGGL(k_table_build, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, (hipStream_t)stream, ad,
+                     table->n_h, table->n_q, table->n_v, table->h_max, table->q_max, (float4*)table->corr,
+                     (float2*)table->vert);
+  if ((rc = check_launch())) return rc;
+  table->atm_hash = atm_hash(&a);
+  return PHOTON_OK;
 }
 
 int photon_radial_profile(const photon_sink* sink, double* density, double* mean_t_ns, void* stream) {

@@ -88,6 +88,12 @@ struct AtmDev {
   double abs_l0, abs_inv_step;
   double abs_l[PHOTON_MAX_ABS];
   double abs_k[PHOTON_MAX_ABS];
+  // straight-line propagation with correction tables (tcorr = NULL: exact)
+  const float4* tcorr;                // (g, dP, dX, 0) per node, q fastest
+  const float2* tvert;                // (rho/rho0, vertical column) per height node
+  int32_t tn_h, tn_q, tn_v;
+  double t_hmax, t_qmax;
+  double t_fi, t_fj, t_fk;            // nodes per metre of height, per unit of q, per metre (vertical)
 };
 
 // Layer of height h: the last k with hb[k] <= h (hb is +inf beyond the last
@@ -293,8 +299,20 @@ struct Fm<float> {
 // Per-segment constants of photon generation, computed once per segment
 // (one lane per segment) and shared by all of its photons.
 // ---------------------------------------------------------------------------
+// Float form: the cone's dominant vertical terms in double. A photon's
+// vertical direction component is 2 (A.p) A_z - p_z, dominated by A_z p_z;
+// rounded to float its absolute error (a few 1e-7) becomes a relative error
+// of the slant path of 1/cos(zenith) times that, about 0.15 ns on steep rays.
 template <typename T>
-struct SegConst {
+struct SegHi {
+  double cos_cd;  // cone cosine (Cherenkov) or 1 - cos of the beaming cone (beamed fluorescence)
+  double azd;     // vertical component of the M_Rod bisector
+};
+template <>
+struct SegHi<double> {};
+
+template <typename T>
+struct SegConst : SegHi<T> {
   double x0, y0, z0, t0, inv_bc;   // start point, start time, 1/(beta c)
   T dx, dy, dz, len;               // unit direction, length
   T cos_c, sin_c;                  // Cherenkov cone (section 1.2); beamed fluorescence: cos_c = om
@@ -352,14 +370,23 @@ __device__ __forceinline__ void seg_const(const SegView& s, int64_t i, const Atm
     c.ax = (T)bx;
     c.ay = (T)by;
     c.az = (T)bz;
+    if constexpr (sizeof(T) == 4) {
+      c.cos_cd = cc;
+      c.azd = bz;
+    }
   } else if (beam.on) {
     double ax, ay, az, bx, by, bz;
-    c.cos_c = (T)beam_cap(s, i, beam, &ax, &ay, &az);
+    const double om = beam_cap(s, i, beam, &ax, &ay, &az);
+    c.cos_c = (T)om;
     c.sin_c = (T)0;
     rod_bisector(ax, ay, az, &bx, &by, &bz);
     c.ax = (T)bx;
     c.ay = (T)by;
     c.az = (T)bz;
+    if constexpr (sizeof(T) == 4) {
+      c.cos_cd = om;
+      c.azd = bz;
+    }
   } else {
     c.cos_c = c.sin_c = c.ax = c.ay = c.az = (T)0;
   }
@@ -409,8 +436,15 @@ __device__ __forceinline__ void gen_cherenkov(const SegConst<T>& c, uint32_t j, 
   const T ap2 = (T)2 * (c.ax * px + c.ay * py + c.az * pz);
   p.ux = ap2 * c.ax - px;
   p.uy = ap2 * c.ay - py;
-  p.uz = ap2 * c.az - pz;
-  p.uzd = (double)p.uz;
+  if constexpr (sizeof(T) == 4) {
+    // the dominant A_z p_z term in double (the small horizontal terms in float)
+    const double pzd = -c.cos_cd;
+    p.uzd = 2.0 * ((double)(c.ax * px + c.ay * py) + c.azd * pzd) * c.azd - pzd;
+    p.uz = (T)p.uzd;
+  } else {
+    p.uz = ap2 * c.az - pz;
+    p.uzd = p.uz;
+  }
   p.lambda = Fm<T>::rcp(inv_l1 - u2 * inv_dl);
   p.w = (T)1;
   p.path = 0.0;
@@ -444,8 +478,16 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
     const T ap2 = (T)2 * (c.ax * px + c.ay * py + c.az * pz);
     p.ux = ap2 * c.ax - px;
     p.uy = ap2 * c.ay - py;
-    p.uz = ap2 * c.az - pz;
-    p.uzd = (double)p.uz;
+    if constexpr (sizeof(T) == 4) {
+      // the dominant A_z p_z term in double, p_z = -(1 - u1 om)
+      const double vd = u01<double>(r.w[1]) * c.cos_cd;
+      const double pz2 = vd - 1.0;
+      p.uzd = 2.0 * ((double)(c.ax * px + c.ay * py) + c.azd * pz2) * c.azd - pz2;
+      p.uz = (T)p.uzd;
+    } else {
+      p.uz = ap2 * c.az - pz;
+      p.uzd = p.uz;
+    }
   } else {
     // cos = 1 - 2 u1 = -(w - 2^31 + 1/2) 2^-31, and 1 - u1 = u(~w): both
     // taken from the 32-bit word, so rays near the horizon keep their
@@ -675,7 +717,75 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C
 
 // DEFER (float only): a near-horizon ray is only marked kDeferred.
 // FORCE_FLOAT (float only): every ray is evaluated in float.
-template <typename T, bool DEFER = false, bool FORCE_FLOAT = false>
+// The exact integrals in double of a ray from height ze (zenith cosine ced,
+// sine sed) down to h_obs; em_out: expm1 of the density drop from the
+// emission layer's base to ze.
+__device__ __forceinline__ void exact_ray_double(const AtmDev& a, const AtmLane& L, double ze, double sed, double ced,
+                                                 double& g0, double& pth, double& opt, double& col, double& ne,
+                                                 double& em_out, double& rho_bot_out) {
+  const int le = layer_of(a, ze);
+  const double bot = (le == a.l_obs) ? a.hobs : L.hb[le];
+  const double rho_bot = (le == a.l_obs) ? a.rho_obs : L.rb[le];
+  const bool homog_e = (a.homog_mask >> le) & 1;
+  const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * L.invH[le]);
+  const double rho_e = rho_bot * (1.0 + em_e);
+  ray_pieces<double>(a, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
+  em_out = em_e;
+  rho_bot_out = rho_bot;
+}
+
+template <typename T>
+__device__ __forceinline__ T lerp_t(T a, T b, T t) {
+  return a + (b - a) * t;
+}
+
+// Straight line plus tabulated corrections (section 2) for a downward photon
+// at or above h_obs (unit direction ux, uy; zenith cosine mu, sine se).
+// Returns false when the photon lies outside the table (above h_max or
+// steeper than q_max): the caller then takes the exact integrals.
+template <typename T>
+__device__ __forceinline__ bool propagate_table(const AtmDev& a, const AtmLane& L, T ux, T uy, T mu, T se,
+                                                Photon<T>& p) {
+  using F = Fm<T>;
+  const double dh = p.z - a.hobs;
+  const T q = se * F::rcp(mu);
+  if (!(p.z <= a.t_hmax) || !(q <= (T)a.t_qmax)) return false;
+  const T fi = (T)(dh * a.t_fi), fj = q * (T)a.t_fj;
+  const int i = min((int)fi, a.tn_h - 2), j = min((int)fj, a.tn_q - 2);
+  const T ta = fi - (T)i, tb = fj - (T)j;
+  const float4* c = a.tcorr + (size_t)i * (size_t)a.tn_q + (size_t)j;
+  const float4 c00 = c[0], c01 = c[1], c10 = c[a.tn_q], c11 = c[a.tn_q + 1];
+  const T g = lerp_t(lerp_t((T)c00.x, (T)c01.x, tb), lerp_t((T)c10.x, (T)c11.x, tb), ta);
+  const T dP = lerp_t(lerp_t((T)c00.y, (T)c01.y, tb), lerp_t((T)c10.y, (T)c11.y, tb), ta);
+  const T dX = lerp_t(lerp_t((T)c00.z, (T)c01.z, tb), lerp_t((T)c10.z, (T)c11.z, tb), ta);
+  const T fk = (T)(dh * a.t_fk);
+  const int k = min((int)fk, a.tn_v - 2);
+  const T tk = fk - (T)k;
+  const float2 v0 = a.tvert[k], v1 = a.tvert[k + 1];
+  const T rho_e = lerp_t((T)v0.x, (T)v1.x, tk);
+  const T VX = lerp_t((T)v0.y, (T)v1.y, tk);
+  const double sec = 1.0 / (double)mu;
+  const double P = dh * sec + (double)dP;
+  const T X = (T)sec * VX + dX;
+  const double O = P + a.eta0 * (double)X;
+  const double disp = (dh + (double)g) * sec;
+  p.x = (T)((double)p.x + (double)ux * disp);
+  p.y = (T)((double)p.y + (double)uy * disp);
+  p.z = a.hobs;
+  p.t = p.t + O * (1.0 / kC);
+  p.path = P;
+  p.w = F::exp_(-(abs_coeff<T>(a, L, p.lambda) * X));
+  const T r = ((T)1 + (T)a.eta0 * rho_e) * (T)(1.0 / a.n_obs);
+  const T sl = r * se;
+  p.ux = ux * r;
+  p.uy = uy * r;
+  p.uz = -F::sqrt_(((T)1 - sl) * ((T)1 + sl));
+  p.status = PHOTON_LANDED;
+  return true;
+}
+
+// TABLE: try the straight line with corrections first (a.tcorr set).
+template <typename T, bool DEFER = false, bool FORCE_FLOAT = false, bool TABLE = false>
 __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Photon<T>& p) {
   using F = Fm<T>;
   if (p.status != PHOTON_LANDED) return;
@@ -696,6 +806,9 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
   const double ced = sizeof(T) == 8 ? -p.uzd * (double)inv_un : -p.uzd;
   const double sed = sizeof(T) == 8 ? sqrt((1.0 - ced) * (1.0 + ced)) : sqrt_refined((1.0 - ced) * (1.0 + ced));
   const T ce = (T)ced, se = (T)sed;
+  if constexpr (TABLE) {
+    if (propagate_table<T>(a, L, ux, uy, ce, se, p)) return;
+  }
   const int le = layer_of(a, ze);
   const double bot = (le == a.l_obs) ? a.hobs : L.hb[le];
   const double rho_bot = (le == a.l_obs) ? a.rho_obs : L.rb[le];
@@ -722,13 +835,11 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
     }
   }
   if (!done) {
-    double cold, ned;
-    const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * invH_e);
-    const double rho_e = rho_bot * (1.0 + em_e);
-    ray_pieces<double>(a, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, cold, ned);
+    double cold, ned, emd, rbd;
+    exact_ray_double(a, L, ze, sed, ced, g0, pth, opt, cold, ned, emd, rbd);
     col = (T)cold;
     ne = (T)ned;
-    em_out = (T)em_e;
+    em_out = (T)emd;
   }
   const double disp = (double)ne * g0;
   p.x = (T)((double)p.x + (double)ux * disp);

@@ -33,7 +33,12 @@ class Atmosphere(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("h_base", C.c_double * MAX_LAYERS),
                 ("scale_height", C.c_double * MAX_LAYERS), ("n0_minus_1", C.c_double),
                 ("h_obs", C.c_double), ("n_abs", C.c_int32), ("abs_lambda_nm", C.c_double * MAX_ABS),
-                ("abs_k_per_m", C.c_double * MAX_ABS)]
+                ("abs_k_per_m", C.c_double * MAX_ABS), ("table", P)]
+
+
+class TableStruct(C.Structure):
+    _fields_ = [("n_h", C.c_int32), ("n_q", C.c_int32), ("n_v", C.c_int32), ("h_max", C.c_double),
+                ("q_max", C.c_double), ("corr", P), ("vert", P), ("atm_hash", C.c_uint64)]
 
 
 class Segments(C.Structure):
@@ -115,6 +120,7 @@ def lib():
         L.photon_count.argtypes = [P, P, P, C.c_uint64, P, P, P]
         L.photon_generate.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P]
         L.photon_radial_profile.argtypes = [P, P, P, P]
+        L.photon_table_build.argtypes = [P, P, P]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
@@ -149,6 +155,28 @@ def init():
 
 
 # ------------------------------------------------------------------ inputs --
+class PropagationTable:
+    """Correction tables of the straight-line propagation (section 2) for one
+    atmosphere, resident on the GPU; built on construction."""
+
+    def __init__(self, atm: Atmosphere, n_h=257, n_q=257, h_max=40000.0, q_max=float(np.tan(np.radians(80.0))),
+                 n_v=4097, device="cuda"):
+        self.corr = torch.zeros(4 * n_h * n_q, dtype=torch.float32, device=device)
+        self.vert = torch.zeros(2 * n_v, dtype=torch.float32, device=device)
+        self.s = TableStruct()
+        self.s.n_h, self.s.n_q, self.s.n_v = int(n_h), int(n_q), int(n_v)
+        self.s.h_max, self.s.q_max = float(h_max), float(q_max)
+        self.s.corr, self.s.vert = self.corr.data_ptr(), self.vert.data_ptr()
+        _check(lib().photon_table_build(C.byref(atm), C.byref(self.s), _stream()))
+
+    def attach(self, atm: Atmosphere) -> Atmosphere:
+        """A copy of atm that propagates with this table (keeps the table alive)."""
+        a = Atmosphere.from_buffer_copy(atm)
+        a.table = C.addressof(self.s)
+        a._table_owner = self
+        return a
+
+
 def atmosphere(d: dict) -> Atmosphere:
     a = Atmosphere()
     hb, H = d["h_base"], d["scale_height"]

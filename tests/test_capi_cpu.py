@@ -284,3 +284,29 @@ def test_radial_validation(ph):
         assert prof(sink(**bad)) == ph.EINVAL, bad
     assert prof(sink(), out=None) == ph.EINVAL
     assert prof(sink(r_min=0.0, log_bins=0)) == ph.ENODEV
+
+
+def test_table_validation(ph):
+    """Correction tables: shape checks and the atmosphere fingerprint, before
+    device work."""
+    L = ph.lib()
+    atm = _valid_atm(ph)
+
+    def table(**kw):
+        t = ph.TableStruct()
+        t.n_h, t.n_q, t.n_v, t.h_max, t.q_max, t.corr, t.vert = 17, 17, 257, 40000.0, 5.0, 0x1000, 0x2000
+        for k, v in kw.items():
+            setattr(t, k, v)
+        return t
+
+    assert L.photon_table_build(C.byref(atm), C.byref(table()), None) == ph.ENODEV
+    for bad in (dict(n_h=1), dict(n_q=5000), dict(n_v=1), dict(h_max=1000.0), dict(q_max=0.0),
+                dict(q_max=float("nan")), dict(corr=None)):
+        assert L.photon_table_build(C.byref(atm), C.byref(table(**bad)), None) == ph.EINVAL, bad
+    # a table that was never built (hash 0) or built for another atmosphere
+    t = table()
+    a2 = ph.Atmosphere.from_buffer_copy(atm)
+    a2.table = C.addressof(t)
+    seg = _fake_segments(ph)
+    assert _gen(ph, seg, a2) == ph.EINVAL
+    assert b"not built for this atmosphere" in L.photon_last_error()
