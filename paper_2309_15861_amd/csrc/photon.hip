@@ -305,6 +305,16 @@ __device__ __forceinline__ void generate(const SegConst<T>& c, uint32_t j, const
     gen_fluor<T>(c, j, k0, k1, thr, lines, g.n_lines, g.beam.on != 0, p);
 }
 
+// The same with the emission kind fixed at compile time.
+template <typename T, bool CHER>
+__device__ __forceinline__ void generate_kind(const SegConst<T>& c, uint32_t j, const GenParams& g, uint32_t k0,
+                                              uint32_t k1, const uint64_t* thr, const T* lines, Photon<T>& p) {
+  if constexpr (CHER)
+    gen_cherenkov<T>(c, j, k0, k1, (T)g.inv_l1, (T)g.inv_dl, p);
+  else
+    gen_fluor<T>(c, j, k0, k1, thr, lines, g.n_lines, g.beam.on != 0, p);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gen(SegView seg, int64_t n_seg, AtmDev atm, GenParams g, uint32_t k0,
                                              uint32_t k1, const uint64_t* __restrict__ offsets, int64_t n_ph,
@@ -717,22 +727,34 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // searches and their constants staged in LDS; every photon is generated,
 // propagated and collected in registers. In the float form, rays near the
 // horizon are appended to a queue for the double pass instead.
-template <typename T, int BS, bool SPLAT = false, bool RADIAL = false, bool TABLE = false>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !SPLAT && BS >= 256) ? 4 : 1))) void k_fused(FusedArgs A) {
-  // the double splat keeps a smaller window so that the whole grid fits in LDS beside it
-  constexpr int kWin = (SPLAT && sizeof(T) == 8) ? kWindow / 2 : kWindow;
+// Kernel instances (MODE bits): the sink of the differentiable form, the
+// radial profile sink, the correction-table propagation, fluorescence
+// emission (else Cherenkov). Each carries only its own code.
+constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8;
+
+template <typename T, int BS, int MODE = 0>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !(MODE & kMSplat) && BS >= 256) ? 4 : 1))) void k_fused(FusedArgs A) {
+  constexpr bool SPLAT = (MODE & kMSplat) != 0;
+  constexpr bool RADIAL = (MODE & kMRadial) != 0;
+  constexpr bool TABLE = (MODE & kMTable) != 0;
+  constexpr bool CHER = (MODE & kMFluo) == 0;
+  // the splat keeps a smaller window so that the whole grid fits in LDS beside it
+  constexpr int kWin = SPLAT ? kWindow / 2 : kWindow;
+  // telescope tables only where a telescope sink can occur
+  constexpr int kTel = (SPLAT || RADIAL) ? 1 : PHOTON_MAX_TELESCOPES;
+  constexpr int kCand = (SPLAT || RADIAL) ? 1 : kCandCells * kCandCells;
   __shared__ SegConst<T> s_seg[kWin];
   __shared__ uint64_t s_off[kWin + 1];
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ T s_lines[PHOTON_MAX_LINES];
-  __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  __shared__ double s_tel[kTel][4];
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ unsigned int s_dcount;
   __shared__ HitStageLds<SPLAT || RADIAL> s_hs;
   __shared__ T s_wsc[SPLAT ? kWin : 1];  // SPLAT: per-segment weight factors mu/mu0
   __shared__ AtmLane s_lane;
-  __shared__ uint32_t s_cand[kCandCells * kCandCells];
+  __shared__ uint32_t s_cand[kCand];
   // slot map of a chunk: bit i of s_bits is set where a segment of the window
   // starts at photon c0 + i; s_pre holds the set bits before each word and
   // s_slot[r] the window slot of the r-th start (r = 0: the segment holding c0)
@@ -758,12 +780,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = (T)A.g.line_nm[tid];
   }
-  if constexpr (!SPLAT) {
+  if constexpr (!SPLAT && !RADIAL) {
+    static_assert(kTel == PHOTON_MAX_TELESCOPES && kCand == kCandCells * kCandCells, "full telescope tables");
     for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
     for (int k = tid; k < kCandCells * kCandCells; k += BS) s_cand[k] = A.sk.cand_mask[k];
   }
   atm_lane_fill(A.atm, &s_lane);
-  const bool cher = A.g.kind == PHOTON_CHERENKOV;
+  constexpr bool cher = CHER;
   const int64_t n_seg = A.n_seg;
   const uint64_t* __restrict__ offsets = A.offsets;
   WaveStatus ws;
@@ -868,7 +891,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
         }
         const uint32_t j = (uint32_t)(q - off_s);
         Photon<T> p;
-        generate<T>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
+        generate_kind<T, CHER>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
         propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p);
         if constexpr (SPLAT) p.w *= wsc;
         if (kDefer) {
@@ -1431,6 +1454,7 @@ int prep_atm(const photon_atmosphere* a, AtmDev* d) {
   std::memset(d, 0, sizeof *d);
   d->nl = a->n_layers;
   d->n_abs = a->n_abs;
+  d->hb[PHOTON_MAX_LAYERS] = HUGE_VAL;
   for (int i = 0; i < PHOTON_MAX_LAYERS; ++i) {
     const int k = i < a->n_layers ? i : a->n_layers - 1;
     // bases beyond the last layer are +inf: layer_of needs no layer count
@@ -1743,8 +1767,12 @@ struct DeviceState {
   unsigned long long* work = nullptr;  // [0] = fused work cursor, [kDeferCounts..] per-block deferred counts
   uint2* defer_q = nullptr;            // deferred (segment row, j), kDeferCap entries
   unsigned long long* defer_pref = nullptr;  // prefix sums of the per-block deferred counts
-  int occ[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fused blocks per CU by [precision][block 128/256/512]
-  int occ_splat[4] = {0, 0, 0, 0};          // splat fused blocks per CU (see launch_fused_bs)
+  struct OccEntry {
+    const void* fn;
+    size_t dyn;
+    int occ;
+  } occ_cache[96] = {};                     // fused blocks per CU by kernel instance and dynamic LDS
+  int n_occ = 0;
   int occ_adj[2] = {0, 0};                  // adjoint blocks per CU by precision
   double* adj_part = nullptr;               // per-block partial sums of the adjoint
   unsigned long long* splat_acc = nullptr;  // fixed-point grid of the splat
@@ -1871,28 +1899,38 @@ int launch_collect(const photon_block* b, const AtmDev& atm, const SinkDev& sk, 
   return check_launch();
 }
 
-constexpr int bs_slot(int bs) { return bs == 128 ? 0 : (bs == 256 ? 1 : 2); }
+// Blocks per CU of a kernel instance with a given dynamic LDS (cached).
+int occupancy_of(DeviceState* dev, const void* fn, int bs, size_t dyn) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < dev->n_occ; ++i)
+    if (dev->occ_cache[i].fn == fn && dev->occ_cache[i].dyn == dyn) return dev->occ_cache[i].occ;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, bs, dyn) != hipSuccess || occ < 1) occ = 1;
+  if (dev->n_occ < 96) dev->occ_cache[dev->n_occ++] = {fn, dyn, occ};
+  return occ;
+}
 
-// Resident blocks per CU of a fused variant, queried once per device (the
-// query is not a stream operation, but it is kept out of captured steps).
+// The fused kernel instance of a mode.
 template <typename T, int BS>
-int fused_occupancy(DeviceState* dev) {
-  int& o = dev->occ[sizeof(T) == 8 ? 0 : 1][bs_slot(BS)];
-  if (o == 0) {
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<T, BS>, BS, 0) != hipSuccess || occ < 1) occ = 1;
-    o = occ;
+const void* fused_instance(int mode) {
+  switch (mode) {
+    case kMSplat: return (const void*)k_fused<T, BS, kMSplat>;
+    case kMRadial: return (const void*)k_fused<T, BS, kMRadial>;
+    case kMTable: return (const void*)k_fused<T, BS, kMTable>;
+    case kMRadial | kMTable: return (const void*)k_fused<T, BS, kMRadial | kMTable>;
+    case kMFluo: return (const void*)k_fused<T, BS, kMFluo>;
+    case kMFluo | kMRadial: return (const void*)k_fused<T, BS, kMFluo | kMRadial>;
+    case kMFluo | kMTable: return (const void*)k_fused<T, BS, kMFluo | kMTable>;
+    case kMFluo | kMRadial | kMTable: return (const void*)k_fused<T, BS, kMFluo | kMRadial | kMTable>;
+    default: return (const void*)k_fused<T, BS, 0>;
   }
-  return o;
 }
 
 void warm_occupancy(DeviceState* dev) {
-  fused_occupancy<float, 128>(dev);
-  fused_occupancy<float, 256>(dev);
-  fused_occupancy<float, 512>(dev);
-  fused_occupancy<double, 128>(dev);
-  fused_occupancy<double, 256>(dev);
-  fused_occupancy<double, 512>(dev);
+  occupancy_of(dev, fused_instance<float, 256>(0), 256, 0);
+  occupancy_of(dev, fused_instance<float, 512>(0), 512, 0);
+  occupancy_of(dev, fused_instance<double, 256>(0), 256, 0);
+  occupancy_of(dev, fused_instance<double, 512>(0), 512, 0);
 }
 
 // The deferral queue of the float form, allocated on first use (not inside
@@ -1917,28 +1955,14 @@ template <typename T, int BS, bool SPLAT = false>
 int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                     const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
                     DeviceState* dev, hipStream_t st, size_t dyn_lds = 0) {
-  int occ;
   const bool radial = !SPLAT && sk.kind == PHOTON_SINK_RADIAL;
   const bool table = !SPLAT && atm.tcorr != nullptr;
-  // the kernel instance: sink (generic, radial) and propagation (exact, table)
-  const void* kfn = (const void*)k_fused<T, BS, SPLAT>;
-  if (radial) kfn = table ? (const void*)k_fused<T, BS, false, true, true> : (const void*)k_fused<T, BS, false, true>;
-  else if (table) kfn = (const void*)k_fused<T, BS, false, false, true>;
-  if (radial || table) {
-    // the radial bins live in dynamic LDS: count, weight and w t per bin
-    if (radial) dyn_lds = (size_t)3 * sizeof(unsigned long long) * (size_t)sk.n_bins;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, BS, dyn_lds) != hipSuccess || occ < 1) occ = 1;
-  } else if (!SPLAT) {
-    occ = fused_occupancy<T, BS>(dev);
-  } else {
-    // splat variants by precision and LDS grid
-    int& o = dev->occ_splat[(sizeof(T) == 8 ? 2 : 0) + (dyn_lds ? 0 : 1)];
-    if (o == 0) {
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_fused<T, BS, true>, BS, dyn_lds) != hipSuccess || o < 1)
-        o = 1;
-    }
-    occ = o;
-  }
+  const int mode = SPLAT ? kMSplat
+                         : ((radial ? kMRadial : 0) | (table ? kMTable : 0) | (g.kind == PHOTON_FLUORESCENCE ? kMFluo : 0));
+  const void* kfn = fused_instance<T, BS>(mode);
+  // the radial bins live in dynamic LDS: count, weight and w t per bin
+  if (radial) dyn_lds = (size_t)3 * sizeof(unsigned long long) * (size_t)sk.n_bins;
+  int occ = occupancy_of(dev, kfn, BS, dyn_lds);
   if (bpc > 0 && bpc < occ) occ = bpc;
   int64_t grid = (int64_t)dev->cu * occ;
   if (n_ph >= 0) {
@@ -2528,8 +2552,8 @@ int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* at
     // each block accumulates the whole grid in LDS when it fits beside the kernel's own LDS
     const size_t lds = (size_t)cells * sizeof(unsigned long long);
     hipFuncAttributes fa;
-    const void* kf = precision == PHOTON_FP32 ? reinterpret_cast<const void*>(&k_fused<float, 1024, true>)
-                                              : reinterpret_cast<const void*>(&k_fused<double, 512, true>);
+    const void* kf = precision == PHOTON_FP32 ? reinterpret_cast<const void*>(&k_fused<float, 1024, kMSplat>)
+                                              : reinterpret_cast<const void*>(&k_fused<double, 512, kMSplat>);
     const bool fits = hipFuncGetAttributes(&fa, kf) == hipSuccess && fa.sharedSizeBytes + lds <= dev->lds_per_block;
     sk.splat_lds = fits ? 1 : 0;
     if (precision == PHOTON_FP32)

@@ -362,21 +362,24 @@ __device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& s
   const T r_e = ne * (T)ced;  // r at the emission point
   double g0 = 0.0;
   T col = (T)0;
+  // piece constants from the LDS record of each layer (as in the forward
+  // propagation)
   {
     T r_top = r_e;
     for (int l = a.nl - 1; l >= a.l_obs; --l) {
       if (l > le) continue;
-      const double top = (l == le) ? ze : a.hb[l + 1];
-      const double bot = (l == a.l_obs) ? a.hobs : a.hb[l];
-      const double dh = top - bot;
+      const double* pc = L.pc[l];
+      const double top = (l == le) ? ze : pc[kPcTop];
+      const double dh = top - pc[kPcBot];
       if (!(dh > 0.0)) continue;
-      const T rho_a = (T)((l == a.l_obs) ? a.rho_obs : a.rb[l]);
-      const T em = (l == le) ? em_e : (T)((l == a.l_obs) ? a.em_obs : a.em_full[l]);
+      const bool homog = (a.homog_mask >> l) & 1;
+      const double H_l = pc[kPcH];
+      const T rho_a = (T)pc[kPcRho];
+      const T em = (l == le) ? em_e : (T)pc[kPcEm];
       const T eps_a = eta0 * rho_a;
       const T ra = F::sqrt_(C2 + eps_a * ((T)2 + eps_a));
       PieceD<T> o;
-      piece_d<T, false>(rho_a, em, dh, (T)a.H[l], (a.homog_mask >> l) & 1, eta0, C2, Cc, invC, invCd, S, ra, r_top,
-                        o);
+      piece_d<T, false>(rho_a, em, dh, (T)H_l, homog, eta0, C2, Cc, invC, invCd, S, ra, r_top, o);
       g0 += o.g;
       col += o.col;
       r_top = ra;
@@ -405,18 +408,22 @@ __device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& s
     T r_top = r_e;
     for (int l = a.nl - 1; l >= a.l_obs; --l) {
       if (l > le) continue;
-      const double top = (l == le) ? ze : a.hb[l + 1];
-      const double bot = (l == a.l_obs) ? a.hobs : a.hb[l];
+      const double* pc = L.pc[l];
+      const double top = (l == le) ? ze : pc[kPcTop];
+      const double bot = pc[kPcBot];
       const double dh = top - bot;
       if (!(dh > 0.0)) continue;
       const bool homog = (a.homog_mask >> l) & 1;
-      const T rho_a = (T)((l == a.l_obs) ? a.rho_obs : a.rb[l]);
-      const T em = (l == le) ? em_e : (T)((l == a.l_obs) ? a.em_obs : a.em_full[l]);
+      const bool is_obs = l == a.l_obs;
+      const double H_l = pc[kPcH];
+      const double invH_l = L.invH[l];
+      const T rho_a = (T)pc[kPcRho];
+      const T em = (l == le) ? em_e : (T)pc[kPcEm];
       const T rho_b = rho_a * ((T)1 + em);
       const T eps_a = eta0 * rho_a;
       const T ra = F::sqrt_(C2 + eps_a * ((T)2 + eps_a));
       PieceD<T> o;
-      piece_d<T, true>(rho_a, em, dh, (T)a.H[l], homog, eta0, C2, Cc, invC, invCd, S, ra, r_top, o);
+      piece_d<T, true>(rho_a, em, dh, (T)H_l, homog, eta0, C2, Cc, invC, invCd, S, ra, r_top, o);
       C2_b += g0_b * o.g_C2 + col_b * o.c_C2;
       const T ea_b = g0_b * o.g_ea + col_b * o.c_ea;
       const T eb_b = g0_b * o.g_eb + col_b * o.c_eb;
@@ -433,7 +440,7 @@ __device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& s
       // rho_obs = rb[l_obs] exp(-(h_obs - hb[l_obs])/H[l_obs])
       const double tb = (double)(ra_b * rho_a);
       acc.lnrb(l, tb);
-      if (l == a.l_obs) acc.H(l, tb * (a.hobs - a.hb[l]) * a.invH[l] * a.invH[l]);
+      if (is_obs) acc.H(l, tb * (bot - L.hb[l]) * invH_l * invH_l);
       // density at the top: rb[l + 1], or rho_e for the emission piece
       if (l == le) {
         rhoe_b += rb_b;

@@ -75,7 +75,7 @@ __device__ __forceinline__ float u01<float>(uint32_t x) { return u01f(x); }
 struct AtmDev {
   int32_t nl;
   int32_t n_abs;
-  double hb[PHOTON_MAX_LAYERS];
+  double hb[PHOTON_MAX_LAYERS + 1];  // +inf beyond the last layer (hb[l + 1] is the top of layer l)
   double H[PHOTON_MAX_LAYERS];
   double rb[PHOTON_MAX_LAYERS];
   double eta0, hobs, rho_obs, n_obs;
@@ -589,9 +589,17 @@ __device__ __forceinline__ void piece_integrals(T rho_a, T em, T dh, T H, bool h
 // into LDS by every kernel that propagates (lane-indexed reads of a kernel
 // argument would be vector memory loads). abs_s[i] is the slope of the
 // absorption coefficient on [abs_l[i], abs_l[i+1]].
+// pc[l]: the piece of layer l a downward ray crosses, with the observation
+// layer folded in: bottom (h_obs in the observation layer, else the layer
+// base), top (the next base, +inf for the top layer), rho/rho0 at the
+// bottom, expm1 of the density drop from bottom to top, scale height. A ray
+// loop reads it with its wave-uniform layer index (broadcast LDS reads:
+// neither scalar registers nor vector memory).
+enum { kPcBot = 0, kPcTop, kPcRho, kPcEm, kPcH, kPcWords = 6 };
 struct AtmLane {
   double hb[PHOTON_MAX_LAYERS], rb[PHOTON_MAX_LAYERS], invH[PHOTON_MAX_LAYERS];
   double abs_l[PHOTON_MAX_ABS], abs_k[PHOTON_MAX_ABS], abs_s[PHOTON_MAX_ABS];
+  double pc[PHOTON_MAX_LAYERS][kPcWords];
 };
 
 // Block-cooperative copy; the caller synchronises before use.
@@ -600,6 +608,15 @@ __device__ __forceinline__ void atm_lane_fill(const AtmDev& a, AtmLane* L) {
     L->hb[i] = a.hb[i];
     L->rb[i] = a.rb[i];
     L->invH[i] = a.invH[i];
+  }
+  for (int i = threadIdx.x; i < PHOTON_MAX_LAYERS; i += blockDim.x) {
+    const bool obs = i == a.l_obs;
+    L->pc[i][kPcBot] = obs ? a.hobs : a.hb[i];
+    L->pc[i][kPcTop] = a.hb[i + 1];
+    L->pc[i][kPcRho] = obs ? a.rho_obs : a.rb[i];
+    L->pc[i][kPcEm] = obs ? a.em_obs : a.em_full[i];
+    L->pc[i][kPcH] = a.H[i];
+    L->pc[i][kPcH + 1] = 0.0;
   }
   for (int i = threadIdx.x; i < PHOTON_MAX_ABS; i += blockDim.x) {
     L->abs_l[i] = a.abs_l[i];
@@ -664,8 +681,9 @@ constexpr int kDeferred = 7;
 // ced/sed: cosine and sine of the emission zenith angle in double; the float
 // form takes C^2 and the dominant 1/C from them.
 template <typename C>
-__device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C em_e, C rho_e, double sed,
-                                           double ced, double& g0, double& pth, double& opt, C& col, C& ne) {
+__device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, int le, double ze, C em_e, C rho_e,
+                                           double sed, double ced, double& g0, double& pth, double& opt, C& col,
+                                           C& ne) {
   using F = Fm<C>;
   const C eta0 = (C)a.eta0;
   const C eps_e = eta0 * rho_e;
@@ -690,21 +708,24 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, int le, double ze, C
   pth = 0.0;
   opt = 0.0;
   // the layer index runs wave-uniformly (lanes above their emission layer
-  // skip the iteration), so the layer constants stay in scalar registers
+  // skip the iteration); the piece constants come from the LDS record of
+  // the layer (a kernel-argument array indexed under per-lane selects would
+  // be read by vector loads with their full latency)
 #pragma unroll 1
   for (int l = a.nl - 1; l >= a.l_obs; --l) {
     if (l > le) continue;
-    const double top = (l == le) ? ze : a.hb[l + 1];
-    const double bot = (l == a.l_obs) ? a.hobs : a.hb[l];
-    const double dh = top - bot;
+    const double* pc = L.pc[l];
+    const double top = (l == le) ? ze : pc[kPcTop];
+    const double dh = top - pc[kPcBot];
     if (!(dh > 0.0)) continue;
-    const C rho_a = (C)((l == a.l_obs) ? a.rho_obs : a.rb[l]);
-    const C em = (l == le) ? em_e : (C)((l == a.l_obs) ? a.em_obs : a.em_full[l]);
+    const C rho_a = (C)pc[kPcRho];
+    const C em = (l == le) ? em_e : (C)pc[kPcEm];
+    const double H_l = pc[kPcH];
+    const bool homog = (a.homog_mask >> l) & 1;
     const C eps_a = eta0 * rho_a;
     const C ra = F::sqrt_(C2 + eps_a * ((C)2 + eps_a));
-    const bool homog = (a.homog_mask >> l) & 1;
     PieceOut<C> o;
-    piece_integrals<C>(rho_a, em, (C)dh, (C)a.H[l], homog, eta0, C2, Cc, invC, S, ra, r_top, o);
+    piece_integrals<C>(rho_a, em, (C)dh, (C)H_l, homog, eta0, C2, Cc, invC, S, ra, r_top, o);
     const double main = homog ? dh / (double)ra : (C2 > (C)0 ? dh * invCd : 0.0);
     const double gp = main + (double)o.g0c;
     g0 += gp;
@@ -729,7 +750,7 @@ __device__ __forceinline__ void exact_ray_double(const AtmDev& a, const AtmLane&
   const bool homog_e = (a.homog_mask >> le) & 1;
   const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * L.invH[le]);
   const double rho_e = rho_bot * (1.0 + em_e);
-  ray_pieces<double>(a, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
+  ray_pieces<double>(a, L, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
   em_out = em_e;
   rho_bot_out = rho_bot;
 }
@@ -826,7 +847,7 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
     const T S = ((T)1 + eps_e) * se;
     const T C2 = (ce * ce * F::rcp((T)1 + se) - eps_e * se) * ((T)1 + S);
     if (FORCE_FLOAT || C2 > (T)kNearHorizonC2) {
-      ray_pieces<T>(a, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
+      ray_pieces<T>(a, L, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
       em_out = em_e;
       done = true;
     } else if (DEFER) {
