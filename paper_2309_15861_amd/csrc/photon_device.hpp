@@ -286,12 +286,28 @@ template <>
 struct Fm<float> {
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-  // log1p(x) = log(u) x / (u - 1) with u = 1 + x rounded (exact u - 1)
+  // log1p(x) = log(u) x / (u - 1) with u = 1 + x rounded (exact u - 1);
+  // log(u) = log2(u) ln 2 from the hardware log2 (u lies near 1 here: no
+  // denormal or infinite argument to guard against)
   static __device__ __forceinline__ float log1p_(float x) {
     const float u = 1.0f + x;
-    return (u == 1.0f) ? x : __logf(u) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
+    return (u == 1.0f) ? x
+                       : (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
   }
-  static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+  // expm1 for x <= 0: Taylor polynomial to x^8 for |x| < 0.5 (truncation
+  // 1e-8 relative), else exp(x) - 1, where 1 - e^x > 0.39 keeps the
+  // subtraction well conditioned; about 2e-7 relative either way
+  static __device__ __forceinline__ float expm1_(float x) {
+    float p = 2.48015873e-05f;  // 1/8!
+    p = __builtin_fmaf(p, x, 1.98412698e-04f);
+    p = __builtin_fmaf(p, x, 1.38888889e-03f);
+    p = __builtin_fmaf(p, x, 8.33333333e-03f);
+    p = __builtin_fmaf(p, x, 4.16666667e-02f);
+    p = __builtin_fmaf(p, x, 1.66666667e-01f);
+    p = __builtin_fmaf(p, x, 0.5f);
+    p = __builtin_fmaf(p, x, 1.0f);
+    return fabsf(x) < 0.5f ? p * x : __expf(x) - 1.0f;
+  }
   static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
 };
 
