@@ -882,6 +882,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
           c = s_seg[a];
           if constexpr (SPLAT) wsc = s_wsc[a];
           off_s = s_off[a];
+          // keeps the LDS load and the global one below apart (merged, they
+          // would become one generic load through a selected pointer)
+          asm volatile("" : "+v"(off_s));
           s = lo + a;
         } else {
           s = lane_upper_index(offsets, n_seg, q);

@@ -341,8 +341,8 @@ __device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& s
   const double ced = -(double)uz;
   const double sed = sqrt((1.0 - ced) * (1.0 + ced));
   const int le = layer_of(a, ze);
-  const double bot_e = (le == a.l_obs) ? a.hobs : L.hb[le];
-  const double rho_bot_e = (le == a.l_obs) ? a.rho_obs : L.rb[le];
+  const double bot_e = L.pc[le][kPcBot];
+  const double rho_bot_e = L.pc[le][kPcRho];
   const bool homog_e = (a.homog_mask >> le) & 1;
   const T eta0 = (T)a.eta0;
   const T em_e = homog_e ? (T)0 : F::expm1_((T)(-(ze - bot_e) * L.invH[le]));

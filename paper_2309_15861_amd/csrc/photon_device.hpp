@@ -761,8 +761,10 @@ __device__ __forceinline__ void exact_ray_double(const AtmDev& a, const AtmLane&
                                                  double& g0, double& pth, double& opt, double& col, double& ne,
                                                  double& em_out, double& rho_bot_out) {
   const int le = layer_of(a, ze);
-  const double bot = (le == a.l_obs) ? a.hobs : L.hb[le];
-  const double rho_bot = (le == a.l_obs) ? a.rho_obs : L.rb[le];
+  // the emission layer's piece record (LDS): a select between a kernel
+  // argument and an LDS array would become a generic (flat) load
+  const double bot = L.pc[le][kPcBot];
+  const double rho_bot = L.pc[le][kPcRho];
   const bool homog_e = (a.homog_mask >> le) & 1;
   const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * L.invH[le]);
   const double rho_e = rho_bot * (1.0 + em_e);
@@ -847,8 +849,10 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
     if (propagate_table<T>(a, L, ux, uy, ce, se, p)) return;
   }
   const int le = layer_of(a, ze);
-  const double bot = (le == a.l_obs) ? a.hobs : L.hb[le];
-  const double rho_bot = (le == a.l_obs) ? a.rho_obs : L.rb[le];
+  // the emission layer's piece record (LDS): a select between a kernel
+  // argument and an LDS array would become a generic (flat) load
+  const double bot = L.pc[le][kPcBot];
+  const double rho_bot = L.pc[le][kPcRho];
   const double invH_e = L.invH[le];
   const bool homog_e = (a.homog_mask >> le) & 1;
 
