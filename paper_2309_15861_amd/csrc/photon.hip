@@ -406,31 +406,30 @@ struct StatusCounter {
   }
 };
 
-// Status totals of a wave counted with ballots: the counts are the same in
-// every lane, so every lane of the wave calls add at the same point (st < 0
-// counts nothing) and lane 0 holds the wave's totals.
-struct WaveStatus {
-  unsigned long long c[PHOTON_N_STATUS];
-  __device__ void clear() {
-#pragma unroll
-    for (int k = 0; k < PHOTON_N_STATUS; ++k) c[k] = 0ull;
-  }
-  __device__ void add(int st) {
-#pragma unroll
-    for (int k = 0; k < PHOTON_N_STATUS; ++k) c[k] += (unsigned long long)__popcll(__ballot(st == k));
-  }
-};
+// Per-lane status counts of one work chunk, eight 8-bit fields in one
+// 64-bit register (a lane sees at most chunk / block <= 128 photons of a
+// chunk). At the chunk's end each wave adds them up, two fields per 32-bit
+// word in 16-bit halves (a wave's field sum stays below 2^14), and one lane
+// adds the sums to the block's LDS totals.
+__device__ __forceinline__ uint64_t status_inc(int st) {
+  return st >= 0 ? (1ull << (8 * st)) : 0ull;
+}
 
-__device__ void flush_wave_status(const WaveStatus& w, unsigned long long* totals) {
-  __shared__ unsigned long long s_tot[PHOTON_N_STATUS];
-  if (threadIdx.x < PHOTON_N_STATUS) s_tot[threadIdx.x] = 0;
-  __syncthreads();
-  if (__lane_id() == 0)
+__device__ __forceinline__ void flush_lane_status(uint64_t pk, unsigned long long* s_stat) {
+  const uint32_t lo = (uint32_t)pk, hi = (uint32_t)(pk >> 32);
+  uint32_t w[4] = {(lo & 0xffu) | ((lo & 0xff00u) << 8), ((lo >> 16) & 0xffu) | ((lo >> 8) & 0xff0000u),
+                   (hi & 0xffu) | ((hi & 0xff00u) << 8), ((hi >> 16) & 0xffu) | ((hi >> 8) & 0xff0000u)};
 #pragma unroll
-    for (int k = 0; k < PHOTON_N_STATUS; ++k)
-      if (w.c[k]) atomicAdd(&s_tot[k], w.c[k]);
-  __syncthreads();
-  if (threadIdx.x < PHOTON_N_STATUS && s_tot[threadIdx.x]) atomicAdd(&totals[threadIdx.x], s_tot[threadIdx.x]);
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = kWaveSize / 2; d > 0; d >>= 1) w[k] += __shfl_xor(w[k], d, kWaveSize);
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (w[k] & 0xffffu) atomicAdd(&s_stat[2 * k], (unsigned long long)(w[k] & 0xffffu));
+      if (w[k] >> 16) atomicAdd(&s_stat[2 * k + 1], (unsigned long long)(w[k] >> 16));
+    }
+  }
 }
 
 // Block-wide reduction of per-lane status counters into global totals.
@@ -789,8 +788,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   constexpr bool cher = CHER;
   const int64_t n_seg = A.n_seg;
   const uint64_t* __restrict__ offsets = A.offsets;
-  WaveStatus ws;
-  ws.clear();
+  __shared__ unsigned long long s_stat[PHOTON_N_STATUS];  // the block's status totals
+  if (tid < PHOTON_N_STATUS) s_stat[tid] = 0ull;
+  uint64_t pk = 0;  // this lane's status counts in the current chunk
   // Slots at or beyond offsets[n_seg] belong to no segment: counted INVALID.
   const uint64_t total = offsets[n_seg];
   const int64_t n_ph = A.n_ph < 0 ? (int64_t)total : A.n_ph;
@@ -804,7 +804,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
     const uint64_t c1 = min(c0 + (uint64_t)A.chunk, (uint64_t)n_ph);
     const uint64_t v1 = min(c1, lim);  // valid slots of this chunk: [c0, v1)
     const int wave = tid / kWaveSize;
-    if (wave == 0) ws.c[PHOTON_INVALID] += c1 - max(c0, v1);
+    if (tid == 0 && c1 > max(c0, v1)) atomicAdd(&s_stat[PHOTON_INVALID], (unsigned long long)(c1 - max(c0, v1)));
     if (c0 >= v1) {
       __syncthreads();
       continue;
@@ -923,9 +923,11 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
           st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
                                          stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
       }
-      ws.add(st_out);
-      if (kDefer) ws.c[PHOTON_HORIZON_FLOAT] += (unsigned long long)__popcll(__ballot(forced));
+      pk += status_inc(st_out);
+      if (kDefer && forced) pk += status_inc(PHOTON_HORIZON_FLOAT);
     }
+    flush_lane_status(pk, s_stat);
+    pk = 0;
     if constexpr (!SPLAT && !RADIAL) {
       if (stage_hits) flush_hits(s_hs.get(), A.sk.hits);
     }
@@ -954,7 +956,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
       }
     }
   }
-  if (A.sk.totals) flush_wave_status(ws, A.sk.totals);
+  // the block's status totals (the loop above ends with a barrier)
+  if (A.sk.totals && tid < PHOTON_N_STATUS && s_stat[tid]) atomicAdd(&A.sk.totals[tid], s_stat[tid]);
 }
 
 // Exclusive prefix sums of the per-block queue lengths (each clamped to the
