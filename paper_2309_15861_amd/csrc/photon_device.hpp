@@ -487,7 +487,7 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
   if (beam) {
     const T v = u1 * c.cos_c;
     const T ct = (T)1 - v;
-    const T st = sqrt(v * ((T)2 - v));
+    const T st = Fm<T>::sqrt_(v * ((T)2 - v));
     T sp, cp;
     sincos2pi(u2, &sp, &cp);
     const T px = st * cp, py = st * sp, pz = -ct;
@@ -511,7 +511,7 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
     const int32_t sw = (int32_t)(r.w[1] ^ 0x80000000u);
     const double ctd = -((double)sw + 0.5) * 0x1p-31;
     const T ct = (T)ctd;
-    const T st = (T)2 * sqrt(u01<T>(r.w[1]) * u01<T>(~r.w[1]));
+    const T st = (T)2 * Fm<T>::sqrt_(u01<T>(r.w[1]) * u01<T>(~r.w[1]));
     T sp, cp;
     sincos2pi(u2, &sp, &cp);
     p.ux = st * cp;
@@ -916,7 +916,7 @@ __device__ __forceinline__ int telescope_hit(const Photon<T>& p, const double (*
     const T cc = (ox * ox + oy * oy + oz * oz) - R * R;
     const T disc = b * b - cc;
     if (disc < (T)0) continue;
-    const T s = -b - sqrt(disc);
+    const T s = -b - Fm<T>::sqrt_(disc);
     if (s < best_s) {
       best_s = s;
       best = k;
@@ -941,7 +941,7 @@ __device__ __forceinline__ int telescope_hit_masked(const Photon<T>& p, const do
     const T cc = (ox * ox + oy * oy + oz * oz) - R * R;
     const T disc = b * b - cc;
     if (disc < (T)0) continue;
-    const T s = -b - sqrt(disc);
+    const T s = -b - Fm<T>::sqrt_(disc);
     if (s < best_s) {
       best_s = s;
       best = k;
