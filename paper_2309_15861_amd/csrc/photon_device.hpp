@@ -289,10 +289,21 @@ struct Fm<float> {
   // log1p(x) = log(u) x / (u - 1) with u = 1 + x rounded (exact u - 1);
   // log(u) = log2(u) ln 2 from the hardware log2 (u lies near 1 here: no
   // denormal or infinite argument to guard against)
+  // For |x| < 1/32 (every argument of the float path's layer integrals, whose
+  // rays lie more than about 6 degrees from the horizon) a degree-6 Taylor
+  // polynomial instead: truncation x^7/7, below 1e-10 relative.
   static __device__ __forceinline__ float log1p_(float x) {
+    if (fabsf(x) < 0.03125f) {
+      float p = -1.66666667e-01f;
+      p = __builtin_fmaf(p, x, 0.2f);
+      p = __builtin_fmaf(p, x, -0.25f);
+      p = __builtin_fmaf(p, x, 3.33333333e-01f);
+      p = __builtin_fmaf(p, x, -0.5f);
+      p = __builtin_fmaf(p, x, 1.0f);
+      return p * x;
+    }
     const float u = 1.0f + x;
-    return (u == 1.0f) ? x
-                       : (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
+    return (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
   }
   // expm1 for x <= 0: Taylor polynomial to x^8 for |x| < 0.5 (truncation
   // 1e-8 relative), else exp(x) - 1, where 1 - e^x > 0.39 keeps the
@@ -721,8 +732,9 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, in
   C r_top = ne * ce;  // r at ze: sqrt(ne^2 - S^2) = ne cos
   g0 = 0.0;
   col = (C)0;
-  pth = 0.0;
-  opt = 0.0;
+  // the small path and optical-path corrections of the pieces, summed in the
+  // working precision and added to the double totals once
+  C lg_sum = (C)0, rd_sum = (C)0;
   // the layer index runs wave-uniformly (lanes above their emission layer
   // skip the iteration); the piece constants come from the LDS record of
   // the layer (a kernel-argument array indexed under per-lane selects would
@@ -743,13 +755,14 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, in
     PieceOut<C> o;
     piece_integrals<C>(rho_a, em, (C)dh, (C)H_l, homog, eta0, C2, Cc, invC, S, ra, r_top, o);
     const double main = homog ? dh / (double)ra : (C2 > (C)0 ? dh * invCd : 0.0);
-    const double gp = main + (double)o.g0c;
-    g0 += gp;
-    pth += gp + (double)o.lgH;
-    opt += gp + (double)o.lgH + (double)o.rdH;
+    g0 += main + (double)o.g0c;
+    lg_sum += o.lgH;
+    rd_sum += o.rdH;
     col += o.col;
     r_top = ra;
   }
+  pth = g0 + (double)lg_sum;
+  opt = pth + (double)rd_sum;
 }
 
 // DEFER (float only): a near-horizon ray is only marked kDeferred.
