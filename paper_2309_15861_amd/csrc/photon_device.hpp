@@ -619,14 +619,17 @@ __device__ __forceinline__ void piece_integrals(T rho_a, T em, T dh, T H, bool h
 // pc[l]: the piece of layer l a downward ray crosses, with the observation
 // layer folded in: bottom (h_obs in the observation layer, else the layer
 // base), top (the next base, +inf for the top layer), rho/rho0 at the
-// bottom, expm1 of the density drop from bottom to top, scale height. A ray
-// loop reads it with its wave-uniform layer index (broadcast LDS reads:
-// neither scalar registers nor vector memory).
-enum { kPcBot = 0, kPcTop, kPcRho, kPcEm, kPcH, kPcWords = 6 };
+// bottom, expm1 of the density drop from bottom to top, scale height, and
+// the thickness top - bottom. A ray loop reads it with its wave-uniform layer
+// index (broadcast LDS reads: neither scalar registers nor vector memory).
+// pcf[l]: the float form's copy (thickness, rho, em, H), so that its loop
+// converts nothing.
+enum { kPcBot = 0, kPcTop, kPcRho, kPcEm, kPcH, kPcDh, kPcWords };
 struct AtmLane {
   double hb[PHOTON_MAX_LAYERS], rb[PHOTON_MAX_LAYERS], invH[PHOTON_MAX_LAYERS];
   double abs_l[PHOTON_MAX_ABS], abs_k[PHOTON_MAX_ABS], abs_s[PHOTON_MAX_ABS];
   double pc[PHOTON_MAX_LAYERS][kPcWords];
+  float4 pcf[PHOTON_MAX_LAYERS];
 };
 
 // Block-cooperative copy; the caller synchronises before use.
@@ -643,7 +646,8 @@ __device__ __forceinline__ void atm_lane_fill(const AtmDev& a, AtmLane* L) {
     L->pc[i][kPcRho] = obs ? a.rho_obs : a.rb[i];
     L->pc[i][kPcEm] = obs ? a.em_obs : a.em_full[i];
     L->pc[i][kPcH] = a.H[i];
-    L->pc[i][kPcH + 1] = 0.0;
+    L->pc[i][kPcDh] = L->pc[i][kPcTop] - L->pc[i][kPcBot];
+    L->pcf[i] = make_float4((float)L->pc[i][kPcDh], (float)L->pc[i][kPcRho], (float)L->pc[i][kPcEm], (float)a.H[i]);
   }
   for (int i = threadIdx.x; i < PHOTON_MAX_ABS; i += blockDim.x) {
     L->abs_l[i] = a.abs_l[i];
@@ -730,11 +734,16 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, in
   const double invCd = C2 > (C)0 ? (sizeof(C) == 8 ? (double)invC : rsqrt_refined(C2d)) : 0.0;
   const C ce = (C)ced;
   C r_top = ne * ce;  // r at ze: sqrt(ne^2 - S^2) = ne cos
-  g0 = 0.0;
+  // the dominant terms (b - a)/C of the pieces add up to (ze - h_obs)/C,
+  // taken once in double; a homogeneous layer's own term dh/r_a enters the
+  // sum below as its difference from dh/C
+  const bool cpos = C2 > (C)0;
+  g0 = cpos ? (ze - a.hobs) * invCd : 0.0;
   col = (C)0;
-  // the small path and optical-path corrections of the pieces, summed in the
-  // working precision and added to the double totals once
-  C lg_sum = (C)0, rd_sum = (C)0;
+  const C dh_e = (C)(ze - L.pc[le][kPcBot]);
+  // the piece remainders and the small path and optical-path corrections,
+  // summed in the working precision and added to the double totals once
+  C g_sum = (C)0, lg_sum = (C)0, rd_sum = (C)0;
   // the layer index runs wave-uniformly (lanes above their emission layer
   // skip the iteration); the piece constants come from the LDS record of
   // the layer (a kernel-argument array indexed under per-lane selects would
@@ -742,25 +751,38 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, in
 #pragma unroll 1
   for (int l = a.nl - 1; l >= a.l_obs; --l) {
     if (l > le) continue;
-    const double* pc = L.pc[l];
-    const double top = (l == le) ? ze : pc[kPcTop];
-    const double dh = top - pc[kPcBot];
-    if (!(dh > 0.0)) continue;
-    const C rho_a = (C)pc[kPcRho];
-    const C em = (l == le) ? em_e : (C)pc[kPcEm];
-    const double H_l = pc[kPcH];
+    C dh_full, rho_a, em_full, H_l;
+    if constexpr (sizeof(C) == 4) {
+      const float4 q = L.pcf[l];
+      dh_full = q.x;
+      rho_a = q.y;
+      em_full = q.z;
+      H_l = q.w;
+    } else {
+      const double* pc = L.pc[l];
+      dh_full = pc[kPcDh];
+      rho_a = pc[kPcRho];
+      em_full = pc[kPcEm];
+      H_l = pc[kPcH];
+    }
+    const C dh = (l == le) ? dh_e : dh_full;
+    if (!(dh > (C)0)) continue;
+    const C em = (l == le) ? em_e : em_full;
     const bool homog = (a.homog_mask >> l) & 1;
     const C eps_a = eta0 * rho_a;
     const C ra = F::sqrt_(C2 + eps_a * ((C)2 + eps_a));
     PieceOut<C> o;
-    piece_integrals<C>(rho_a, em, (C)dh, (C)H_l, homog, eta0, C2, Cc, invC, S, ra, r_top, o);
-    const double main = homog ? dh / (double)ra : (C2 > (C)0 ? dh * invCd : 0.0);
-    g0 += main + (double)o.g0c;
+    piece_integrals<C>(rho_a, em, dh, H_l, homog, eta0, C2, Cc, invC, S, ra, r_top, o);
+    // homogeneous: dh/r_a - dh/C = -dh (r_a^2 - C^2) / (r_a C (r_a + C))
+    const C gm = !homog ? (C)0
+                        : (cpos ? -dh * eps_a * ((C)2 + eps_a) * F::rcp(ra * Cc * (ra + Cc)) : dh * F::rcp(ra));
+    g_sum += gm + o.g0c;
     lg_sum += o.lgH;
     rd_sum += o.rdH;
     col += o.col;
     r_top = ra;
   }
+  g0 += (double)g_sum;
   pth = g0 + (double)lg_sum;
   opt = pth + (double)rd_sum;
 }
