@@ -90,7 +90,11 @@ struct SinkDev {
   int32_t n_tel;
   unsigned long long* totals;
   double tel[PHOTON_MAX_TELESCOPES][4];
-  double cand_x0, cand_y0, cand_inv_cell;
+  // h_obs (the float form's LDS table holds x, y, z - h_obs, R); the
+  // candidate grid's origin and cells per metre (float: the lists carry a
+  // 1 mm margin for the rounding)
+  double tel_hobs;
+  float cand_x0, cand_y0, cand_inv_cell;
   uint32_t cand_mask[kCandCells * kCandCells];
   photon_hits hits;
   double x_min, y_min, cell;
@@ -528,7 +532,8 @@ struct HitStageLds<true> {
 // splat grid, or the radial bins as count, weight, w t), or NULL to add to
 // the global arrays directly.
 template <typename T, bool SPLAT = false, bool RADIAL = false>
-__device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], double n_obs, Photon<T>& p,
+__device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], const float (*telf)[4],
+                                           double n_obs, Photon<T>& p,
                                            uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q,
                                            HitStage* stage, unsigned long long* lds_acc,
                                            const uint32_t* cand) {
@@ -581,15 +586,18 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
     T s_hit = (T)0;
     if (active && st == PHOTON_LANDED) {
       uint32_t mask;
-      if (-(double)p.uz >= kCapCos) {
-        const double fx = ((double)p.x - sk.cand_x0) * sk.cand_inv_cell;
-        const double fy = ((double)p.y - sk.cand_y0) * sk.cand_inv_cell;
-        const bool in = fx >= 0.0 && fy >= 0.0 && fx < (double)kCandCells && fy < (double)kCandCells;
+      if (-p.uz >= (T)kCapCos) {
+        const T fx = (p.x - (T)sk.cand_x0) * (T)sk.cand_inv_cell;
+        const T fy = (p.y - (T)sk.cand_y0) * (T)sk.cand_inv_cell;
+        const bool in = fx >= (T)0 && fy >= (T)0 && fx < (T)kCandCells && fy < (T)kCandCells;
         mask = in ? cand[(int)fy * kCandCells + (int)fx] : 0u;
       } else {
         mask = sk.n_tel >= 32 ? 0xffffffffu : ((1u << sk.n_tel) - 1u);
       }
-      k = telescope_hit_masked<T>(p, tel, mask, s_hit);
+      if constexpr (sizeof(T) == 4)
+        k = telescope_hit_masked_f(p, telf, (float)(p.z - sk.tel_hobs), mask, s_hit);
+      else
+        k = telescope_hit_masked<T>(p, tel, mask, s_hit);
     }
     const bool hit = k >= 0;
     const unsigned long long m = __ballot(hit);
@@ -652,11 +660,21 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
   return st;
 }
 
+// Word k of the float telescope table (x, y, z - h_obs, R).
+__device__ __forceinline__ float tel_float(const SinkDev& sk, int k) {
+  const double v = (&sk.tel[0][0])[k];
+  return (float)((k & 3) == 2 ? v - sk.tel_hobs : v);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, SinkDev sk, double n_obs) {
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  __shared__ __align__(16) float s_telf[PHOTON_MAX_TELESCOPES][4];
   __shared__ uint32_t s_cand[kCandCells * kCandCells];
-  if (threadIdx.x < PHOTON_MAX_TELESCOPES * 4) (&s_tel[0][0])[threadIdx.x] = (&sk.tel[0][0])[threadIdx.x];
+  if (threadIdx.x < PHOTON_MAX_TELESCOPES * 4) {
+    (&s_tel[0][0])[threadIdx.x] = (&sk.tel[0][0])[threadIdx.x];
+    (&s_telf[0][0])[threadIdx.x] = tel_float(sk, threadIdx.x);
+  }
   if (threadIdx.x < kCandCells * kCandCells) s_cand[threadIdx.x] = sk.cand_mask[threadIdx.x];
   __syncthreads();
   StatusCounter sc;
@@ -680,9 +698,10 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
     j = b.j[q];
   }
   const int st = sk.kind == PHOTON_SINK_RADIAL
-                     ? sink_photon<T, false, true>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr,
-                                                   s_cand)
-                     : sink_photon<T>(sk, s_tel, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr, s_cand);
+                     ? sink_photon<T, false, true>(sk, s_tel, s_telf, n_obs, p, s, j, active, (uint64_t)q, nullptr,
+                                                   nullptr, s_cand)
+                     : sink_photon<T>(sk, s_tel, s_telf, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr,
+                                      s_cand);
   if (active) sc.add(st);
   if (sk.totals) flush_status(sc, sk.totals);
 }
@@ -747,6 +766,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ T s_lines[PHOTON_MAX_LINES];
   __shared__ double s_tel[kTel][4];
+  __shared__ __align__(16) float s_telf[kTel][4];
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ unsigned int s_dcount;
@@ -781,7 +801,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   }
   if constexpr (!SPLAT && !RADIAL) {
     static_assert(kTel == PHOTON_MAX_TELESCOPES && kCand == kCandCells * kCandCells, "full telescope tables");
-    for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+    for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) {
+      (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+      (&s_telf[0][0])[k] = tel_float(A.sk, k);
+    }
     for (int k = tid; k < kCandCells * kCandCells; k += BS) s_cand[k] = A.sk.cand_mask[k];
   }
   atm_lane_fill(A.atm, &s_lane);
@@ -895,7 +918,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
         const uint32_t j = (uint32_t)(q - off_s);
         Photon<T> p;
         generate_kind<T, CHER>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
-        propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p);
+        propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p, c.layer);
         if constexpr (SPLAT) p.w *= wsc;
         if (kDefer) {
           const bool defer = p.status == kDeferred;
@@ -913,14 +936,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
               } else {
                 // queue full: this ray is evaluated in float after all
                 p.status = PHOTON_LANDED;
-                propagate<T, false, true>(A.atm, s_lane, p);
+                propagate<T, false, true>(A.atm, s_lane, p, c.layer);
                 forced = true;
               }
             }
           }
         }
         if (!kDefer || p.status != kDeferred)
-          st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, A.atm.n_obs, p, (uint32_t)s, j, true, q,
+          st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, A.atm.n_obs, p, (uint32_t)s, j, true, q,
                                          stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
       }
       pk += status_inc(st_out);
@@ -1007,6 +1030,7 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ double s_lines[PHOTON_MAX_LINES];
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
+  __shared__ __align__(16) float s_telf[PHOTON_MAX_TELESCOPES][4];
   __shared__ AtmLane s_lane;
   __shared__ uint32_t s_cand[kCandCells * kCandCells];
   const int tid = threadIdx.x;
@@ -1014,7 +1038,10 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = A.g.line_nm[tid];
   }
-  for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+  for (int k = tid; k < PHOTON_MAX_TELESCOPES * 4; k += BS) {
+    (&s_tel[0][0])[k] = (&A.sk.tel[0][0])[k];
+    (&s_telf[0][0])[k] = tel_float(A.sk, k);
+  }
   for (int k = tid; k < kCandCells * kCandCells; k += BS) s_cand[k] = A.sk.cand_mask[k];
   atm_lane_fill(A.atm, &s_lane);
   __syncthreads();
@@ -1054,14 +1081,14 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     pf.status = p.status;
     int st;
     if (splat)
-      st = sink_photon<float, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr, nullptr,
-                                    s_cand);
+      st = sink_photon<float, true>(A.sk, s_tel, s_telf, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr,
+                                    nullptr, s_cand);
     else if (A.sk.kind == PHOTON_SINK_RADIAL)
-      st = sink_photon<float, false, true>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr,
-                                           nullptr, s_cand);
+      st = sink_photon<float, false, true>(A.sk, s_tel, s_telf, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0,
+                                           nullptr, nullptr, s_cand);
     else
-      st = sink_photon<float>(A.sk, s_tel, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y, nullptr,
-                              nullptr, s_cand);
+      st = sink_photon<float>(A.sk, s_tel, s_telf, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y,
+                              nullptr, nullptr, s_cand);
     sc.add(st);
   }
   if (A.sk.totals) flush_status(sc, A.sk.totals);
@@ -1495,8 +1522,14 @@ int prep_atm(const photon_atmosphere* a, AtmDev* d) {
     for (int i = 0; i + 1 < a->n_abs && uni; ++i)
       uni = std::fabs((a->abs_lambda_nm[i + 1] - a->abs_lambda_nm[i]) - step) <= 1e-9 * step;
     d->abs_uniform = uni ? 1 : 0;
-    d->abs_l0 = a->abs_lambda_nm[0];
-    d->abs_inv_step = uni ? 1.0 / step : 0.0;
+    d->absf_l0 = (float)a->abs_lambda_nm[0];
+    d->absf_inv_step = (float)(uni ? 1.0 / step : 0.0);
+  }
+  if (a->n_abs >= 1) {
+    d->absf_l_lo = (float)d->abs_l[0];
+    d->absf_k_lo = (float)d->abs_k[0];
+    d->absf_l_hi = (float)d->abs_l[a->n_abs - 1];
+    d->absf_k_hi = (float)d->abs_k[a->n_abs - 1];
   }
   if (a->table) {
     const photon_table* t = a->table;
@@ -1646,9 +1679,10 @@ void build_candidates(const photon_sink* s, double hobs, SinkDev* d) {
     y1 = std::max(y1, s->tel[k][1] + reach[k]);
   }
   const double cell = std::max(x1 - x0, y1 - y0) / kCandCells * (1.0 + 1e-9) + 1e-9;
-  d->cand_x0 = x0;
-  d->cand_y0 = y0;
-  d->cand_inv_cell = 1.0 / cell;
+  d->cand_x0 = (float)x0;
+  d->cand_y0 = (float)y0;
+  d->cand_inv_cell = (float)(1.0 / cell);
+  d->tel_hobs = hobs;
   for (int iy = 0; iy < kCandCells; ++iy)
     for (int ix = 0; ix < kCandCells; ++ix) {
       uint32_t m = 0;
@@ -1657,7 +1691,9 @@ void build_candidates(const photon_sink* s, double hobs, SinkDev* d) {
         // distance from the sphere centre to the cell square, with a margin
         const double dx = std::max(0.0, std::max(cx0 - s->tel[k][0], s->tel[k][0] - (cx0 + cell)));
         const double dy = std::max(0.0, std::max(cy0 - s->tel[k][1], s->tel[k][1] - (cy0 + cell)));
-        if (dx * dx + dy * dy <= reach[k] * reach[k] * (1.0 + 1e-6) + 1e-6) m |= 1u << k;
+        // (1 mm more: the float form finds its cell to float rounding)
+        const double rm = reach[k] * (1.0 + 1e-6) + 1e-3;
+        if (dx * dx + dy * dy <= rm * rm) m |= 1u << k;
       }
       d->cand_mask[iy * kCandCells + ix] = m;
     }

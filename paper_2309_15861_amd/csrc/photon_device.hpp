@@ -85,9 +85,12 @@ struct AtmDev {
   double em_full[PHOTON_MAX_LAYERS];  // expm1(-(hb[l+1] - hb[l]) / H[l]): density ratio - 1 across layer l
   double em_obs;                      // expm1(-(top of the observation layer - hobs) / H[l_obs])
   int32_t abs_uniform;                // absorption nodes equally spaced
-  double abs_l0, abs_inv_step;
   double abs_l[PHOTON_MAX_ABS];
   double abs_k[PHOTON_MAX_ABS];
+  // first node and nodes per nm (uniform nodes: the first guess of the node
+  // index in either precision, corrected by one comparison each way)
+  float absf_l0, absf_inv_step;
+  float absf_l_lo, absf_l_hi, absf_k_lo, absf_k_hi;  // first and last nodes in float
   // straight-line propagation with correction tables (tcorr = NULL: exact)
   const float4* tcorr;                // (g, dP, dX, 0) per node, q fastest
   const float2* tvert;                // (rho/rho0, vertical column) per height node
@@ -345,6 +348,7 @@ struct SegConst : SegHi<T> {
   T cos_c, sin_c;                  // Cherenkov cone (section 1.2); beamed fluorescence: cos_c = om
   T ax, ay, az;                    // unit bisector of the cone axis and (0,0,-1)
   uint32_t idx, shower;
+  int32_t layer;                   // the layer holding the whole segment (1 mm margin), else -1
 };
 
 // Unit bisector A of a cone axis d and the downward normal: M_Rod
@@ -387,6 +391,13 @@ __device__ __forceinline__ void seg_const(const SegView& s, int64_t i, const Atm
   c.len = (T)s.len[i];
   c.idx = seg_idx(s, i);
   c.shower = seg_shower(s, i);
+  {
+    // emission heights z0 + s dz, s in [0, len], rounded in either precision
+    const double z1 = c.z0 + s.len[i] * uz;
+    const double m = 1e-3 + 1e-6 * s.len[i];
+    const int l0 = layer_of(a, fmin(c.z0, z1) - m), l1 = layer_of(a, fmax(c.z0, z1) + m);
+    c.layer = l0 == l1 ? l0 : -1;
+  }
   if (cherenkov) {
     const double n = seg_index(s, i, a);
     const double cc = 1.0 / (s.beta[i] * n);
@@ -630,6 +641,7 @@ struct AtmLane {
   double abs_l[PHOTON_MAX_ABS], abs_k[PHOTON_MAX_ABS], abs_s[PHOTON_MAX_ABS];
   double pc[PHOTON_MAX_LAYERS][kPcWords];
   float4 pcf[PHOTON_MAX_LAYERS];
+  float abs_lf[PHOTON_MAX_ABS], abs_kf[PHOTON_MAX_ABS], abs_sf[PHOTON_MAX_ABS];
 };
 
 // Block-cooperative copy; the caller synchronises before use.
@@ -653,20 +665,23 @@ __device__ __forceinline__ void atm_lane_fill(const AtmDev& a, AtmLane* L) {
     L->abs_l[i] = a.abs_l[i];
     L->abs_k[i] = a.abs_k[i];
     L->abs_s[i] = (i + 1 < a.n_abs) ? (a.abs_k[i + 1] - a.abs_k[i]) / (a.abs_l[i + 1] - a.abs_l[i]) : 0.0;
+    L->abs_lf[i] = (float)a.abs_l[i];
+    L->abs_kf[i] = (float)a.abs_k[i];
+    L->abs_sf[i] = (float)L->abs_s[i];
   }
 }
 
 // Absorption coefficient at rho/rho0 = 1: piecewise linear in lambda,
 // clamped to the end values outside the table.
 template <typename T>
-__device__ __forceinline__ T abs_coeff(const AtmDev& a, const AtmLane& L, T lambda) {
+__device__ __forceinline__ T abs_coeff_double(const AtmDev& a, const AtmLane& L, T lambda) {
   if (a.n_abs <= 0) return (T)0;
   const double l = (double)lambda;
   if (l <= a.abs_l[0]) return (T)a.abs_k[0];
   if (l >= a.abs_l[a.n_abs - 1]) return (T)a.abs_k[a.n_abs - 1];
   int lo;
   if (a.abs_uniform) {
-    lo = (int)((l - a.abs_l0) * a.abs_inv_step);
+    lo = (int)((l - (double)a.absf_l0) * (double)a.absf_inv_step);
     lo = lo < 0 ? 0 : (lo > a.n_abs - 2 ? a.n_abs - 2 : lo);
     // guard against the last bit of the index computation
     if (l < L.abs_l[lo]) --lo;
@@ -680,6 +695,36 @@ __device__ __forceinline__ T abs_coeff(const AtmDev& a, const AtmLane& L, T lamb
     }
   }
   return (T)(L.abs_k[lo] + (l - L.abs_l[lo]) * L.abs_s[lo]);
+}
+
+// The float form: the same interpolation on float copies of the nodes (the
+// function is continuous, so a node decided differently by rounding moves
+// the value by rounding only).
+__device__ __forceinline__ float abs_coeff_float(const AtmDev& a, const AtmLane& L, float l) {
+  if (a.n_abs <= 0) return 0.0f;
+  if (l <= a.absf_l_lo) return a.absf_k_lo;
+  if (l >= a.absf_l_hi) return a.absf_k_hi;
+  int lo;
+  if (a.abs_uniform) {
+    lo = (int)((l - a.absf_l0) * a.absf_inv_step);
+    lo = lo < 0 ? 0 : (lo > a.n_abs - 2 ? a.n_abs - 2 : lo);
+    if (l < L.abs_lf[lo]) --lo;
+    else if (!(l < L.abs_lf[lo + 1])) ++lo;
+  } else {
+    lo = 0;
+    int hi = a.n_abs - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (L.abs_lf[mid] <= l) lo = mid; else hi = mid;
+    }
+  }
+  return L.abs_kf[lo] + (l - L.abs_lf[lo]) * L.abs_sf[lo];
+}
+
+template <typename T>
+__device__ __forceinline__ T abs_coeff(const AtmDev& a, const AtmLane& L, T lambda) {
+  if constexpr (sizeof(T) == 4) return abs_coeff_float(a, L, lambda);
+  else return abs_coeff_double<T>(a, L, lambda);
 }
 
 // Double square root and reciprocal square root for the float path: the
@@ -709,22 +754,21 @@ constexpr int kDeferred = 7;
 // rho_e = rho_bot (1 + em_e) is the density at ze, se/ce the sine/cosine of
 // the zenith angle at emission. Accumulates in double int dh/r (g0), the path
 // and the optical path, and in C the density-weighted path (col).
-// ced/sed: cosine and sine of the emission zenith angle in double; the float
-// form takes C^2 and the dominant 1/C from them.
+// ced: cosine of the emission zenith angle in double, se its sine; the float
+// form takes C^2 and the dominant 1/C from ced.
 template <typename C>
 __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, int le, double ze, C em_e, C rho_e,
-                                           double sed, double ced, double& g0, double& pth, double& opt, C& col,
-                                           C& ne) {
+                                           C se, double ced, double& g0, double& pth, double& opt, C& col, C& ne) {
   using F = Fm<C>;
   const C eta0 = (C)a.eta0;
   const C eps_e = eta0 * rho_e;
   ne = (C)1 + eps_e;
-  const C se = (C)sed;
   const C S = ne * se;
   // C^2 = 1 - S^2. Double form: 1 - S = ce^2/(1 + se) - eps_e se, free of
   // cancellation up to the horizon. Float form (rays with C^2 > 0.01 only):
   // ce^2 - eps_e (2 + eps_e) se^2, whose terms differ by a factor of 16 or more.
   const double epsd = (double)eps_e;
+  const double sed = (double)se;  // used by the double form only
   const double C2d = sizeof(C) == 8 ? (ced * ced / (1.0 + sed) - epsd * sed) * (1.0 + (1.0 + epsd) * sed)
                                     : ced * ced - epsd * (2.0 + epsd) * ((1.0 - ced) * (1.0 + ced));
   const C C2 = (C)C2d;
@@ -859,8 +903,9 @@ __device__ __forceinline__ bool propagate_table(const AtmDev& a, const AtmLane& 
 }
 
 // TABLE: try the straight line with corrections first (a.tcorr set).
+// layer_hint: the emission layer when the caller knows it (>= 0), else -1.
 template <typename T, bool DEFER = false, bool FORCE_FLOAT = false, bool TABLE = false>
-__device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Photon<T>& p) {
+__device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Photon<T>& p, int layer_hint = -1) {
   using F = Fm<T>;
   if (p.status != PHOTON_LANDED) return;
   if (!(p.uz < (T)0)) {
@@ -878,12 +923,26 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
   // float form's directions are unit to rounding; rescaling the exact
   // component by a float norm would only add error)
   const double ced = sizeof(T) == 8 ? -p.uzd * (double)inv_un : -p.uzd;
-  const double sed = sizeof(T) == 8 ? sqrt((1.0 - ced) * (1.0 + ced)) : sqrt_refined((1.0 - ced) * (1.0 + ced));
-  const T ce = (T)ced, se = (T)sed;
+  const double omc = (1.0 - ced) * (1.0 + ced);
+  // the sine in double only where a double pass in place needs it (the
+  // float form enters it in float terms only)
+  double sed = 0.0;
+  T se;
+  if constexpr (sizeof(T) == 8) {
+    sed = sqrt(omc);
+    se = sed;
+  } else if constexpr (DEFER) {
+    se = F::sqrt_((T)omc);
+  } else {
+    sed = sqrt_refined(omc);
+    se = (T)sed;
+  }
+  const T ce = (T)ced;
   if constexpr (TABLE) {
     if (propagate_table<T>(a, L, ux, uy, ce, se, p)) return;
   }
-  const int le = layer_of(a, ze);
+  int le = layer_hint;
+  if (le < 0) le = layer_of(a, ze);
   // the emission layer's piece record (LDS): a select between a kernel
   // argument and an LDS array would become a generic (flat) load
   const double bot = L.pc[le][kPcBot];
@@ -902,7 +961,7 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
     const T S = ((T)1 + eps_e) * se;
     const T C2 = (ce * ce * F::rcp((T)1 + se) - eps_e * se) * ((T)1 + S);
     if (FORCE_FLOAT || C2 > (T)kNearHorizonC2) {
-      ray_pieces<T>(a, L, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
+      ray_pieces<T>(a, L, le, ze, em_e, rho_e, se, ced, g0, pth, opt, col, ne);
       em_out = em_e;
       done = true;
     } else if (DEFER) {
@@ -917,9 +976,16 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
     ne = (T)ned;
     em_out = (T)emd;
   }
-  const double disp = (double)ne * g0;
-  p.x = (T)((double)p.x + (double)ux * disp);
-  p.y = (T)((double)p.y + (double)uy * disp);
+  if constexpr (sizeof(T) == 4) {
+    // the horizontal displacement to float rounding (the landing point is float)
+    const T disp = ne * (T)g0;
+    p.x = p.x + ux * disp;
+    p.y = p.y + uy * disp;
+  } else {
+    const double disp = (double)ne * g0;
+    p.x = p.x + ux * disp;
+    p.y = p.y + uy * disp;
+  }
   p.z = a.hobs;
   p.t = p.t + opt * (1.0 / kC);
   p.path = pth;
@@ -977,6 +1043,31 @@ __device__ __forceinline__ int telescope_hit_masked(const Photon<T>& p, const do
     const T disc = b * b - cc;
     if (disc < (T)0) continue;
     const T s = -b - Fm<T>::sqrt_(disc);
+    if (s < best_s) {
+      best_s = s;
+      best = k;
+    }
+  }
+  s_hit = best_s;
+  return best;
+}
+
+// The float form on float centres (x, y, z - h_obs, R); pz_rel = z - h_obs
+// of the photon.
+__device__ __forceinline__ int telescope_hit_masked_f(const Photon<float>& p, const float (*tel)[4], float pz_rel,
+                                                      uint32_t mask, float& s_hit) {
+  int best = -1;
+  float best_s = INFINITY;
+  while (mask) {
+    const int k = __builtin_ctz(mask);
+    mask &= mask - 1u;
+    const float4 c = *reinterpret_cast<const float4*>(tel[k]);
+    const float ox = p.x - c.x, oy = p.y - c.y, oz = pz_rel - c.z;
+    const float b = p.ux * ox + p.uy * oy + p.uz * oz;
+    const float cc = (ox * ox + oy * oy + oz * oz) - c.w * c.w;
+    const float disc = b * b - cc;
+    if (disc < 0.0f) continue;
+    const float s = -b - __builtin_amdgcn_sqrtf(disc);
     if (s < best_s) {
       best_s = s;
       best = k;
