@@ -533,7 +533,7 @@ struct HitStageLds<true> {
 // the global arrays directly.
 template <typename T, bool SPLAT = false, bool RADIAL = false>
 __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], const float (*telf)[4],
-                                           double n_obs, Photon<T>& p,
+                                           double n_over_c, Photon<T>& p,
                                            uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q,
                                            HitStage* stage, unsigned long long* lds_acc,
                                            const uint32_t* cand) {
@@ -607,10 +607,18 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
         r.seg = seg_row;
         r.j = j;
         r.tel = k;
-        r.x = (double)p.x + (double)s_hit * (double)p.ux;
-        r.y = (double)p.y + (double)s_hit * (double)p.uy;
-        r.z = p.z + (double)s_hit * (double)p.uz;
-        r.t = p.t + n_obs * (double)s_hit / kC;
+        if constexpr (sizeof(T) == 4) {
+          // the point on the sphere to float rounding (a few metres from the landing point)
+          r.x = (double)(p.x + s_hit * p.ux);
+          r.y = (double)(p.y + s_hit * p.uy);
+          r.z = p.z + (double)(s_hit * p.uz);
+          r.t = p.t + (double)(s_hit * (float)n_over_c);
+        } else {
+          r.x = p.x + s_hit * p.ux;
+          r.y = p.y + s_hit * p.uy;
+          r.z = p.z + s_hit * p.uz;
+          r.t = p.t + n_over_c * s_hit;
+        }
         r.ux = (float)p.ux;
         r.uy = (float)p.uy;
         r.uz = (float)p.uz;
@@ -668,6 +676,7 @@ __device__ __forceinline__ float tel_float(const SinkDev& sk, int k) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, SinkDev sk, double n_obs) {
+  const double n_over_c = n_obs * (1.0 / kC);  // ns per metre at the observation level
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];
   __shared__ __align__(16) float s_telf[PHOTON_MAX_TELESCOPES][4];
   __shared__ uint32_t s_cand[kCandCells * kCandCells];
@@ -698,9 +707,9 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
     j = b.j[q];
   }
   const int st = sk.kind == PHOTON_SINK_RADIAL
-                     ? sink_photon<T, false, true>(sk, s_tel, s_telf, n_obs, p, s, j, active, (uint64_t)q, nullptr,
+                     ? sink_photon<T, false, true>(sk, s_tel, s_telf, n_over_c, p, s, j, active, (uint64_t)q, nullptr,
                                                    nullptr, s_cand)
-                     : sink_photon<T>(sk, s_tel, s_telf, n_obs, p, s, j, active, (uint64_t)q, nullptr, nullptr,
+                     : sink_photon<T>(sk, s_tel, s_telf, n_over_c, p, s, j, active, (uint64_t)q, nullptr, nullptr,
                                       s_cand);
   if (active) sc.add(st);
   if (sk.totals) flush_status(sc, sk.totals);
@@ -818,6 +827,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   const uint64_t total = offsets[n_seg];
   const int64_t n_ph = A.n_ph < 0 ? (int64_t)total : A.n_ph;
   const uint64_t lim = min((uint64_t)n_ph, total);
+  const double n_over_c = A.atm.n_obs * (1.0 / kC);  // ns per metre at the observation level
 
   for (;;) {
     if (tid == 0) s_c0 = atomicAdd(A.cursor, (unsigned long long)A.chunk);
@@ -943,7 +953,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
           }
         }
         if (!kDefer || p.status != kDeferred)
-          st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, A.atm.n_obs, p, (uint32_t)s, j, true, q,
+          st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, q,
                                          stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
       }
       pk += status_inc(st_out);
@@ -1046,6 +1056,7 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
   atm_lane_fill(A.atm, &s_lane);
   __syncthreads();
   const bool cher = A.g.kind == PHOTON_CHERENKOV;
+  const double n_over_c = A.atm.n_obs * (1.0 / kC);
   StatusCounter sc;
   sc.clear();
   const unsigned long long* __restrict__ pref = A.defer_pref;
@@ -1081,13 +1092,13 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
     pf.status = p.status;
     int st;
     if (splat)
-      st = sink_photon<float, true>(A.sk, s_tel, s_telf, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0, nullptr,
+      st = sink_photon<float, true>(A.sk, s_tel, s_telf, n_over_c, pf, (uint32_t)s, e.y, true, 0, nullptr,
                                     nullptr, s_cand);
     else if (A.sk.kind == PHOTON_SINK_RADIAL)
-      st = sink_photon<float, false, true>(A.sk, s_tel, s_telf, A.atm.n_obs, pf, (uint32_t)s, e.y, true, 0,
+      st = sink_photon<float, false, true>(A.sk, s_tel, s_telf, n_over_c, pf, (uint32_t)s, e.y, true, 0,
                                            nullptr, nullptr, s_cand);
     else
-      st = sink_photon<float>(A.sk, s_tel, s_telf, A.atm.n_obs, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y,
+      st = sink_photon<float>(A.sk, s_tel, s_telf, n_over_c, pf, (uint32_t)s, e.y, true, A.offsets[s] + e.y,
                               nullptr, nullptr, s_cand);
     sc.add(st);
   }

@@ -750,27 +750,35 @@ constexpr float kNearHorizonC2 = 0.01f;
 // Internal status of a photon left to the double pass (never reported).
 constexpr int kDeferred = 7;
 
+// C^2 = 1 - S^2 of a ray with zenith cosine ced and sine se where
+// eps = n - 1 is epsd, in double. Double form: 1 - S = ce^2/(1 + se) - eps se,
+// free of cancellation up to the horizon. Float form (taken to decide the
+// float rays, C^2 > 0.01): ce^2 - eps (2 + eps)(1 - ce)(1 + ce), whose terms
+// differ by a factor of 16 or more there.
+template <typename C>
+__device__ __forceinline__ double ray_c2(double ced, C se, double epsd) {
+  if constexpr (sizeof(C) == 8) {
+    return (ced * ced / (1.0 + se) - epsd * se) * (1.0 + (1.0 + epsd) * se);
+  } else {
+    return ced * ced - epsd * (2.0 + epsd) * ((1.0 - ced) * (1.0 + ced));
+  }
+}
+
 // Layer pieces from the emission height ze down to h_obs in precision C.
 // rho_e = rho_bot (1 + em_e) is the density at ze, se/ce the sine/cosine of
 // the zenith angle at emission. Accumulates in double int dh/r (g0), the path
 // and the optical path, and in C the density-weighted path (col).
 // ced: cosine of the emission zenith angle in double, se its sine; the float
-// form takes C^2 and the dominant 1/C from ced.
+// form takes the dominant 1/C from C2d, C^2 in double (ray_c2).
 template <typename C>
 __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, int le, double ze, C em_e, C rho_e,
-                                           C se, double ced, double& g0, double& pth, double& opt, C& col, C& ne) {
+                                           C se, double ced, double C2d, double& g0, double& pth, double& opt,
+                                           C& col, C& ne) {
   using F = Fm<C>;
   const C eta0 = (C)a.eta0;
   const C eps_e = eta0 * rho_e;
   ne = (C)1 + eps_e;
   const C S = ne * se;
-  // C^2 = 1 - S^2. Double form: 1 - S = ce^2/(1 + se) - eps_e se, free of
-  // cancellation up to the horizon. Float form (rays with C^2 > 0.01 only):
-  // ce^2 - eps_e (2 + eps_e) se^2, whose terms differ by a factor of 16 or more.
-  const double epsd = (double)eps_e;
-  const double sed = (double)se;  // used by the double form only
-  const double C2d = sizeof(C) == 8 ? (ced * ced / (1.0 + sed) - epsd * sed) * (1.0 + (1.0 + epsd) * sed)
-                                    : ced * ced - epsd * (2.0 + epsd) * ((1.0 - ced) * (1.0 + ced));
   const C C2 = (C)C2d;
   const C Cc = C2 > (C)0 ? F::sqrt_(C2) : (C)0;
   const C invC = C2 > (C)0 ? F::rcp(Cc) : (C)0;
@@ -847,7 +855,8 @@ __device__ __forceinline__ void exact_ray_double(const AtmDev& a, const AtmLane&
   const bool homog_e = (a.homog_mask >> le) & 1;
   const double em_e = homog_e ? 0.0 : expm1(-(ze - bot) * L.invH[le]);
   const double rho_e = rho_bot * (1.0 + em_e);
-  ray_pieces<double>(a, L, le, ze, em_e, rho_e, sed, ced, g0, pth, opt, col, ne);
+  const double C2d = ray_c2<double>(ced, sed, a.eta0 * rho_e);
+  ray_pieces<double>(a, L, le, ze, em_e, rho_e, sed, ced, C2d, g0, pth, opt, col, ne);
   em_out = em_e;
   rho_bot_out = rho_bot;
 }
@@ -958,10 +967,9 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
     const T em_e = homog_e ? (T)0 : F::expm1_((T)(-(ze - bot) * invH_e));
     const T rho_e = (T)rho_bot * ((T)1 + em_e);
     const T eps_e = (T)a.eta0 * rho_e;
-    const T S = ((T)1 + eps_e) * se;
-    const T C2 = (ce * ce * F::rcp((T)1 + se) - eps_e * se) * ((T)1 + S);
-    if (FORCE_FLOAT || C2 > (T)kNearHorizonC2) {
-      ray_pieces<T>(a, L, le, ze, em_e, rho_e, se, ced, g0, pth, opt, col, ne);
+    const double C2d = ray_c2<T>(ced, se, (double)eps_e);
+    if (FORCE_FLOAT || C2d > (double)kNearHorizonC2) {
+      ray_pieces<T>(a, L, le, ze, em_e, rho_e, se, ced, C2d, g0, pth, opt, col, ne);
       em_out = em_e;
       done = true;
     } else if (DEFER) {
