@@ -634,13 +634,15 @@ __device__ __forceinline__ void piece_integrals(T rho_a, T em, T dh, T H, bool h
 // the thickness top - bottom. A ray loop reads it with its wave-uniform layer
 // index (broadcast LDS reads: neither scalar registers nor vector memory).
 // pcf[l]: the float form's copy (thickness, rho, em, H), so that its loop
-// converts nothing.
+// converts nothing. pfg[l], pfh[l]: what a whole layer's piece needs that
+// does not depend on the ray, for the float form (below).
 enum { kPcBot = 0, kPcTop, kPcRho, kPcEm, kPcH, kPcDh, kPcWords };
 struct AtmLane {
   double hb[PHOTON_MAX_LAYERS], rb[PHOTON_MAX_LAYERS], invH[PHOTON_MAX_LAYERS];
   double abs_l[PHOTON_MAX_ABS], abs_k[PHOTON_MAX_ABS], abs_s[PHOTON_MAX_ABS];
   double pc[PHOTON_MAX_LAYERS][kPcWords];
   float4 pcf[PHOTON_MAX_LAYERS];
+  float4 pfg[PHOTON_MAX_LAYERS], pfh[PHOTON_MAX_LAYERS];
   float abs_lf[PHOTON_MAX_ABS], abs_kf[PHOTON_MAX_ABS], abs_sf[PHOTON_MAX_ABS];
 };
 
@@ -660,6 +662,16 @@ __device__ __forceinline__ void atm_lane_fill(const AtmDev& a, AtmLane* L) {
     L->pc[i][kPcH] = a.H[i];
     L->pc[i][kPcDh] = L->pc[i][kPcTop] - L->pc[i][kPcBot];
     L->pcf[i] = make_float4((float)L->pc[i][kPcDh], (float)L->pc[i][kPcRho], (float)L->pc[i][kPcEm], (float)a.H[i]);
+    // eps_a, eps_a (2 + eps_a), d = eps_b - eps_a, d (2 + eps_a + eps_b);
+    // n_b, -H drho (2 + eps_a + eps_b), H
+    const double eps_a = a.eta0 * L->pc[i][kPcRho];
+    const double d = eps_a * L->pc[i][kPcEm];
+    const double two_e = 2.0 + eps_a + (eps_a + d);
+    const bool homog = (a.homog_mask >> i) & 1;
+    L->pfg[i] = make_float4((float)eps_a, (float)(eps_a * (2.0 + eps_a)), (float)d, (float)(d * two_e));
+    L->pfh[i] = make_float4((float)(1.0 + eps_a + d),
+                            homog ? 0.0f : (float)(-a.H[i] * L->pc[i][kPcRho] * L->pc[i][kPcEm] * two_e),
+                            (float)a.H[i], 0.0f);
   }
   for (int i = threadIdx.x; i < PHOTON_MAX_ABS; i += blockDim.x) {
     L->abs_l[i] = a.abs_l[i];
@@ -796,31 +808,9 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, in
   // the piece remainders and the small path and optical-path corrections,
   // summed in the working precision and added to the double totals once
   C g_sum = (C)0, lg_sum = (C)0, rd_sum = (C)0;
-  // the layer index runs wave-uniformly (lanes above their emission layer
-  // skip the iteration); the piece constants come from the LDS record of
-  // the layer (a kernel-argument array indexed under per-lane selects would
-  // be read by vector loads with their full latency)
-#pragma unroll 1
-  for (int l = a.nl - 1; l >= a.l_obs; --l) {
-    if (l > le) continue;
-    C dh_full, rho_a, em_full, H_l;
-    if constexpr (sizeof(C) == 4) {
-      const float4 q = L.pcf[l];
-      dh_full = q.x;
-      rho_a = q.y;
-      em_full = q.z;
-      H_l = q.w;
-    } else {
-      const double* pc = L.pc[l];
-      dh_full = pc[kPcDh];
-      rho_a = pc[kPcRho];
-      em_full = pc[kPcEm];
-      H_l = pc[kPcH];
-    }
-    const C dh = (l == le) ? dh_e : dh_full;
-    if (!(dh > (C)0)) continue;
-    const C em = (l == le) ? em_e : em_full;
-    const bool homog = (a.homog_mask >> l) & 1;
+  // one piece: its remainder of int dh/r, the path and optical-path
+  // corrections and the column go to the sums
+  auto add_piece = [&](C dh, C rho_a, C em, C H_l, bool homog) {
     const C eps_a = eta0 * rho_a;
     const C ra = F::sqrt_(C2 + eps_a * ((C)2 + eps_a));
     PieceOut<C> o;
@@ -833,6 +823,52 @@ __device__ __forceinline__ void ray_pieces(const AtmDev& a, const AtmLane& L, in
     rd_sum += o.rdH;
     col += o.col;
     r_top = ra;
+  };
+  if constexpr (sizeof(C) == 4) {
+    // the emission layer's piece per lane, then the whole layers below it
+    // with the wave-uniform layer index (lanes at or above it skip the
+    // iteration), whose ray-independent terms come precomputed (LDS)
+    if (dh_e > (C)0) {
+      const float4 q = L.pcf[le];
+      add_piece(dh_e, q.y, em_e, q.w, (a.homog_mask >> le) & 1);
+    }
+#pragma unroll 1
+    for (int l = a.nl - 2; l >= a.l_obs; --l) {
+      if (l >= le) continue;
+      const bool homog = (a.homog_mask >> l) & 1;
+      if (homog || !cpos) {
+        const float4 q = L.pcf[l];
+        add_piece(q.x, q.y, q.z, q.w, homog);
+        continue;
+      }
+      // piece_integrals for C^2 > 0 with the layer's constants folded:
+      // r_a - r_b = -d (2 + eps_a + eps_b)/(r_a + r_b), and so on
+      const float4 g = L.pfg[l];  // eps_a, eps_a (2 + eps_a), d, d (2 + eps_a + eps_b)
+      const float4 h = L.pfh[l];  // n_b, -H drho (2 + eps_a + eps_b), H
+      const C ra = F::sqrt_(C2 + g.y);
+      const C inv_rs = F::rcp(ra + r_top);
+      const C rd = -g.w * inv_rs;
+      const C den = Cc * ra + C2 + g.x;
+      const C delta = g.z + Cc * g.w * inv_rs;
+      g_sum += (h.z * invC) * F::log1p_(delta * F::rcp(den));
+      lg_sum += h.z * F::log1p_((rd - g.z) * F::rcp(h.x + r_top));
+      rd_sum += h.z * rd;
+      col += h.y * inv_rs;
+      r_top = ra;
+    }
+  } else {
+    // the layer index runs wave-uniformly (lanes above their emission layer
+    // skip the iteration); the piece constants come from the LDS record of
+    // the layer (a kernel-argument array indexed under per-lane selects
+    // would be read by vector loads with their full latency)
+#pragma unroll 1
+    for (int l = a.nl - 1; l >= a.l_obs; --l) {
+      if (l > le) continue;
+      const double* pc = L.pc[l];
+      const C dh = (l == le) ? dh_e : (C)pc[kPcDh];
+      if (!(dh > (C)0)) continue;
+      add_piece(dh, (C)pc[kPcRho], (l == le) ? em_e : (C)pc[kPcEm], (C)pc[kPcH], (a.homog_mask >> l) & 1);
+    }
   }
   g0 += (double)g_sum;
   pth = g0 + (double)lg_sum;
