@@ -125,6 +125,22 @@ constexpr int32_t kSinkSplat = 16;
 // ------------------------------------------------------ wave/block helpers --
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Lanes of the wave mask m below this lane (its rank among them).
+__device__ __forceinline__ unsigned int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// The value v of lane src (the same src on every lane), read with scalar
+// lane reads rather than a cross-lane permute.
+__device__ __forceinline__ unsigned long long lane_value(unsigned long long v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned int lane_value(unsigned int v, int src) {
+  return (unsigned int)__builtin_amdgcn_readlane((int)v, src);
+}
+
 __device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
   const int lane = lane_id();
 #pragma unroll
@@ -630,11 +646,11 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
       // there is one, else in the output); lanes write at their rank
       const int leader = __ffsll((long long)m) - 1;
       const unsigned int nh = (unsigned int)__popcll(m);
-      const unsigned int rank = (unsigned int)__popcll(m & ((1ull << lane_id()) - 1ull));
+      const unsigned int rank = lanes_below(m);
       unsigned long long base = 0;
       if (stage) {
         if (lane_id() == leader) base = atomicAdd(&stage->n, nh);
-        base = __shfl(base, leader, kWaveSize);
+        base = lane_value(base, leader);
         if (hit) {
           if (base + rank < (unsigned long long)kHitStage) {
             stage->rec[base + rank] = r;
@@ -645,7 +661,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
         }
       } else {
         if (lane_id() == leader) base = atomicAdd(sk.hits.count, (unsigned long long)nh);
-        base = __shfl(base, leader, kWaveSize);
+        base = lane_value(base, leader);
         if (hit) {
           const unsigned long long slot = base + rank;
           if (slot < (unsigned long long)sk.hits.capacity) write_hit(sk.hits, slot, r);
@@ -938,9 +954,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
             const int leader = __ffsll((long long)m) - 1;
             unsigned int base = 0;
             if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
-            base = __shfl(base, leader, kWaveSize);
+            base = lane_value(base, leader);
             if (defer) {
-              const uint64_t slot = (uint64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+              const uint64_t slot = (uint64_t)base + lanes_below(m);
               if (slot < (uint64_t)A.defer_cap) {
                 A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
               } else {
@@ -1271,9 +1287,9 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
             const int leader = __ffsll((long long)m) - 1;
             unsigned int base = 0;
             if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
-            base = __shfl(base, leader, kWaveSize);
+            base = lane_value(base, leader);
             if (defer) {
-              const uint64_t slot = (uint64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+              const uint64_t slot = (uint64_t)base + lanes_below(m);
               if (slot < (uint64_t)A.defer_cap)
                 A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
               else  // queue full: evaluated in float after all

@@ -1100,18 +1100,28 @@ __device__ __forceinline__ int telescope_hit_masked(const Photon<T>& p, const do
 // of the photon.
 __device__ __forceinline__ int telescope_hit_masked_f(const Photon<float>& p, const float (*tel)[4], float pz_rel,
                                                       uint32_t mask, float& s_hit) {
-  int best = -1;
-  float best_s = INFINITY;
-  while (mask) {
-    const int k = __builtin_ctz(mask);
-    mask &= mask - 1u;
+  // entry distance along the line to sphere k, or +inf when the line misses it
+  auto entry = [&](int k) {
     const float4 c = *reinterpret_cast<const float4*>(tel[k]);
     const float ox = p.x - c.x, oy = p.y - c.y, oz = pz_rel - c.z;
     const float b = p.ux * ox + p.uy * oy + p.uz * oz;
     const float cc = (ox * ox + oy * oy + oz * oz) - c.w * c.w;
     const float disc = b * b - cc;
-    if (disc < 0.0f) continue;
-    const float s = -b - __builtin_amdgcn_sqrtf(disc);
+    return disc < 0.0f ? INFINITY : -b - __builtin_amdgcn_sqrtf(disc);
+  };
+  int best = -1;
+  float best_s = INFINITY;
+  // the first candidate (usually the only one) outside the loop
+  if (mask) {
+    const int k = __builtin_ctz(mask);
+    mask &= mask - 1u;
+    best_s = entry(k);
+    best = best_s < INFINITY ? k : -1;
+  }
+  while (mask) {
+    const int k = __builtin_ctz(mask);
+    mask &= mask - 1u;
+    const float s = entry(k);
     if (s < best_s) {
       best_s = s;
       best = k;
