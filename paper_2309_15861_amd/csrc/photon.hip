@@ -732,7 +732,8 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
 }
 
 // ------------------------------------------------------------ fused kernel --
-constexpr int kWindow = 256;        // segments staged in LDS per work chunk
+constexpr int kWindow = 128;        // segments staged in LDS per piece of a work chunk
+constexpr int kAdjWindow = 256;     // segment offsets staged in LDS per chunk of the adjoint
 constexpr int kMaxChunk = 16384;     // photons per work chunk (the slot map's size)
 constexpr int kMaxChunkSplat = 8192;
 
@@ -775,14 +776,20 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // emission (else Cherenkov). Each carries only its own code.
 constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8;
 
+// Float instances are built for the waves per SIMD that their LDS allows:
+// five of 256 threads (five blocks of under 32 KB per CU), four of 512.
+constexpr int fused_waves_per_eu(bool fp32, int mode, int bs) {
+  return (!fp32 || (mode & kMSplat)) ? 1 : (bs == 256 ? 5 : (bs >= 512 ? 4 : 1));
+}
+
 template <typename T, int BS, int MODE = 0>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !(MODE & kMSplat) && BS >= 256) ? 4 : 1))) void k_fused(FusedArgs A) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu(sizeof(T) == 4, MODE, BS))))
+void k_fused(FusedArgs A) {
   constexpr bool SPLAT = (MODE & kMSplat) != 0;
   constexpr bool RADIAL = (MODE & kMRadial) != 0;
   constexpr bool TABLE = (MODE & kMTable) != 0;
   constexpr bool CHER = (MODE & kMFluo) == 0;
-  // the splat keeps a smaller window so that the whole grid fits in LDS beside it
-  constexpr int kWin = SPLAT ? kWindow / 2 : kWindow;
+  constexpr int kWin = kWindow;
   // telescope tables only where a telescope sink can occur
   constexpr int kTel = (SPLAT || RADIAL) ? 1 : PHOTON_MAX_TELESCOPES;
   constexpr int kCand = (SPLAT || RADIAL) ? 1 : kCandCells * kCandCells;
@@ -858,125 +865,137 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
       __syncthreads();
       continue;
     }
-    if (wave == 0) {
-      const int64_t sl = wave_upper_index(offsets, n_seg, c0);
-      if (lane_id() == 0) s_lo = sl;
-    }
     if (wave == (BS > kWaveSize ? 1 : 0)) {
       const int64_t sh = wave_upper_index(offsets, n_seg, v1 - 1);
       if (lane_id() == 0) s_hi = sh;
     }
-    __syncthreads();
-    // both ends lie in [0, n_seg) for offsets from the count call; the
-    // clamps keep every index in bounds for any offsets array
-    const int64_t lo = min(s_lo, n_seg - 1);
-    const int64_t W = min(s_hi, n_seg - 1) - lo + 1;
-    const bool win = W >= 1 && W <= kWin;
-    if (win) {
-      for (int t = tid; t < W; t += BS) {
-        seg_const<T>(A.seg, lo + t, A.atm, cher, A.g.beam, s_seg[t]);
-        if constexpr (SPLAT) s_wsc[t] = splat_wscale<T>(A, lo + t);
-        s_off[t] = offsets[lo + t];
-      }
-      if (tid == 0) s_off[W] = offsets[lo + W];
-    }
-    __syncthreads();
-    if (win) {
-      // chunks start at multiples of the chunk size (a multiple of 64), so the
-      // 64 photons of a wave share one word of the map
-      const int nw = (int)((v1 - c0 + 63) >> 6);
-      for (int k = tid; k < nw; k += BS) s_bits[k] = 0ull;
-      __syncthreads();
-      for (int t = tid + 1; t < W; t += BS) {
-        const uint64_t st = s_off[t];
-        if (st < v1 && s_off[t + 1] > st) atomicOr(&s_bits[(st - c0) >> 6], 1ull << ((st - c0) & 63));
-      }
-      __syncthreads();
+    // the chunk in pieces [cs, ce) whose segments fit the LDS window (one
+    // piece unless the chunk spans more than kWin segments)
+    for (uint64_t cs = c0; cs < v1;) {
       if (wave == 0) {
-        uint32_t carry = 0;
-        for (int base = 0; base < nw; base += kWaveSize) {
-          const int k = base + lane_id();
-          const uint32_t cnt = k < nw ? (uint32_t)__popcll(s_bits[k]) : 0u;
-          const uint32_t inc = (uint32_t)wave_incl_scan((unsigned long long)cnt);
-          if (k < nw) s_pre[k] = carry + inc - cnt;
-          carry += (uint32_t)__shfl(inc, kWaveSize - 1, kWaveSize);
-        }
+        const int64_t sl = wave_upper_index(offsets, n_seg, cs);
+        if (lane_id() == 0) s_lo = sl;
       }
       __syncthreads();
-      if (tid == 0) s_slot[0] = 0;
-      for (int t = tid + 1; t < W; t += BS) {
-        const uint64_t st = s_off[t];
-        if (st < v1 && s_off[t + 1] > st) {
-          const uint64_t i = st - c0;
-          const uint32_t r = s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull));
-          s_slot[r] = (uint16_t)t;
+      // both ends lie in [0, n_seg) for offsets from the count call; the
+      // clamps keep every index in bounds for any offsets array
+      const int64_t lo = min(s_lo, n_seg - 1);
+      const int64_t W_all = min(s_hi, n_seg - 1) - lo + 1;
+      const int64_t W = min(W_all, (int64_t)kWin);
+      bool win = W >= 1;
+      if (win) {
+        for (int t = tid; t < W; t += BS) {
+          seg_const<T>(A.seg, lo + t, A.atm, cher, A.g.beam, s_seg[t]);
+          if constexpr (SPLAT) s_wsc[t] = splat_wscale<T>(A, lo + t);
+          s_off[t] = offsets[lo + t];
         }
+        if (tid == 0) s_off[W] = offsets[lo + W];
       }
       __syncthreads();
-    }
-    // every lane runs the same number of iterations (the status ballots)
-    for (uint64_t qb = c0; qb < v1; qb += BS) {
-      const uint64_t q = qb + tid;
-      int st_out = -1;
-      bool forced = false;
-      if (q < v1) {
-        SegConst<T> c;
-        uint64_t off_s;
-        int64_t s;
-        T wsc = (T)1;
-        if (win) {
-          // starts at or before q, counted from the map
-          const uint64_t i = q - c0;
-          const int a = s_slot[s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull))];
-          c = s_seg[a];
-          if constexpr (SPLAT) wsc = s_wsc[a];
-          off_s = s_off[a];
-          // keeps the LDS load and the global one below apart (merged, they
-          // would become one generic load through a selected pointer)
-          asm volatile("" : "+v"(off_s));
-          s = lo + a;
-        } else {
-          s = lane_upper_index(offsets, n_seg, q);
-          seg_const<T>(A.seg, s, A.atm, cher, A.g.beam, c);
-          if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
-          off_s = offsets[s];
+      // the piece ends where the first segment beyond the window starts
+      uint64_t ce = win ? min(v1, (uint64_t)s_off[W]) : v1;
+      if (!(ce > cs)) {
+        ce = v1;
+        win = false;
+      }
+      if (win) {
+        const int nw = (int)((ce - cs + 63) >> 6);
+        for (int k = tid; k < nw; k += BS) s_bits[k] = 0ull;
+        __syncthreads();
+        for (int t = tid + 1; t < W; t += BS) {
+          const uint64_t st = s_off[t];
+          if (st < ce && s_off[t + 1] > st) atomicOr(&s_bits[(st - cs) >> 6], 1ull << ((st - cs) & 63));
         }
-        const uint32_t j = (uint32_t)(q - off_s);
-        Photon<T> p;
-        generate_kind<T, CHER>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
-        propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p, c.layer);
-        if constexpr (SPLAT) p.w *= wsc;
-        if (kDefer) {
-          const bool defer = p.status == kDeferred;
-          const unsigned long long m = __ballot(defer);
-          if (m) {
-            // the block's own queue: one LDS atomic per wave
-            const int leader = __ffsll((long long)m) - 1;
-            unsigned int base = 0;
-            if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
-            base = lane_value(base, leader);
-            if (defer) {
-              const uint64_t slot = (uint64_t)base + lanes_below(m);
-              if (slot < (uint64_t)A.defer_cap) {
-                A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
-              } else {
-                // queue full: this ray is evaluated in float after all
-                p.status = PHOTON_LANDED;
-                propagate<T, false, true>(A.atm, s_lane, p, c.layer);
-                forced = true;
+        __syncthreads();
+        if (wave == 0) {
+          uint32_t carry = 0;
+          for (int base = 0; base < nw; base += kWaveSize) {
+            const int k = base + lane_id();
+            const uint32_t cnt = k < nw ? (uint32_t)__popcll(s_bits[k]) : 0u;
+            const uint32_t inc = (uint32_t)wave_incl_scan((unsigned long long)cnt);
+            if (k < nw) s_pre[k] = carry + inc - cnt;
+            carry += (uint32_t)__shfl(inc, kWaveSize - 1, kWaveSize);
+          }
+        }
+        __syncthreads();
+        if (tid == 0) s_slot[0] = 0;
+        for (int t = tid + 1; t < W; t += BS) {
+          const uint64_t st = s_off[t];
+          if (st < ce && s_off[t + 1] > st) {
+            const uint64_t i = st - cs;
+            const uint32_t r = s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull));
+            s_slot[r] = (uint16_t)t;
+          }
+        }
+        __syncthreads();
+      }
+      // every lane runs the same number of iterations (the status ballots)
+      for (uint64_t qb = cs; qb < ce; qb += BS) {
+        const uint64_t q = qb + tid;
+        int st_out = -1;
+        bool forced = false;
+        if (q < ce) {
+          SegConst<T> c;
+          uint64_t off_s;
+          int64_t s;
+          T wsc = (T)1;
+          if (win) {
+            // starts at or before q, counted from the map
+            const uint64_t i = q - cs;
+            const int a = s_slot[s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull))];
+            c = s_seg[a];
+            if constexpr (SPLAT) wsc = s_wsc[a];
+            off_s = s_off[a];
+            // keeps the LDS load and the global one below apart (merged, they
+            // would become one generic load through a selected pointer)
+            asm volatile("" : "+v"(off_s));
+            s = lo + a;
+          } else {
+            s = lane_upper_index(offsets, n_seg, q);
+            seg_const<T>(A.seg, s, A.atm, cher, A.g.beam, c);
+            if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
+            off_s = offsets[s];
+          }
+          const uint32_t j = (uint32_t)(q - off_s);
+          Photon<T> p;
+          generate_kind<T, CHER>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
+          propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p, c.layer);
+          if constexpr (SPLAT) p.w *= wsc;
+          if (kDefer) {
+            const bool defer = p.status == kDeferred;
+            const unsigned long long m = __ballot(defer);
+            if (m) {
+              // the block's own queue: one LDS atomic per wave
+              const int leader = __ffsll((long long)m) - 1;
+              unsigned int base = 0;
+              if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
+              base = lane_value(base, leader);
+              if (defer) {
+                const uint64_t slot = (uint64_t)base + lanes_below(m);
+                if (slot < (uint64_t)A.defer_cap) {
+                  A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
+                } else {
+                  // queue full: this ray is evaluated in float after all
+                  p.status = PHOTON_LANDED;
+                  propagate<T, false, true>(A.atm, s_lane, p, c.layer);
+                  forced = true;
+                }
               }
             }
           }
+          if (!kDefer || p.status != kDeferred)
+            st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, q,
+                                           stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
         }
-        if (!kDefer || p.status != kDeferred)
-          st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, q,
-                                         stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
+        pk += status_inc(st_out);
+        if (kDefer && forced) pk += status_inc(PHOTON_HORIZON_FLOAT);
       }
-      pk += status_inc(st_out);
-      if (kDefer && forced) pk += status_inc(PHOTON_HORIZON_FLOAT);
+      // the per-lane 8-bit counters stay below 256 increments per piece
+      flush_lane_status(pk, s_stat);
+      pk = 0;
+      cs = ce;
+      __syncthreads();  // the window is refilled for the next piece
     }
-    flush_lane_status(pk, s_stat);
-    pk = 0;
     if constexpr (!SPLAT && !RADIAL) {
       if (stage_hits) flush_hits(s_hs.get(), A.sk.hits);
     }
@@ -1213,7 +1232,7 @@ __device__ __forceinline__ void seg_reduce_add(long long key, double v0, double 
 // queues rays near the horizon for k_splat_adjoint_deferred.
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
-  __shared__ uint64_t s_off[kWindow + 1];
+  __shared__ uint64_t s_off[kAdjWindow + 1];
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ double s_acc[kAdjWords * BS];  // lane-private sums: word k of thread t at k * BS + t
@@ -1247,7 +1266,7 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
     __syncthreads();
     const int64_t lo = min(s_lo, n_seg - 1);
     const int64_t W = min(s_hi, n_seg - 1) - lo + 1;
-    const bool win = W >= 1 && W <= kWindow;
+    const bool win = W >= 1 && W <= kAdjWindow;
     if (win)
       for (int t = tid; t <= W; t += BS) s_off[t] = offsets[lo + t];
     __syncthreads();

@@ -113,3 +113,37 @@ def test_device_total_matches_explicit_total(batched):
     assert np.array_equal(res[0], res[1])
     extra = res[2] - res[0]
     assert extra[ph.INVALID] == 1000 and extra.sum() == 1000
+
+
+@pytest.mark.parametrize("prec", [ph.FP32, ph.FP64])
+def test_chunk_pieces_do_not_change_photons(prec):
+    """Sparse segments (fluorescence at 1/400 of the yield: a few photons
+    each): a work chunk spans many more segments than the LDS window holds and
+    is processed in pieces. Every photon comes out the same for every launch
+    shape, bit for bit."""
+    a = W.default_atmosphere(absorption=True)
+    lam, rel = W.fluorescence_lines()
+    seg = W.fluorescence(40_000, seed=5)
+    em = ph.emission_fluor(lam, rel, W.FLUOR_YIELD_PER_MEV / 400.0)
+    d = ph.DeviceSegments(seg)
+    atm = ph.atmosphere(a)
+    counts, offsets = ph.count(d, atm, em, 5)
+    torch.cuda.synchronize()
+    total = int(offsets[-1].item())
+    per_seg = total / len(seg["x0"])
+    assert 16384 / max(per_seg, 1e-9) > 4 * 128  # chunks of 16384 span many windows
+    outs = []
+    for tun in (ph.tuning(128, 1024, 0), ph.tuning(256, 4096, 0), ph.tuning(512, 16384, 0),
+                ph.tuning(256, 16384, 0)):
+        plane = ph.PhotonBlock(total, prec)
+        plane.n_photons = total
+        totals = ph.status_totals()
+        ph.run_fused(d, atm, em, 5, prec, offsets, -1, ph.sink_plane(plane, totals), tun)
+        torch.cuda.synchronize()
+        outs.append((plane.numpy(), totals.cpu().numpy()))
+    g0, t0 = outs[0]
+    assert t0[:7].sum() == total
+    for g, t in outs[1:]:
+        assert np.array_equal(t, t0)
+        for f in g0:
+            assert np.array_equal(g[f], g0[f], equal_nan=np.issubdtype(g0[f].dtype, np.floating)), f
