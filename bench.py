@@ -37,8 +37,8 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9          # VALU lane-slots/s: CUs x SIMDs x la
 SLOTS_PER_PHOTON = {"fp32": 300.0, "fp64": 750.0}
 PMC_FILE = os.path.join(ROOT, "profiles", "fused_shower_fp32_traffic.json")
 # launch shapes the autotuner chooses from: (block, chunk, blocks per CU; 0 = as many as fit)
-TUNING_CANDIDATES = [(256, 4096, 0), (256, 8192, 0), (256, 16384, 0), (512, 8192, 0), (512, 16384, 0),
-                     (128, 4096, 0), (256, 8192, 2)]
+TUNING_CANDIDATES = [(256, 3072, 0), (256, 4096, 0), (256, 8192, 0), (256, 16384, 0), (512, 8192, 0),
+                     (512, 16384, 0), (128, 4096, 0), (256, 8192, 2)]
 
 
 def source_hash() -> str:
@@ -449,7 +449,7 @@ def main():
     achieved = SLOTS_PER_PHOTON["fp32"] * total / (r32["fused_ms"] * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=achieved / PEAK_SLOTS, traffic=traffic_per_launch(),
-                    kernel=f"k_fused<float,{r32['tuning'][0]},false,false>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
+                    kernel=f"k_fused<float, {r32['tuning'][0]}, 0>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
                     fused_ms=r32["fused_ms"], tuning=r32["tuning"])
     r64 = results.get("fp64", r32)
     out = {

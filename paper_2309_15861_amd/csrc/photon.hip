@@ -473,7 +473,7 @@ struct HitRec {
   int32_t tel;
   float ux, uy, uz, lam, w;
 };
-constexpr int kHitStage = 128;  // hit records staged per block and work chunk
+constexpr int kHitStage = 64;  // hit records staged per block and work chunk
 
 struct HitStage {
   unsigned int n;
@@ -777,9 +777,9 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8;
 
 // Float instances are built for the waves per SIMD that their LDS allows:
-// five of 256 threads (five blocks of under 32 KB per CU), four of 512.
+// six of 256 threads (six blocks of under 26.6 KB per CU), four of 512.
 constexpr int fused_waves_per_eu(bool fp32, int mode, int bs) {
-  return (!fp32 || (mode & kMSplat)) ? 1 : (bs == 256 ? 5 : (bs >= 512 ? 4 : 1));
+  return (!fp32 || (mode & kMSplat)) ? 1 : (bs == 256 ? 6 : (bs >= 512 ? 4 : 1));
 }
 
 template <typename T, int BS, int MODE = 0>
