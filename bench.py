@@ -37,6 +37,7 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9          # VALU lane-slots/s: CUs x SIMDs x la
 SLOTS_PER_PHOTON = {"fp32": 300.0, "fp64": 750.0}
 PMC_FILE = os.path.join(ROOT, "profiles", "fused_shower_fp32_traffic.json")
 # launch shapes the autotuner chooses from: (block, chunk, blocks per CU; 0 = as many as fit)
+FP32_TUNING = "256,3072,0"
 TUNING_CANDIDATES = [(256, 3072, 0), (256, 4096, 0), (256, 8192, 0), (256, 16384, 0), (512, 8192, 0),
                      (512, 16384, 0), (128, 4096, 0), (256, 8192, 2)]
 
@@ -355,8 +356,11 @@ def main():
     ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True,
                     help="also time 64 showers of 1e3..1e6 segments in one graph-captured step")
     ap.add_argument("--tuning", default=None,
-                    help="block,chunk,blocks_per_cu of the fused kernel instead of the autotuner's choice "
+                    help="block,chunk,blocks_per_cu of the fused kernel for both forms instead of the defaults "
                          "(profiling runs)")
+    ap.add_argument("--fp32-tuning", default=FP32_TUNING,
+                    help="launch shape of the FP32 form: the fastest on this workload in repeated sweeps of the "
+                         "tuning candidates (a single autotuner pass is within its noise); 'auto' to autotune")
     ap.add_argument("--cut", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the shower step with the 6 degree Cherenkov angular particle cut")
     ap.add_argument("--table", action=argparse.BooleanOptionalAction, default=True,
@@ -413,6 +417,8 @@ def main():
         # launch shape from the autotuner, then the whole step captured in a graph
         if args.tuning:
             best = ph.tuning(*(int(v) for v in args.tuning.split(",")))
+        elif prec == ph.FP32 and args.fp32_tuning != "auto":
+            best = ph.tuning(*(int(v) for v in args.fp32_tuning.split(",")))
         else:
             best, _ = ph.autotune(d, atm, em, seed, prec, offsets, sink, TUNING_CANDIDATES, reps=3)
         plan = ph.Plan(d, atm, em, seed, prec, counts, offsets, sink, best)
@@ -431,15 +437,15 @@ def main():
         assert hits.count() <= hits.capacity
         nhits = hits.count()
         plan.close()
-        # the fused kernel alone, same shape, bracketed by events on its stream
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        for e0, e1 in evs:
-            e0.record(stream)
+        # the persistent kernel alone, same shape: the library's HIP events
+        # around its launch on the stream it runs on
+        ph.kernel_timing(True)
+        kms = []
+        for _ in range(args.steps):
             ph.run_fused(d, atm, em, seed, prec, offsets, -1, sink, best)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        fused_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+            kms.append(ph.fused_kernel_ms())
+        ph.kernel_timing(False)
+        fused_ms = float(np.mean(kms))
         results[name] = dict(ms_per_step=ms / args.steps, fused_ms=fused_ms,
                              photons_per_s=total * args.steps / (ms * 1e-3), hits=nhits,
                              status_totals=[int(x) for x in tot],

@@ -348,6 +348,17 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
                      const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
                      const photon_tuning* tuning, void* stream);
 
+/* Kernel timing, a measurement aid. With on != 0, every fused launch on the
+   current device outside a stream capture (photon_run_fused, the splat
+   forward) records a pair of HIP events on its stream around the persistent
+   kernel alone (not the clearing, count or near-horizon kernels around it).
+   photon_fused_kernel_ms waits for the last such launch and returns its
+   kernel time in ms; PHOTON_EINVAL if none was timed since timing was last
+   switched. Events are created on the first call with on != 0 and kept for
+   the process. */
+int photon_kernel_timing(int32_t on);
+int photon_fused_kernel_ms(float* ms);
+
 /* ---- captured steps (HIP graphs) and launch-shape tuning ------------------ */
 
 /* A plan is one whole step captured into a HIP graph: per-segment counts and

@@ -1865,6 +1865,10 @@ struct DeviceState {
   double* adj_part = nullptr;               // per-block partial sums of the adjoint
   unsigned long long* splat_acc = nullptr;  // fixed-point grid of the splat
   int64_t splat_cells = 0;
+  // kernel timing (photon_kernel_timing): events around the last fused
+  // kernel launched outside a stream capture
+  bool timing = false, timed = false;
+  hipEvent_t t_ev[2] = {nullptr, nullptr};
 };
 std::mutex g_mu;
 DeviceState g_dev[64];
@@ -2082,8 +2086,19 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   A.n_defer_blocks = (int32_t)grid;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
   void* kargs[] = {&A};
+  bool timed = false;
+  if (dev->timing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return fail(PHOTON_EHIP, "stream capture query failed");
+    timed = cs == hipStreamCaptureStatusNone;
+    if (timed && hipEventRecord(dev->t_ev[0], st) != hipSuccess) return fail(PHOTON_EHIP, "event record failed");
+  }
   if (hipLaunchKernel(kfn, dim3((unsigned)grid), dim3(BS), kargs, dyn_lds, st) != hipSuccess)
     return fail(PHOTON_EHIP, "fused kernel launch failed");
+  if (timed) {
+    if (hipEventRecord(dev->t_ev[1], st) != hipSuccess) return fail(PHOTON_EHIP, "event record failed");
+    dev->timed = true;
+  }
   if (defer) {
     hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
                        (int)grid, A.defer_cap, dev->defer_pref);
@@ -2424,6 +2439,30 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm, c
   DeviceState* dev;
   if ((rc = current_device(&dev))) return rc;
   return enqueue_fused(a, offsets, n_photons, tuning, dev, (hipStream_t)stream);
+}
+
+int photon_kernel_timing(int32_t on) {
+  DeviceState* dev;
+  int rc;
+  if ((rc = current_device(&dev))) return rc;
+  if (on && !dev->t_ev[0]) {
+    for (hipEvent_t& e : dev->t_ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(PHOTON_EHIP, "event creation failed");
+  }
+  dev->timing = on != 0;
+  dev->timed = false;
+  return PHOTON_OK;
+}
+
+int photon_fused_kernel_ms(float* ms) {
+  if (!ms) return fail(PHOTON_EINVAL, "ms is NULL");
+  DeviceState* dev;
+  int rc;
+  if ((rc = current_device(&dev))) return rc;
+  if (!dev->timed) return fail(PHOTON_EINVAL, "no fused kernel timed on this device (photon_kernel_timing off?)");
+  if (hipEventSynchronize(dev->t_ev[1]) != hipSuccess || hipEventElapsedTime(ms, dev->t_ev[0], dev->t_ev[1]) != hipSuccess)
+    return fail(PHOTON_EHIP, "event timing failed");
+  return PHOTON_OK;
 }
 
 int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,

@@ -121,13 +121,15 @@ def lib():
         L.photon_generate.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P]
         L.photon_radial_profile.argtypes = [P, P, P, P]
         L.photon_table_build.argtypes = [P, P, P]
+        L.photon_kernel_timing.argtypes = [C.c_int32]
+        L.photon_fused_kernel_ms.argtypes = [P]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
                   "photon_run_fused", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
                   "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward",
-                  "photon_count"):
+                  "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -487,6 +489,20 @@ def run_fused(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precisio
     _check(lib().photon_run_fused(C.byref(s), C.byref(atm), C.byref(em), int(seed), int(precision),
                                   _ptr(offsets), int(n_photons), C.byref(sink),
                                   None if tuning is None else C.byref(tuning), _stream()))
+
+
+def kernel_timing(on: bool):
+    """Events around every fused kernel launched on the current device
+    outside a stream capture (photon_kernel_timing)."""
+    _check(lib().photon_kernel_timing(1 if on else 0))
+
+
+def fused_kernel_ms() -> float:
+    """Kernel time of the last fused launch timed on the current device
+    (waits for it)."""
+    ms = C.c_float(0.0)
+    _check(lib().photon_fused_kernel_ms(C.byref(ms)))
+    return float(ms.value)
 
 
 def tuning(block=256, chunk=4096, blocks_per_cu=0) -> Tuning:

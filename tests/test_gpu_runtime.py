@@ -147,3 +147,31 @@ def test_chunk_pieces_do_not_change_photons(prec):
         assert np.array_equal(t, t0)
         for f in g0:
             assert np.array_equal(g[f], g0[f], equal_nan=np.issubdtype(g0[f].dtype, np.floating)), f
+
+
+def test_kernel_timing(batched):
+    """The library's events around the persistent kernel: positive, below the
+    time of the whole fused call (which adds the clearing and the
+    near-horizon pass), and absent while switched off or under capture."""
+    a, seg, d, atm, em, counts, offsets, total = batched
+    sink = ph.sink_status(ph.status_totals())
+    ph.kernel_timing(True)
+    with pytest.raises(ph.PhotonError):
+        ph.fused_kernel_ms()           # nothing timed yet
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ph.run_fused(d, atm, em, 4, ph.FP32, offsets, -1, sink, ph.tuning(256, 4096, 0))
+    e1.record(stream)
+    k = ph.fused_kernel_ms()
+    torch.cuda.synchronize()
+    assert 0.0 < k <= e0.elapsed_time(e1)
+    # a captured step records no events
+    plan = ph.Plan(d, atm, em, 4, ph.FP32, counts, offsets, sink, ph.tuning(256, 4096, 0))
+    ph.kernel_timing(True)
+    plan.launch()
+    torch.cuda.synchronize()
+    with pytest.raises(ph.PhotonError):
+        ph.fused_kernel_ms()
+    plan.close()
+    ph.kernel_timing(False)
