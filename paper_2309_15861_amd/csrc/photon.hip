@@ -303,6 +303,36 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+// Up to kZeroLists arrays of 64-bit words and one of 32-bit words cleared by
+// one launch (the sink outputs and the work cursor of a step).
+constexpr int kZeroLists = 6;
+struct ZeroList {
+  unsigned long long* p[kZeroLists];
+  int32_t n[kZeroLists];
+  int32_t k = 0;
+  uint32_t* p32 = nullptr;
+  int32_t n32 = 0;
+  void add(unsigned long long* q, int32_t m) {
+    p[k] = q;
+    n[k++] = m;
+  }
+};
+
+__global__ void k_zero_list(ZeroList z) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  for (int i = 0; i < z.k; ++i)
+    for (int j = t; j < z.n[i]; j += stride) z.p[i][j] = 0ull;
+  for (int j = t; j < z.n32; j += stride) z.p32[j] = 0u;
+}
+
+void launch_zero_list(const ZeroList& z, hipStream_t st) {
+  int m = z.n32;
+  for (int i = 0; i < z.k; ++i) m = m > z.n[i] ? m : z.n[i];
+  if (m <= 0) return;
+  const int blocks = (int)std::min<int64_t>((m + 255) / 256, 64);
+  hipLaunchKernelGGL(k_zero_list, dim3((unsigned)blocks), dim3(256), 0, st, z);
+}
+
 __global__ void k_zero_u32(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -882,7 +912,10 @@ void k_fused(FusedArgs A) {
       const int64_t lo = min(s_lo, n_seg - 1);
       const int64_t W_all = min(s_hi, n_seg - 1) - lo + 1;
       const int64_t W = min(W_all, (int64_t)kWin);
-      bool win = W >= 1;
+      // windows while the rest of the chunk has at least one photon per
+      // segment; sparser chunks (mostly empty segments) look their photons'
+      // segments up in global memory instead of staging every segment
+      bool win = W >= 1 && (W_all <= (int64_t)kWin || (int64_t)(v1 - cs) >= W_all);
       if (win) {
         for (int t = tid; t < W; t += BS) {
           seg_const<T>(A.seg, lo + t, A.atm, cher, A.g.beam, s_seg[t]);
@@ -2046,7 +2079,7 @@ int ensure_defer_queue(DeviceState* dev) {
 template <typename T, int BS, bool SPLAT = false>
 int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                     const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
-                    DeviceState* dev, hipStream_t st, size_t dyn_lds = 0) {
+                    DeviceState* dev, hipStream_t st, size_t dyn_lds = 0, const ZeroList* pre = nullptr) {
   const bool radial = !SPLAT && sk.kind == PHOTON_SINK_RADIAL;
   const bool table = !SPLAT && atm.tcorr != nullptr;
   const int mode = SPLAT ? kMSplat
@@ -2084,7 +2117,10 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   A.defer_cap = defer ? kDeferCap / grid : 0;
   A.defer_pref = dev->defer_pref;
   A.n_defer_blocks = (int32_t)grid;
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
+  // the work cursor, with whatever the caller asked to clear before the kernel
+  ZeroList z = pre ? *pre : ZeroList{};
+  z.add(dev->work, 1);
+  launch_zero_list(z, st);
   void* kargs[] = {&A};
   bool timed = false;
   if (dev->timing) {
@@ -2110,7 +2146,7 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
 template <typename T>
 int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                  const uint64_t* offsets, int64_t n_ph, const photon_tuning* tun, const SinkDev& sk,
-                 DeviceState* dev, hipStream_t st) {
+                 DeviceState* dev, hipStream_t st, const ZeroList* pre = nullptr) {
   int bs = tun ? tun->block : 256;
   int64_t chunk = tun ? tun->chunk : 4096;
   int bpc = tun ? tun->blocks_per_cu : 0;
@@ -2119,9 +2155,9 @@ int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParam
     return fail(PHOTON_EINVAL, "tuning.chunk must be a multiple of block, at most %d", kMaxChunk);
   if (bpc < 0) return fail(PHOTON_EINVAL, "tuning.blocks_per_cu must be >= 0");
   switch (bs) {
-    case 128: return launch_fused_bs<T, 128>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st);
-    case 512: return launch_fused_bs<T, 512>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st);
-    default: return launch_fused_bs<T, 256>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st);
+    case 128: return launch_fused_bs<T, 128>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre);
+    case 512: return launch_fused_bs<T, 512>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre);
+    default: return launch_fused_bs<T, 256>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre);
   }
 }
 
@@ -2168,30 +2204,36 @@ int prep_step(const photon_segments* seg, const photon_atmosphere* atm, const ph
   return PHOTON_OK;
 }
 
-int clear_sink(const SinkDev& sk, hipStream_t st) {
-  if (sk.totals) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, sk.totals, PHOTON_N_STATUS);
-  if (sk.kind == PHOTON_SINK_TELESCOPES)
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, sk.hits.count, 1);
+// The sink outputs a step clears before its fused kernel.
+ZeroList sink_zero_list(const SinkDev& sk) {
+  ZeroList z;
+  if (sk.totals) z.add(sk.totals, PHOTON_N_STATUS);
+  if (sk.kind == PHOTON_SINK_TELESCOPES) z.add(sk.hits.count, 1);
   if (sk.kind == PHOTON_SINK_GRID) {
-    const int cells = sk.nx * sk.ny;
-    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, sk.grid_count, cells);
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, st, sk.grid_weight, cells);
+    z.p32 = sk.grid_count;
+    z.n32 = sk.nx * sk.ny;
+    z.add(sk.grid_weight, sk.nx * sk.ny);
   }
   if (sk.kind == PHOTON_SINK_RADIAL) {
-    const unsigned nb = (unsigned)ceil_div(sk.n_bins, 256);
-    hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, st, sk.rad_count, sk.n_bins);
-    hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, st, sk.rad_w, sk.n_bins);
-    hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, st, sk.rad_wt, sk.n_bins);
+    z.add(sk.rad_count, sk.n_bins);
+    z.add(sk.rad_w, sk.n_bins);
+    z.add(sk.rad_wt, sk.n_bins);
   }
-  return check_launch();
+  return z;
 }
 
 int enqueue_fused(const StepArgs& a, const uint64_t* offsets, int64_t n_ph, const photon_tuning* tun,
-                  DeviceState* dev, hipStream_t st) {
-  if (a.n == 0 || n_ph == 0) return PHOTON_OK;
+                  DeviceState* dev, hipStream_t st, const ZeroList* pre = nullptr) {
+  if (a.n == 0 || n_ph == 0) {
+    if (pre) {
+      launch_zero_list(*pre, st);
+      return check_launch();
+    }
+    return PHOTON_OK;
+  }
   return a.precision == PHOTON_FP64
-             ? launch_fused<double>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st)
-             : launch_fused<float>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st);
+             ? launch_fused<double>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st, pre)
+             : launch_fused<float>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st, pre);
 }
 
 // One whole step: counts + offsets, cleared outputs, fused kernel.
@@ -2199,8 +2241,9 @@ int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const p
                  DeviceState* dev, hipStream_t st) {
   int rc;
   if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.cut, a.g.beam, a.seed, counts, offsets, st))) return rc;
-  if ((rc = clear_sink(a.sk, st))) return rc;
-  return enqueue_fused(a, offsets, -1, tun, dev, st);
+  // the sink outputs are cleared by the launch that clears the work cursor
+  const ZeroList z = sink_zero_list(a.sk);
+  return enqueue_fused(a, offsets, -1, tun, dev, st, &z);
 }
 
 // ------------------------------------------------------ differentiable form --
