@@ -321,7 +321,9 @@ int photon_gen_fluor(const photon_segments* seg, const photon_atmosphere* atm,
    the plane-parallel atmosphere (n sin(theta) conserved) is carried to
    h_obs with closed-form layer integrals: landing point, arrival time
    t + (optical path)/c, path length, arrival direction (Snell), weight
-   exp(-k(lambda) * column density along the ray). Errors: EINVAL. */
+   exp(-k(lambda) * column density along the ray). Directions are taken as
+   unit vectors in FP32 (the generators' are, to rounding) and normalised in
+   FP64. Errors: EINVAL. */
 int photon_propagate(photon_block* inout, const photon_atmosphere* atm, void* stream);
 
 /* Collection of a propagated block into `sink` (status totals, telescope

@@ -636,7 +636,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
         const T fx = (p.x - (T)sk.cand_x0) * (T)sk.cand_inv_cell;
         const T fy = (p.y - (T)sk.cand_y0) * (T)sk.cand_inv_cell;
         const bool in = fx >= (T)0 && fy >= (T)0 && fx < (T)kCandCells && fy < (T)kCandCells;
-        mask = in ? cand[(int)fy * kCandCells + (int)fx] : 0u;
+        mask = in ? cand[__umul24((uint32_t)fy, (uint32_t)kCandCells) + (uint32_t)fx] : 0u;
       } else {
         mask = sk.n_tel >= 32 ? 0xffffffffu : ((1u << sk.n_tel) - 1u);
       }

@@ -343,7 +343,8 @@ struct SegHi<double> {};
 
 template <typename T>
 struct SegConst : SegHi<T> {
-  double x0, y0, z0, t0, inv_bc;   // start point, start time, 1/(beta c)
+  T x0, y0;                        // start point (horizontal: in the working precision)
+  double z0, t0, inv_bc;           // start height, start time, 1/(beta c)
   T dx, dy, dz, len;               // unit direction, length
   T cos_c, sin_c;                  // Cherenkov cone (section 1.2); beamed fluorescence: cos_c = om
   T ax, ay, az;                    // unit bisector of the cone axis and (0,0,-1)
@@ -380,8 +381,8 @@ __device__ __forceinline__ void seg_const(const SegView& s, int64_t i, const Atm
   const double dx = s.dx[i], dy = s.dy[i], dz = s.dz[i];
   const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
   const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
-  c.x0 = s.x0[i];
-  c.y0 = s.y0[i];
+  c.x0 = (T)s.x0[i];
+  c.y0 = (T)s.y0[i];
   c.z0 = s.z0[i];
   c.t0 = s.t0[i];
   c.inv_bc = 1.0 / (s.beta[i] * kC);
@@ -464,8 +465,8 @@ __device__ __forceinline__ void gen_cherenkov(const SegConst<T>& c, uint32_t j, 
   const U4 r = philox(j, c.idx, c.shower, kDomCher, k0, k1);
   const T u0 = u01<T>(r.w[0]), u1 = u01<T>(r.w[1]), u2 = u01<T>(r.w[2]);
   const T s = u0 * c.len;
-  p.x = (T)c.x0 + s * c.dx;
-  p.y = (T)c.y0 + s * c.dy;
+  p.x = c.x0 + s * c.dx;
+  p.y = c.y0 + s * c.dy;
   p.z = c.z0 + (double)(s * c.dz);
   p.t = c.t0 + (double)s * c.inv_bc;
   T sp, cp;
@@ -502,8 +503,8 @@ __device__ __forceinline__ void gen_fluor(const SegConst<T>& c, uint32_t j, uint
   const U4 r = philox(j, c.idx, c.shower, kDomFluo, k0, k1);
   const T u0 = u01<T>(r.w[0]), u1 = u01<T>(r.w[1]), u2 = u01<T>(r.w[2]);
   const T s = u0 * c.len;
-  p.x = (T)c.x0 + s * c.dx;
-  p.y = (T)c.y0 + s * c.dy;
+  p.x = c.x0 + s * c.dx;
+  p.y = c.y0 + s * c.dy;
   p.z = c.z0 + (double)(s * c.dz);
   p.t = c.t0 + (double)s * c.inv_bc;
   if (beam) {
@@ -962,11 +963,12 @@ __device__ __forceinline__ void propagate(const AtmDev& a, const AtmLane& L, Pho
     p.status = PHOTON_BELOW;
     return;
   }
-  const T inv_un = F::rcp(F::sqrt_(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz));
+  // the float form's directions are unit to rounding (a half turn of a unit
+  // vector, or drawn on the sphere): used as they are; the double form
+  // renormalises
+  const T inv_un = sizeof(T) == 8 ? F::rcp(F::sqrt_(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz)) : (T)1;
   const T ux = p.ux * inv_un, uy = p.uy * inv_un;
-  // zenith cosine and sine in double from the double vertical component (the
-  // float form's directions are unit to rounding; rescaling the exact
-  // component by a float norm would only add error)
+  // zenith cosine and sine in double from the double vertical component
   const double ced = sizeof(T) == 8 ? -p.uzd * (double)inv_un : -p.uzd;
   const double omc = (1.0 - ced) * (1.0 + ced);
   // the sine in double only where a double pass in place needs it (the
