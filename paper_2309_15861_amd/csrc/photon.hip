@@ -836,9 +836,10 @@ void k_fused(FusedArgs A) {
   __shared__ T s_wsc[SPLAT ? kWin : 1];  // SPLAT: per-segment weight factors mu/mu0
   __shared__ AtmLane s_lane;
   __shared__ uint32_t s_cand[kCand];
-  // slot map of a chunk: bit i of s_bits is set where a segment of the window
-  // starts at photon c0 + i; s_pre holds the set bits before each word and
-  // s_slot[r] the window slot of the r-th start (r = 0: the segment holding c0)
+  // slot map of a piece [cs, ce) of a chunk: bit i of s_bits is set where a
+  // segment of the window starts at photon cs + i; s_pre holds the set bits
+  // before each word and s_slot[r] the window slot of the r-th start (r = 0:
+  // the segment holding cs)
   constexpr int kMapWords = (SPLAT ? kMaxChunkSplat : kMaxChunk) / 64;
   __shared__ unsigned long long s_bits[kMapWords];
   __shared__ uint32_t s_pre[kMapWords];
@@ -875,7 +876,7 @@ void k_fused(FusedArgs A) {
   const uint64_t* __restrict__ offsets = A.offsets;
   __shared__ unsigned long long s_stat[PHOTON_N_STATUS];  // the block's status totals
   if (tid < PHOTON_N_STATUS) s_stat[tid] = 0ull;
-  uint64_t pk = 0;  // this lane's status counts in the current chunk
+  uint64_t pk = 0;  // this lane's status counts in the current piece
   // Slots at or beyond offsets[n_seg] belong to no segment: counted INVALID.
   const uint64_t total = offsets[n_seg];
   const int64_t n_ph = A.n_ph < 0 ? (int64_t)total : A.n_ph;
