@@ -333,11 +333,6 @@ void launch_zero_list(const ZeroList& z, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_list, dim3((unsigned)blocks), dim3(256), 0, st, z);
 }
 
-__global__ void k_zero_u32(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
 // Grid-stride clear of n 64-bit words (a kernel, not a memset node, so that
 // captured graphs replay it faithfully).
 __global__ void k_zero64_n(unsigned long long* p, int64_t n) {
@@ -1223,12 +1218,6 @@ __device__ __forceinline__ void adj_block_sums(const double* s_acc, double* row)
     for (int i = 0; i < BS; ++i) t += s_acc[tid * BS + i];
     row[tid] = t;
   }
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int d = kWaveSize / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWaveSize);
-  return v;
 }
 
 // Sums over each run of equal keys of a wave (keys nondecreasing over the

@@ -260,30 +260,10 @@ __device__ __forceinline__ uint32_t poisson_chunks(double mu) {
 }
 
 // One chunk: the smallest k with F(k) >= u for Poisson(mc), p0 = exp(-mc).
-// Four terms per pass with their reciprocals 1/k read together, so the LDS
-// latency is paid once per four steps of the dependent chain; the terms and
-// the running sum are formed in the same order as one step at a time.
 __device__ __forceinline__ uint32_t poisson_chunk(double u, double mc, double p0, const double* rk) {
 #pragma clang fp contract(off)
   uint32_t k = 0;
   double p = p0, F = p0;
-  if (!(u > F)) return 0u;
-  while (k + 4u <= kPoissonKmax) {
-    const double r1 = rk[k + 1], r2 = rk[k + 2], r3 = rk[k + 3], r4 = rk[k + 4];
-    p = (p * mc) * r1;
-    F = F + p;
-    if (!(u > F)) return k + 1u;
-    p = (p * mc) * r2;
-    F = F + p;
-    if (!(u > F)) return k + 2u;
-    p = (p * mc) * r3;
-    F = F + p;
-    if (!(u > F)) return k + 3u;
-    p = (p * mc) * r4;
-    F = F + p;
-    if (!(u > F)) return k + 4u;
-    k += 4u;
-  }
   while (u > F && k < kPoissonKmax) {
     k += 1;
     p = (p * mc) * rk[k];
