@@ -1108,6 +1108,9 @@ __global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
   __shared__ AtmLane s_lane;
   __shared__ uint32_t s_cand[kCandCells * kCandCells];
   const int tid = threadIdx.x;
+  // blocks beyond the queued rays leave before staging their tables (the
+  // grid is sized for the largest queue; usually a few blocks have work)
+  if ((uint64_t)blockIdx.x * BS >= A.defer_pref[A.n_defer_blocks]) return;
   if (tid < PHOTON_MAX_LINES) {
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = A.g.line_nm[tid];
