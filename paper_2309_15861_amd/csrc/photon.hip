@@ -90,7 +90,7 @@ struct SinkDev {
   int32_t n_tel;
   unsigned long long* totals;
   double tel[PHOTON_MAX_TELESCOPES][4];
-  // h_obs (the float form's LDS table holds x, y, z - h_obs, R); the
+  // h_obs (the float form's LDS table holds x, y, z - h_obs, R^2); the
   // candidate grid's origin and cells per metre (float: the lists carry a
   // 1 mm margin for the rounding)
   double tel_hobs;
@@ -628,10 +628,20 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
     if (active && st == PHOTON_LANDED) {
       uint32_t mask;
       if (-p.uz >= (T)kCapCos) {
+        // cell indices rounded down (negative outside the grid on the low
+        // side, so one unsigned comparison per axis bounds them)
         const T fx = (p.x - (T)sk.cand_x0) * (T)sk.cand_inv_cell;
         const T fy = (p.y - (T)sk.cand_y0) * (T)sk.cand_inv_cell;
-        const bool in = fx >= (T)0 && fy >= (T)0 && fx < (T)kCandCells && fy < (T)kCandCells;
-        mask = in ? cand[__umul24((uint32_t)fy, (uint32_t)kCandCells) + (uint32_t)fx] : 0u;
+        uint32_t ix, iy;
+        if constexpr (sizeof(T) == 4) {
+          ix = (uint32_t)__float2int_rd(fx);
+          iy = (uint32_t)__float2int_rd(fy);
+        } else {
+          ix = (uint32_t)(int)floor(fmax(fmin(fx, 1e9), -1e9));
+          iy = (uint32_t)(int)floor(fmax(fmin(fy, 1e9), -1e9));
+        }
+        const bool in = ix < (uint32_t)kCandCells && iy < (uint32_t)kCandCells;
+        mask = in ? cand[__umul24(iy, (uint32_t)kCandCells) + ix] : 0u;
       } else {
         mask = sk.n_tel >= 32 ? 0xffffffffu : ((1u << sk.n_tel) - 1u);
       }
@@ -709,10 +719,10 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
   return st;
 }
 
-// Word k of the float telescope table (x, y, z - h_obs, R).
+// Word k of the float telescope table (x, y, z - h_obs, R^2).
 __device__ __forceinline__ float tel_float(const SinkDev& sk, int k) {
   const double v = (&sk.tel[0][0])[k];
-  return (float)((k & 3) == 2 ? v - sk.tel_hobs : v);
+  return (float)((k & 3) == 2 ? v - sk.tel_hobs : ((k & 3) == 3 ? v * v : v));
 }
 
 template <typename T>

@@ -1098,7 +1098,7 @@ __device__ __forceinline__ int telescope_hit_masked(const Photon<T>& p, const do
   return best;
 }
 
-// The float form on float centres (x, y, z - h_obs, R); pz_rel = z - h_obs
+// The float form on float centres (x, y, z - h_obs, R^2); pz_rel = z - h_obs
 // of the photon.
 __device__ __forceinline__ int telescope_hit_masked_f(const Photon<float>& p, const float (*tel)[4], float pz_rel,
                                                       uint32_t mask, float& s_hit) {
@@ -1107,7 +1107,7 @@ __device__ __forceinline__ int telescope_hit_masked_f(const Photon<float>& p, co
     const float4 c = *reinterpret_cast<const float4*>(tel[k]);
     const float ox = p.x - c.x, oy = p.y - c.y, oz = pz_rel - c.z;
     const float b = p.ux * ox + p.uy * oy + p.uz * oz;
-    const float cc = (ox * ox + oy * oy + oz * oz) - c.w * c.w;
+    const float cc = (ox * ox + oy * oy + oz * oz) - c.w;
     const float disc = b * b - cc;
     return disc < 0.0f ? INFINITY : -b - __builtin_amdgcn_sqrtf(disc);
   };
