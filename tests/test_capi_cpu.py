@@ -141,6 +141,15 @@ def test_valid_arguments_without_device_report_enodev(ph):
     assert ph.lib().photon_init() == ph.ENODEV
 
 
+def test_kernel_timing_without_device(ph):
+    """The timing entry points: a NULL output is rejected before any device
+    access; switching timing on needs a device."""
+    L = ph.lib()
+    assert L.photon_fused_kernel_ms(None) == ph.EINVAL
+    assert L.photon_kernel_timing(1) == ph.ENODEV
+    assert L.photon_kernel_timing(0) == ph.ENODEV
+
+
 def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
     from paper_2309_15861_amd import photon
     monkeypatch.setattr(photon, "_lib", None)
