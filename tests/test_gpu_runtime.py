@@ -116,15 +116,18 @@ def test_device_total_matches_explicit_total(batched):
 
 
 @pytest.mark.parametrize("prec", [ph.FP32, ph.FP64])
-def test_chunk_pieces_do_not_change_photons(prec):
+@pytest.mark.parametrize("dilution", [400.0, 8000.0])
+def test_chunk_pieces_do_not_change_photons(prec, dilution):
     """Sparse segments (fluorescence at 1/400 of the yield: a few photons
     each): a work chunk spans many more segments than the LDS window holds and
-    is processed in pieces. Every photon comes out the same for every launch
-    shape, bit for bit."""
+    is processed in pieces. At 1/8000 (most segments empty, fewer photons than
+    segments in a chunk) chunks look their segments up in global memory
+    instead. Every photon comes out the same for every launch shape, bit for
+    bit."""
     a = W.default_atmosphere(absorption=True)
     lam, rel = W.fluorescence_lines()
     seg = W.fluorescence(40_000, seed=5)
-    em = ph.emission_fluor(lam, rel, W.FLUOR_YIELD_PER_MEV / 400.0)
+    em = ph.emission_fluor(lam, rel, W.FLUOR_YIELD_PER_MEV / dilution)
     d = ph.DeviceSegments(seg)
     atm = ph.atmosphere(a)
     counts, offsets = ph.count(d, atm, em, 5)
@@ -132,6 +135,7 @@ def test_chunk_pieces_do_not_change_photons(prec):
     total = int(offsets[-1].item())
     per_seg = total / len(seg["x0"])
     assert 16384 / max(per_seg, 1e-9) > 4 * 128  # chunks of 16384 span many windows
+    assert (per_seg < 1.0) == (dilution > 1000.0) and total > 1000
     outs = []
     for tun in (ph.tuning(128, 1024, 0), ph.tuning(256, 4096, 0), ph.tuning(512, 16384, 0),
                 ph.tuning(256, 16384, 0)):
