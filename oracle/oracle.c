@@ -123,6 +123,42 @@ static void draw4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* The exponential wherever it decides an integer (the Poisson count, via   */
+/* the refractive index at the segment midpoint and exp(-mean), and the     */
+/* layer base densities those use). A library exp is only faithful to about */
+/* one unit in the last place and differs between libraries, which would    */
+/* let a count differ between two correct implementations. This one is a    */
+/* fully specified sequence of IEEE double operations (no contraction), so  */
+/* any implementation of the same steps gets the same bits:                 */
+/*   k = nearest integer to x / ln 2 (ties to even);                        */
+/*   r = (x - k ln2_hi) - k ln2_lo   (W. J. Cody, W. Waite, "Software Manual */
+/*       for the Elementary Functions", 1980: ln 2 split so that k ln2_hi is  */
+/*       exact; |r| <= ln 2 / 2);                                           */
+/*   e^r = sum of r^i / i! for i = 0..13 (Taylor series; the first omitted   */
+/*       term is below 5e-18 for |r| <= ln 2 / 2), by Horner from i = 13;    */
+/*   exp(x) = e^r 2^k (ldexp).                                              */
+/* The coefficients are 1/i! rounded to double.                             */
+/* ------------------------------------------------------------------------ */
+static const double OR_INV_FACT[14] = {
+    1.0, 1.0, 0.5, 0x1.5555555555555p-3, 0x1.5555555555555p-5, 0x1.1111111111111p-7,
+    0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19,
+    0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+
+double or_exp_fixed(double x) {
+  if (isnan(x)) return x;
+  if (x > 709.78) return INFINITY;
+  if (x < -745.2) return 0.0;
+  const double ln2_hi = 0x1.62e42fee00000p-1;   /* 21 trailing zero bits */
+  const double ln2_lo = 0x1.a39ef35793c76p-33;
+  const double inv_ln2 = 0x1.71547652b82fep+0;
+  double k = rint(x * inv_ln2);
+  double r = (x - k * ln2_hi) - k * ln2_lo;
+  double p = OR_INV_FACT[13];
+  for (int i = 12; i >= 0; --i) p = p * r + OR_INV_FACT[i];
+  return ldexp(p, (int)k);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Atmosphere: plane-parallel, piecewise exponential density, refractive    */
 /* index n(h) = 1 + (n0 - 1) rho(h)/rho0. Layer i covers                     */
 /* [h_base[i], h_base[i+1]); layer 0 also extends below h_base[0] and the   */
@@ -131,7 +167,7 @@ static void draw4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t
 void or_atm_prepare(or_atmosphere* a) {
   a->rho_base[0] = 1.0;
   for (int i = 0; i + 1 < a->n_layers; ++i)
-    a->rho_base[i + 1] = a->rho_base[i] * exp(-(a->h_base[i + 1] - a->h_base[i]) / a->H[i]);
+    a->rho_base[i + 1] = a->rho_base[i] * or_exp_fixed(-(a->h_base[i + 1] - a->h_base[i]) / a->H[i]);
 }
 
 int or_layer_of(const or_atmosphere* a, double h) {
@@ -193,7 +229,7 @@ double or_segment_index(const or_segments* s, int64_t i, const or_atmosphere* a)
   int l = 0;
   for (int k = 0; k < a->n_layers; ++k)
     if (a->h_base[k] <= zc) l = k;
-  double rho = a->rho_base[l] * exp(-(zc - a->h_base[l]) / a->H[l]);
+  double rho = a->rho_base[l] * or_exp_fixed(-(zc - a->h_base[l]) / a->H[l]);
   return 1.0 + a->eta0 * rho;
 }
 
@@ -228,8 +264,8 @@ double or_mean_fluor(const or_segments* s, int64_t i, double yield_per_MeV) {
    mu is split into m equal chunks of at most 128 (exp(-mu) would underflow
    for large mu); each chunk draws the smallest k with F(k) >= u, F the
    Poisson(mu/m) CDF summed term by term p_k = (p_{k-1} * mc) * (1/k), with
-   1/k rounded to double. The sum of m independent Poisson(mu/m) variates is
-   Poisson(mu).
+   1/k rounded to double and p_0 = exp(-mc) by or_exp_fixed. The sum of m
+   independent Poisson(mu/m) variates is Poisson(mu).
    *margin receives min over chunks of |u - F(k)| at the accepted k and at
    k-1 (how close the decision was). */
 #define OR_POISSON_CHUNK 128.0
@@ -248,7 +284,7 @@ uint32_t or_poisson(double mu, uint64_t seed, uint32_t idx, uint32_t shower, dou
     double u[4];
     draw4(seed, c, idx, shower, OR_DOM_COUNT, u, 0);
     uint32_t k = 0;
-    double p = exp(-mc);
+    double p = or_exp_fixed(-mc);
     double F = p, Fprev = 0.0;
     while (u[0] > F && k < OR_POISSON_KMAX) {
       k += 1;

@@ -71,6 +71,8 @@ def lib():
         L.or_uniform.argtypes = [C.c_uint32]
         L.or_uniform.restype = C.c_double
         L.or_atm_prepare.argtypes = [P]
+        L.or_exp_fixed.argtypes = [C.c_double]
+        L.or_exp_fixed.restype = C.c_double
         L.or_density.argtypes = [P, C.c_double]
         L.or_density.restype = C.c_double
         L.or_index.argtypes = [P, C.c_double]
@@ -202,6 +204,12 @@ def philox(ctr: np.ndarray, key) -> np.ndarray:
     for i in range(ctr.shape[0]):
         L.or_philox(ctr[i].ctypes.data, k.ctypes.data, out[i].ctypes.data)
     return out
+
+
+def exp_fixed(x) -> np.ndarray:
+    """The specified exp of the count path (or_exp_fixed), elementwise."""
+    f = lib().or_exp_fixed
+    return np.array([f(float(v)) for v in np.ravel(x)], np.float64).reshape(np.shape(x))
 
 
 def uniform(x) -> np.ndarray:

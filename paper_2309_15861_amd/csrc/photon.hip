@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
     m = poisson_chunks(mu);
     if (m) {
       mc = mu / (double)m;
-      p0 = exp(-mc);
+      p0 = exp_fixed(-mc);
     }
     idx = seg_idx(seg, i);
     sh = seg_shower(seg, i);
@@ -1578,7 +1578,8 @@ int prep_atm(const photon_atmosphere* a, AtmDev* d) {
     if (std::isinf(a->scale_height[k]) && i < a->n_layers) d->homog_mask |= 1 << i;
   }
   d->rb[0] = 1.0;
-  for (int i = 0; i + 1 < a->n_layers; ++i) d->rb[i + 1] = d->rb[i] * std::exp(-(a->h_base[i + 1] - a->h_base[i]) / a->scale_height[i]);
+  for (int i = 0; i + 1 < a->n_layers; ++i)
+    d->rb[i + 1] = d->rb[i] * exp_fixed(-(a->h_base[i + 1] - a->h_base[i]) / a->scale_height[i]);
   for (int i = a->n_layers; i < PHOTON_MAX_LAYERS; ++i) d->rb[i] = d->rb[a->n_layers - 1];
   d->eta0 = a->n0_minus_1;
   d->hobs = a->h_obs;

@@ -99,6 +99,41 @@ struct AtmDev {
   double t_fi, t_fj, t_fk;            // nodes per metre of height, per unit of q, per metre (vertical)
 };
 
+// The exponential of the count path (the index at the segment midpoint, the
+// layer base densities it uses, and exp(-mean) of the Poisson draw): a count
+// is an integer decided on these values, and library exp routines differ in
+// the last bit, so every step is fixed here as a sequence of IEEE double
+// operations without contraction that any implementation of the same steps
+// reproduces bit for bit. Argument reduction after Cody and Waite (1980):
+// x = k ln 2 + r with k the nearest integer to x/ln 2 (ties to even) and
+// ln 2 split into a head with 21 trailing zero bits (k ln2_hi exact) and a
+// tail; e^r as its Taylor series through r^13 (|r| <= ln 2 / 2, first
+// omitted term below 5e-18) in Horner form from the highest power with
+// coefficients 1/i! rounded to double; scaled by 2^k. About 1 ulp.
+__host__ __device__ inline double exp_fixed(double x) {
+#pragma clang fp contract(off)
+  if (x != x) return x;
+  if (x > 709.78) return HUGE_VAL;
+  if (x < -745.2) return 0.0;
+  const double k = rint(x * 0x1.71547652b82fep+0);
+  const double r = (x - k * 0x1.62e42fee00000p-1) - k * 0x1.a39ef35793c76p-33;
+  double p = 0x1.6124613a86d09p-33;   // 1/13!
+  p = p * r + 0x1.1eed8eff8d898p-29;  // 1/12!
+  p = p * r + 0x1.ae64567f544e4p-26;  // 1/11!
+  p = p * r + 0x1.27e4fb7789f5cp-22;  // 1/10!
+  p = p * r + 0x1.71de3a556c734p-19;  // 1/9!
+  p = p * r + 0x1.a01a01a01a01ap-16;  // 1/8!
+  p = p * r + 0x1.a01a01a01a01ap-13;  // 1/7!
+  p = p * r + 0x1.6c16c16c16c17p-10;  // 1/6!
+  p = p * r + 0x1.1111111111111p-7;   // 1/5!
+  p = p * r + 0x1.5555555555555p-5;   // 1/4!
+  p = p * r + 0x1.5555555555555p-3;   // 1/3!
+  p = p * r + 0.5;
+  p = p * r + 1.0;
+  p = p * r + 1.0;
+  return ldexp(p, (int)k);
+}
+
 // Layer of height h: the last k with hb[k] <= h (hb is +inf beyond the last
 // layer; layer 0 also extends below hb[0]).
 __device__ __forceinline__ int layer_of(const AtmDev& a, double h) {
@@ -147,7 +182,7 @@ __device__ __forceinline__ double seg_index(const SegView& s, int64_t i, const A
   const double dzh = dz / dn;
   const double zc = s.z0[i] + (0.5 * s.len[i]) * dzh;
   const int l = layer_of(a, zc);
-  const double rho = a.rb[l] * exp(-(zc - a.hb[l]) / a.H[l]);
+  const double rho = a.rb[l] * exp_fixed(-(zc - a.hb[l]) / a.H[l]);
   return 1.0 + a.eta0 * rho;
 }
 
