@@ -350,6 +350,26 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
                      const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
                      const photon_tuning* tuning, void* stream);
 
+/* photon_run_fused for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): same arguments, kernels and results, but it allocates nothing.
+   Its scratch (work cursor, per-block near-horizon counts and their prefix
+   sums, and a queue of 2^20 near-horizon rays: 8.1 MiB) is a static device
+   array that every GPU the library runs on holds until the process ends; its
+   address is looked up once per device (photon_init, else the first call).
+   Limit: the FP32 form queues at most 2^20 / (blocks of the launch)
+   near-horizon rays per block for the double pass; a block that queues more
+   finishes the excess in float and counts it in PHOTON_HORIZON_FLOAT, as
+   photon_run_fused does beyond its 2^24-ray queue. Every call on one GPU
+   works in that GPU's one array and leaves its contents behind (the cursor
+   is cleared at the start of each call): calls that overlap on one GPU, on
+   any streams, race. Errors: as photon_run_fused; PHOTON_EHIP if the
+   array's address cannot be looked up. */
+int photon_run_fused_noalloc(const photon_segments* seg, const photon_atmosphere* atm,
+                             const photon_emission* em, uint64_t seed, int32_t precision,
+                             const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
+                             const photon_tuning* tuning, void* stream);
+
 /* Kernel timing, a measurement aid. With on != 0, every fused launch on the
    current device outside a stream capture (photon_run_fused, the splat
    forward) records a pair of HIP events on its stream around the persistent

@@ -33,6 +33,19 @@
 
 using namespace ph;
 
+// Scratch of photon_run_fused_noalloc, the entry point for callers that cannot
+// allocate: words [0, 8192) hold the work-queue cursor (word 0) and the
+// per-block counts of queued near-horizon rays (from word 64), words
+// [8192, 16384) their prefix sums, and the rest a queue of 2^20 rays
+// (segment row, photon number). 8.1 MiB; every device that runs the entry
+// point holds its own copy until the process ends. Host code never uses this
+// name as an address: it takes each device's address from
+// hipGetSymbolAddress.
+constexpr size_t kScratchAreaWords = 8192;
+constexpr int64_t kScratchDeferRays = 1 << 20;
+constexpr size_t kScratchWords = 2 * kScratchAreaWords + (size_t)kScratchDeferRays;
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
 namespace {
 
 thread_local std::string g_err;
@@ -1883,6 +1896,16 @@ constexpr int64_t kDeferCap = 1 << 24;  // near-horizon rays queued per fused FP
 constexpr int kWorkWords = 8192;         // u64 words of the per-device work area
 constexpr int kDeferCounts = 64;         // offset of the per-block deferred counts
 constexpr int kMaxFusedGrid = kWorkWords - kDeferCounts;
+static_assert(kScratchAreaWords == (size_t)kWorkWords, "the static scratch holds one work area");
+
+// Device memory a fused run works in besides its inputs and outputs.
+struct FusedScratch {
+  unsigned long long* cursor = nullptr;        // work-queue position (one word)
+  unsigned long long* defer_counts = nullptr;  // per block: queued near-horizon rays (kMaxFusedGrid words)
+  unsigned long long* defer_pref = nullptr;    // their exclusive prefix sums (kMaxFusedGrid + 1 words)
+  uint2* defer_q = nullptr;                    // the queue (float form only)
+  int64_t defer_rays = 0;                      // its length
+};
 
 struct DeviceState {
   bool checked = false;
@@ -1906,6 +1929,7 @@ struct DeviceState {
   // kernel launched outside a stream capture
   bool timing = false, timed = false;
   hipEvent_t t_ev[2] = {nullptr, nullptr};
+  unsigned long long* scratch_ptr = nullptr;  // this device's address of the static scratch
 };
 std::mutex g_mu;
 DeviceState g_dev[64];
@@ -1923,16 +1947,49 @@ int current_device(DeviceState** out) {
     d.ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
     d.cu = prop.multiProcessorCount;
     d.lds_per_block = prop.sharedMemPerBlock;
-    if (d.ok && hipMalloc(&d.work, sizeof(unsigned long long) * kWorkWords) != hipSuccess) {
-      d.ok = false;
-      d.work = nullptr;
-      return fail(PHOTON_EHIP, "work area allocation failed");
-    }
-    if (d.ok && hipMemset(d.work, 0, sizeof(unsigned long long) * kWorkWords) != hipSuccess)
-      return fail(PHOTON_EHIP, "work area clear failed");
   }
   if (!d.ok) return fail(PHOTON_ENODEV, "current device is not gfx950");
   *out = &d;
+  return PHOTON_OK;
+}
+
+// The device's work area (work cursor, per-block deferral counts), allocated
+// on first use (not inside a stream capture: photon_init and plan creation
+// allocate it before capturing).
+int ensure_work(DeviceState* dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev->work) return PHOTON_OK;
+  if (hipMalloc(&dev->work, sizeof(unsigned long long) * kWorkWords) != hipSuccess) {
+    dev->work = nullptr;
+    return fail(PHOTON_EHIP, "work area allocation failed");
+  }
+  if (hipMemset(dev->work, 0, sizeof(unsigned long long) * kWorkWords) != hipSuccess) {
+    (void)hipFree(dev->work);
+    dev->work = nullptr;
+    return fail(PHOTON_EHIP, "work area clear failed");
+  }
+  return PHOTON_OK;
+}
+
+// This device's address of the static scratch (looked up once per device,
+// with the device current). Allocates nothing.
+int static_scratch(DeviceState* dev, FusedScratch* ws) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!dev->scratch_ptr) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(PHOTON_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      dev->scratch_ptr = (unsigned long long*)p;
+    }
+  }
+  unsigned long long* base = dev->scratch_ptr;
+  ws->cursor = base;
+  ws->defer_counts = base + kDeferCounts;
+  ws->defer_pref = base + kScratchAreaWords;
+  ws->defer_q = (uint2*)(base + 2 * kScratchAreaWords);
+  ws->defer_rays = kScratchDeferRays;
   return PHOTON_OK;
 }
 
@@ -2080,10 +2137,27 @@ int ensure_defer_queue(DeviceState* dev) {
   return PHOTON_OK;
 }
 
+// The device's own fused scratch: the work area and, for the float form, the
+// deferral queue of kDeferCap rays, both allocated on first use.
+int device_scratch(DeviceState* dev, bool defer, FusedScratch* ws) {
+  int rc;
+  if ((rc = ensure_work(dev))) return rc;
+  if (defer && (rc = ensure_defer_queue(dev))) return rc;
+  ws->cursor = dev->work;
+  ws->defer_counts = dev->work + kDeferCounts;
+  ws->defer_pref = dev->defer_pref;
+  ws->defer_q = dev->defer_q;
+  ws->defer_rays = defer ? kDeferCap : 0;
+  return PHOTON_OK;
+}
+
+// Launches the fused kernel (and, in the float form, the near-horizon double
+// pass) working in `scratch`, or in the device's own scratch when it is NULL.
 template <typename T, int BS, bool SPLAT = false>
 int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                     const uint64_t* offsets, int64_t n_ph, int64_t chunk, int bpc, const SinkDev& sk,
-                    DeviceState* dev, hipStream_t st, size_t dyn_lds = 0, const ZeroList* pre = nullptr) {
+                    DeviceState* dev, hipStream_t st, size_t dyn_lds = 0, const ZeroList* pre = nullptr,
+                    const FusedScratch* scratch_in = nullptr) {
   const bool radial = !SPLAT && sk.kind == PHOTON_SINK_RADIAL;
   const bool table = !SPLAT && atm.tcorr != nullptr;
   const int mode = SPLAT ? kMSplat
@@ -2100,8 +2174,11 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   }
   if (grid > kMaxFusedGrid) grid = kMaxFusedGrid;
   const bool defer = sizeof(T) == 4;
-  if (defer) {
-    const int rc = ensure_defer_queue(dev);
+  FusedScratch ws;
+  if (scratch_in) {
+    ws = *scratch_in;
+  } else {
+    const int rc = device_scratch(dev, defer, &ws);
     if (rc) return rc;
   }
   FusedArgs A;
@@ -2115,15 +2192,15 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   A.n_ph = n_ph;
   A.chunk = chunk;
   A.sk = sk;
-  A.cursor = dev->work;
-  A.defer_counts = dev->work + kDeferCounts;
-  A.defer_q = dev->defer_q;
-  A.defer_cap = defer ? kDeferCap / grid : 0;
-  A.defer_pref = dev->defer_pref;
+  A.cursor = ws.cursor;
+  A.defer_counts = ws.defer_counts;
+  A.defer_q = ws.defer_q;
+  A.defer_cap = defer ? ws.defer_rays / grid : 0;
+  A.defer_pref = ws.defer_pref;
   A.n_defer_blocks = (int32_t)grid;
   // the work cursor, with whatever the caller asked to clear before the kernel
   ZeroList z = pre ? *pre : ZeroList{};
-  z.add(dev->work, 1);
+  z.add(ws.cursor, 1);
   launch_zero_list(z, st);
   void* kargs[] = {&A};
   bool timed = false;
@@ -2141,7 +2218,7 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   }
   if (defer) {
     hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
-                       (int)grid, A.defer_cap, dev->defer_pref);
+                       (int)grid, A.defer_cap, A.defer_pref);
     hipLaunchKernelGGL((k_fused_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A);
   }
   return check_launch();
@@ -2150,7 +2227,8 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
 template <typename T>
 int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParams& g, uint64_t seed,
                  const uint64_t* offsets, int64_t n_ph, const photon_tuning* tun, const SinkDev& sk,
-                 DeviceState* dev, hipStream_t st, const ZeroList* pre = nullptr) {
+                 DeviceState* dev, hipStream_t st, const ZeroList* pre = nullptr,
+                 const FusedScratch* ws = nullptr) {
   int bs = tun ? tun->block : 256;
   int64_t chunk = tun ? tun->chunk : 4096;
   int bpc = tun ? tun->blocks_per_cu : 0;
@@ -2159,9 +2237,9 @@ int launch_fused(const SegView& sv, int64_t n, const AtmDev& atm, const GenParam
     return fail(PHOTON_EINVAL, "tuning.chunk must be a multiple of block, at most %d", kMaxChunk);
   if (bpc < 0) return fail(PHOTON_EINVAL, "tuning.blocks_per_cu must be >= 0");
   switch (bs) {
-    case 128: return launch_fused_bs<T, 128>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre);
-    case 512: return launch_fused_bs<T, 512>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre);
-    default: return launch_fused_bs<T, 256>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre);
+    case 128: return launch_fused_bs<T, 128>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre, ws);
+    case 512: return launch_fused_bs<T, 512>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre, ws);
+    default: return launch_fused_bs<T, 256>(sv, n, atm, g, seed, offsets, n_ph, chunk, bpc, sk, dev, st, 0, pre, ws);
   }
 }
 
@@ -2227,7 +2305,7 @@ ZeroList sink_zero_list(const SinkDev& sk) {
 }
 
 int enqueue_fused(const StepArgs& a, const uint64_t* offsets, int64_t n_ph, const photon_tuning* tun,
-                  DeviceState* dev, hipStream_t st, const ZeroList* pre = nullptr) {
+                  DeviceState* dev, hipStream_t st, const ZeroList* pre = nullptr, const FusedScratch* ws = nullptr) {
   if (a.n == 0 || n_ph == 0) {
     if (pre) {
       launch_zero_list(*pre, st);
@@ -2236,8 +2314,8 @@ int enqueue_fused(const StepArgs& a, const uint64_t* offsets, int64_t n_ph, cons
     return PHOTON_OK;
   }
   return a.precision == PHOTON_FP64
-             ? launch_fused<double>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st, pre)
-             : launch_fused<float>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st, pre);
+             ? launch_fused<double>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st, pre, ws)
+             : launch_fused<float>(a.sv, a.n, a.ad, a.g, a.seed, offsets, n_ph, tun, a.sk, dev, st, pre, ws);
 }
 
 // One whole step: counts + offsets, cleared outputs, fused kernel.
@@ -2349,7 +2427,8 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
   int rc;
   if ((rc = ensure_adj_partials(dev))) return rc;
   constexpr bool defer = sizeof(T) == 4;
-  if (defer && (rc = ensure_defer_queue(dev))) return rc;
+  FusedScratch ws;
+  if ((rc = device_scratch(dev, defer, &ws))) return rc;
   if (c.n > 0) {
     const unsigned zb = (unsigned)std::min<int64_t>(ceil_div(c.n, 256), 4096);
     hipLaunchKernelGGL(k_zero64_n, dim3(zb), dim3(256), 0, st, (unsigned long long*)gdx, c.n);
@@ -2376,18 +2455,18 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
     A.gdy = gdy;
     A.gdz = gdz;
     A.partials = dev->adj_part;
-    A.cursor = dev->work;
-    A.defer_counts = dev->work + kDeferCounts;
-    A.defer_q = dev->defer_q;
-    A.defer_cap = defer ? kDeferCap / grid : 0;
-    A.defer_pref = dev->defer_pref;
+    A.cursor = ws.cursor;
+    A.defer_counts = ws.defer_counts;
+    A.defer_q = ws.defer_q;
+    A.defer_cap = defer ? ws.defer_rays / grid : 0;
+    A.defer_pref = ws.defer_pref;
     A.n_defer_blocks = (int32_t)grid;
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev->work, 1);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, ws.cursor, 1);
     hipLaunchKernelGGL((k_splat_adjoint<T, BS>), dim3((unsigned)grid), dim3(BS), 0, st, A);
     nb = (int)grid;
     if (defer) {
       hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
-                         (int)grid, A.defer_cap, dev->defer_pref);
+                         (int)grid, A.defer_cap, A.defer_pref);
       hipLaunchKernelGGL((k_splat_adjoint_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A, grid);
       nb = 2 * (int)grid;
     }
@@ -2412,7 +2491,11 @@ const char* photon_last_error(void) { return g_err.c_str(); }
 
 int photon_init(void) {
   DeviceState* d;
-  return current_device(&d);
+  int rc;
+  if ((rc = current_device(&d))) return rc;
+  if ((rc = ensure_work(d))) return rc;
+  FusedScratch ws;
+  return static_scratch(d, &ws);
 }
 
 int photon_gen_cherenkov(const photon_segments* seg, const photon_atmosphere* atm, double lambda_min_nm,
@@ -2488,6 +2571,24 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm, c
   return enqueue_fused(a, offsets, n_photons, tuning, dev, (hipStream_t)stream);
 }
 
+int photon_run_fused_noalloc(const photon_segments* seg, const photon_atmosphere* atm, const photon_emission* em,
+                             uint64_t seed, int32_t precision, const uint64_t* offsets, int64_t n_photons,
+                             const photon_sink* sink, const photon_tuning* tuning, void* stream) {
+  StepArgs a;
+  int rc;
+  if ((rc = prep_step(seg, atm, em, seed, precision, sink, tuning, &a))) return rc;
+  if (!offsets) return fail(PHOTON_EINVAL, "offsets is NULL");
+  if (n_photons < -1) return fail(PHOTON_EINVAL, "n_photons must be >= 0, or -1 (total read on the device)");
+  if (sink->kind == PHOTON_SINK_PLANE && n_photons > sink->plane->capacity)
+    return fail(PHOTON_ECAPACITY, "n_photons = %lld exceeds the plane capacity %lld", (long long)n_photons,
+                (long long)sink->plane->capacity);
+  DeviceState* dev;
+  if ((rc = current_device(&dev))) return rc;
+  FusedScratch ws;
+  if ((rc = static_scratch(dev, &ws))) return rc;
+  return enqueue_fused(a, offsets, n_photons, tuning, dev, (hipStream_t)stream, nullptr, &ws);
+}
+
 int photon_kernel_timing(int32_t on) {
   DeviceState* dev;
   int rc;
@@ -2524,7 +2625,8 @@ int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm,
   DeviceState* dev;
   if ((rc = current_device(&dev))) return rc;
   warm_occupancy(dev);
-  if (precision == PHOTON_FP32 && (rc = ensure_defer_queue(dev))) return rc;
+  FusedScratch ws;
+  if ((rc = device_scratch(dev, precision == PHOTON_FP32, &ws))) return rc;
   hipStream_t cs;
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   photon_plan_s* p = new photon_plan_s;

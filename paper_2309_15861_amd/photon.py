@@ -112,6 +112,7 @@ def lib():
         L.photon_propagate.argtypes = [P, P, P]
         L.photon_collect.argtypes = [P, P, P, P]
         L.photon_run_fused.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, C.c_int64, P, P, P]
+        L.photon_run_fused_noalloc.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, C.c_int64, P, P, P]
         L.photon_plan_create.argtypes = [P, P, P, C.c_uint64, C.c_int32, P, P, P, P, P]
         L.photon_plan_launch.argtypes = [P, P]
         L.photon_plan_destroy.argtypes = [P]
@@ -127,7 +128,7 @@ def lib():
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
-                  "photon_run_fused", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
+                  "photon_run_fused", "photon_run_fused_noalloc", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
                   "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward",
                   "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms"):
             getattr(L, f).restype = C.c_int
@@ -489,6 +490,16 @@ def run_fused(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precisio
     _check(lib().photon_run_fused(C.byref(s), C.byref(atm), C.byref(em), int(seed), int(precision),
                                   _ptr(offsets), int(n_photons), C.byref(sink),
                                   None if tuning is None else C.byref(tuning), _stream()))
+
+
+def run_fused_noalloc(seg: DeviceSegments, atm: Atmosphere, em: Emission, seed, precision, offsets, n_photons,
+                      sink: Sink, tuning: Tuning | None = None):
+    """run_fused working in the library's static device scratch: the call
+    allocates nothing (photon_run_fused_noalloc)."""
+    s = seg.struct()
+    _check(lib().photon_run_fused_noalloc(C.byref(s), C.byref(atm), C.byref(em), int(seed), int(precision),
+                                          _ptr(offsets), int(n_photons), C.byref(sink),
+                                          None if tuning is None else C.byref(tuning), _stream()))
 
 
 def kernel_timing(on: bool):

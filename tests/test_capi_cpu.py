@@ -319,3 +319,27 @@ def test_table_validation(ph):
     seg = _fake_segments(ph)
     assert _gen(ph, seg, a2) == ph.EINVAL
     assert b"not built for this atmosphere" in L.photon_last_error()
+
+
+def test_noalloc_entry_validates_like_run_fused(ph):
+    """photon_run_fused_noalloc checks its arguments exactly as
+    photon_run_fused does, before any device work."""
+    L = ph.lib()
+    atm = _valid_atm(ph)
+    seg = _fake_segments(ph)
+    em = ph.emission_cherenkov()
+    sink = ph.Sink()
+    sink.kind = ph.SINK_STATUS
+    for fn in (L.photon_run_fused, L.photon_run_fused_noalloc):
+        t = ph.tuning(100, 400, 0)
+        assert fn(C.byref(seg), C.byref(atm), C.byref(em), 1, 1, 0x3000, -1, C.byref(sink), C.byref(t),
+                  None) == ph.EINVAL
+        assert fn(C.byref(seg), C.byref(atm), C.byref(em), 1, 1, None, -1, C.byref(sink), None,
+                  None) == ph.EINVAL
+        assert fn(C.byref(seg), C.byref(atm), C.byref(em), 1, 1, 0x3000, -2, C.byref(sink), None,
+                  None) == ph.EINVAL
+        assert fn(C.byref(seg), C.byref(atm), C.byref(em), 1, 7, 0x3000, -1, C.byref(sink), None,
+                  None) == ph.EINVAL
+        if not torch.cuda.is_available():
+            assert fn(C.byref(seg), C.byref(atm), C.byref(em), 1, 1, 0x3000, -1, C.byref(sink), None,
+                      None) == ph.ENODEV
