@@ -91,6 +91,51 @@ def check_propagated(g, ref, tol, mask=None):
     assert dp.max() <= max(tol["land"], 1e-9)
 
 
+def grid_bounds(ref, g, tol, wtol):
+    """Per-cell bounds of a ground grid from the oracle's photons: the count
+    and weight of photons whose landing point is farther than the landing
+    tolerance from every cell edge (they must land in the oracle's cell), and
+    of the photons within it, which may land in any cell they touch (or off
+    the grid). tol and wtol are the landing (relative to the displacement)
+    and the relative weight tolerance, per photon."""
+    nx, ny, cell = g["nx"], g["ny"], g["cell"]
+    landed = ref["status"] == O.LANDED
+    scale = np.maximum(np.hypot(ref["xl"] - ref["xe"], ref["yl"] - ref["ye"]), 1.0)
+    t = tol * scale
+    ix = [np.floor((ref["xl"] + sgn * t - g["x_min"]) / cell).astype(np.int64) for sgn in (-1, 1)]
+    iy = [np.floor((ref["yl"] + sgn * t - g["y_min"]) / cell).astype(np.int64) for sgn in (-1, 1)]
+    w = ref["weight"]
+    certain = landed & (ix[0] == ix[1]) & (iy[0] == iy[1])
+    inside = certain & (ix[0] >= 0) & (ix[0] < nx) & (iy[0] >= 0) & (iy[0] < ny)
+    c = (iy[0] * nx + ix[0])[inside]
+    cnt = np.bincount(c, minlength=nx * ny)
+    wsum = np.bincount(c, weights=w[inside], minlength=nx * ny)
+    wdev = np.bincount(c, weights=(w * wtol)[inside], minlength=nx * ny)
+    amb_cnt = np.zeros(nx * ny, np.int64)
+    amb_w = np.zeros(nx * ny)
+    amb = np.nonzero(landed & ~certain)[0]
+    for q in amb:
+        cells = {(a, b) for a in (ix[0][q], ix[1][q]) for b in (iy[0][q], iy[1][q])
+                 if 0 <= a < nx and 0 <= b < ny}
+        for a, b in cells:
+            amb_cnt[b * nx + a] += 1
+            amb_w[b * nx + a] += w[q] * (1.0 + wtol[q])
+    return cnt, wsum, wdev, amb_cnt, amb_w, len(amb)
+
+
+def check_grid(gcount, gweight, bounds):
+    """GPU grid against grid_bounds, cell by cell. Weights are sums of
+    photon weights rounded to units of 2^-32."""
+    cnt, wsum, wdev, amb_cnt, amb_w, n_amb = bounds
+    gcount = gcount.astype(np.int64)
+    assert np.all(gcount >= cnt), f"cell below the oracle's certain count by {(cnt - gcount).max()}"
+    assert np.all(gcount <= cnt + amb_cnt), f"cell above its certain + edge photons by {(gcount - cnt - amb_cnt).max()}"
+    gw = gweight.astype(np.float64) / 2**32
+    fix = gcount * 2.0**-33 + 1e-12 * np.maximum(gw, wsum)
+    assert np.all(gw >= wsum - wdev - fix), f"cell weight low by {(wsum - wdev - fix - gw).max():.3e}"
+    assert np.all(gw <= wsum + wdev + amb_w + fix), f"cell weight high by {(gw - wsum - wdev - amb_w - fix).max():.3e}"
+
+
 # ------------------------------------------------------------------ counts --
 @pytest.mark.parametrize("name", ["plain", "shower", "fluor", "ragged"])
 def test_counts_bit_exact(name):
@@ -266,19 +311,14 @@ def test_grid_matches_oracle(fluor_run):
             blk, _, _ = run_block(d, atm, em, 3, prec, offsets, total)
             ph.collect(blk, atm, sink)
         torch.cuda.synchronize()
-        gcount = gc.cpu().numpy()
-        # photons within tolerance of a cell edge may fall on either side
-        lx = (ref["xl"] - g["x_min"]) / g["cell"]
-        ly = (ref["yl"] - g["y_min"]) / g["cell"]
-        scale = np.maximum(np.hypot(ref["xl"] - ref["xe"], ref["yl"] - ref["ye"]), 1.0) / g["cell"]
-        tol = (1e-9 if prec == ph.FP64 else 1e-5) * scale
-        edge = (np.abs(lx - np.round(lx)) < tol) | (np.abs(ly - np.round(ly)) < tol)
-        n_edge = int((edge & (ref["status"] == O.LANDED)).sum())
-        assert np.abs(gcount.astype(np.int64) - hist).sum() <= 2 * n_edge
-        gwsum = gw.cpu().numpy().astype(np.float64) / 2**32
-        assert np.abs(gwsum - wsum).sum() <= 2 * n_edge + 1e-5 * wsum.sum()
+        # per cell; photons within the landing tolerance of a cell edge may fall on either side
+        tol = TOL64 if prec == ph.FP64 else TOL32
+        bounds = grid_bounds(ref, g, tol["land"], tol["w"] + tol["w_tau"] * ref["tau"])
+        check_grid(gc.cpu().numpy(), gw.cpu().numpy(), bounds)
         tot = totals.cpu().numpy()
         assert tot.sum() == total
+        assert tot[ph.UP] == (ref["status"] == O.UP).sum()
+        assert abs(int(tot[ph.LANDED]) - int(hist.sum())) <= bounds[5]
 
 
 def test_fused_launch_shapes_agree(plain_run):
