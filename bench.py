@@ -1,16 +1,27 @@
 #!/usr/bin/env python3
-"""Photons propagated per second on one MI355X.
+"""Photons propagated per second on one MI355X: FP32-split vs FP64, batched.
 
-Workload: shower-shaped Cherenkov input (2e5 electron segments following a
-1 TeV gamma longitudinal profile, E^-2 energies from 20 MeV, lateral
-sigma 50 m, zenith 20 deg), five-layer exponential atmosphere with
-wavelength-dependent absorption, 16 telescope spheres (R = 6 m, 100 m grid)
-at 2.2 km. One step = the whole hot path on resident inputs: per-segment
-counts and offsets, clearing the outputs, and the fused persistent kernel
-(generation, propagation, telescope collection). The headline value is the
-FP32-bulk form (float generation and bending, double time and path); the
-plain FP64 form is timed beside it. The FP64 CPU oracle is timed on the
-host's cores over the same workload.
+Headline workload: 64 showers in one persistent launch (segment counts
+log-uniform 1e3..1e6 per shower, zenith 0..60 deg, electron segments 5..30 km
+with directions within 5 deg of the shower axis, energies log-uniform
+50 MeV..1 GeV; 1.38e7 segments, 2.3e9 photons), five-layer exponential
+atmosphere with wavelength-dependent absorption, 16 telescope spheres
+(R = 6 m, 100 m grid) at 2.2 km. One step = the whole hot path on resident
+inputs, replayed from a captured graph: per-segment counts and offsets,
+clearing of the outputs, the fused persistent kernel (generation,
+propagation, telescope collection) and the near-horizon double pass. The
+launch shape comes from the library's autotuner. The headline value is the
+FP32-split form (float generation and bending, double time and path); the
+plain FP64 form of the same step is timed beside it.
+
+Also reported: the shower workload (2e5 segments) in both forms, the plain
+FP64 Cherenkov workload through the materialised photon block (count,
+generate, propagate: HBM-bound), the fluorescence workload on its 64 x 64
+ground grid in both forms, the angular cut, the correction-table
+propagation, radial profiles, fluorescence beaming and the differentiable
+form. Every timed form carries its largest error against the FP64 oracle on
+a sample of its photons. The oracle itself is timed on the host's cores
+(all of them and one) on a sample of the headline workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -20,6 +31,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -29,17 +41,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9          # VALU lane-slots/s: CUs x SIMDs x lanes x clock
+PEAK_HBM = 8.0e12                          # B/s
 # Algorithmic VALU issue slots per photon (quarter-rate operations count 4):
 # Philox4x32-10 (10 rounds of two 32x32->64 multiplies and two 3-way xors,
 # ~100-120), uniforms (~8), cone/rotation/translation/wavelength (~30),
 # propagation over ~2 layer pieces (~90), absorption (~15), telescope
-# selection and hit test (~30).
+# selection and hit test (~30). The double form is priced at 750 (its
+# transcendentals are instruction sequences).
 SLOTS_PER_PHOTON = {"fp32": 300.0, "fp64": 750.0}
-PMC_FILE = os.path.join(ROOT, "profiles", "fused_shower_fp32_traffic.json")
+# Algorithmic HBM bytes per photon of the materialised FP64 path: the
+# generator writes x, y, ux, uy, uz, lambda, w, z, t, path (f64), segment, j
+# (u32) and status (i32) = 92 B; propagation reads 84 B (all but segment and
+# j) and writes 76 B (all but segment, j and lambda). The propagated block is
+# the observation-plane output in slot order.
+BLOCK_BYTES = {"gen": 92.0, "propagate": 160.0}
+COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
 # launch shapes the autotuner chooses from: (block, chunk, blocks per CU; 0 = as many as fit)
-FP32_TUNING = "256,3072,0"
 TUNING_CANDIDATES = [(256, 3072, 0), (256, 4096, 0), (256, 8192, 0), (256, 16384, 0), (512, 8192, 0),
                      (512, 16384, 0), (128, 4096, 0), (256, 8192, 2)]
+SHOWER_FP32_TUNING = (256, 3072, 0)   # fastest on the shower workload in repeated sweeps
 
 
 def source_hash() -> str:
@@ -50,100 +70,373 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per fused launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel source."""
+def counters(key):
+    """Counter figures of one kernel and workload from the committed
+    rocprofv3 runs, if they were taken on the current kernel source."""
     try:
-        with open(PMC_FILE) as fh:
+        with open(COUNTERS) as fh:
             d = json.load(fh)
     except OSError:
         return None
     if d.get("source_hash") != source_hash():
         return None
-    return d.get("bytes_per_launch")
+    return d.get("kernels", {}).get(key)
 
 
-def cpu_baseline(seg, atm_dict, tel, seed, max_threads=16):
-    """The FP64 oracle on the host: counts, photon generation + propagation
-    and telescope test for every segment, in batches of 20000 segments."""
-    import numpy as np
-
-    import oracle.oracle as O
-    from paper_2309_15861_amd import workloads as W
-
-    threads = max(1, min(max_threads, len(os.sched_getaffinity(0))))
-    O.set_threads(threads)
-    oatm = O.Atmosphere.from_dict(atm_dict)
-    n_obs = oatm.index(atm_dict["h_obs"])
-    n = len(seg["x0"])
-    photons = 0
-    t0 = time.perf_counter()
-    for b0 in range(0, n, 20000):
-        sub = W.subsample(seg, np.arange(b0, min(n, b0 + 20000)))
-        cnt = O.counts(sub, oatm, "cherenkov", seed)[0]
-        off = O.offsets_of(cnt)
-        ph = O.photons_all(sub, oatm, "cherenkov", seed, off)
-        O.telescopes(ph, tel, n_obs)
-        photons += int(off[-1])
-    dt = time.perf_counter() - t0
-    return dict(value=photons / dt, unit="photons/s", cores=O.num_threads(), kind="oracle",
-                sample=f"all {n} segments ({photons} photons) in batches of 20000 segments; "
-                       f"counts + generation + quadrature propagation + telescope test; {dt:.1f} s")
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model or platform.processor(), nproc=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0)), omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
 
 
-def batched_showers(args):
-    """64 showers (segment counts log-uniform 1e3..1e6, zenith 0..60 deg) in
-    one graph-captured step, FP32 bulk, telescope sink per shower core."""
+def host_threads():
+    """Threads the host share allows: the CPUs this process may run on,
+    limited by OMP_NUM_THREADS when it is set."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+# ------------------------------------------------------------------ timing --
+def time_steps(fn, steps, warmup):
+    """ms per call of fn (which enqueues on the current stream), HIP events
+    around `steps` calls after `warmup` untimed ones."""
     import torch
-
-    from paper_2309_15861_amd import photon as ph
-    from paper_2309_15861_amd import workloads as W
-
-    seg = W.batched_showers(seed=4)
-    a = W.default_atmosphere(absorption=True)
-    d = ph.DeviceSegments(seg)
-    atm = ph.atmosphere(a)
-    em = ph.emission_cherenkov(300.0, 600.0)
-    counts = torch.empty(d.n, dtype=torch.int32, device="cuda")
-    offsets = torch.empty(d.n + 1, dtype=torch.int64, device="cuda")
-    ph.gen_cherenkov(d, atm, 300.0, 600.0, 4, ph.FP64, counts, offsets)
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
-    total = int(offsets[-1].item())
-    hits = ph.HitBuffer(1 << 22)       # hits beyond the capacity are still counted in the totals
-    totals = ph.status_totals()
-    sink = ph.sink_telescopes(W.telescopes_16(), hits, totals)
-    best, _ = ph.autotune(d, atm, em, 4, ph.FP32, offsets, sink, TUNING_CANDIDATES, reps=2)
-    plan = ph.Plan(d, atm, em, 4, ph.FP32, counts, offsets, sink, best)
-    plan.launch()
-    torch.cuda.synchronize()
-    steps = max(2, args.steps // 4)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        plan.launch()
+        fn()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    tot = totals.cpu().numpy()
-    assert int(tot[:7].sum()) == total
-    plan.close()
-    return dict(workload="64 showers, segments log-uniform 1e3..1e6 per shower, zenith 0..60 deg",
-                segments=d.n, photons=total, hits=int(tot[ph.HIT]), ms_per_step=ms,
-                photons_per_s=total / (ms * 1e-3),
-                precision="fp32 bulk, fp64 time/path", steps=steps,
-                tuning=[best.block, best.chunk, best.blocks_per_cu])
+    return e0.elapsed_time(e1) / steps
+
+
+def kernel_times(d, atm, em, seed, prec, offsets, sink, tun, reps):
+    """Mean time of the persistent kernel alone and of the near-horizon
+    double pass after it (the library's HIP events on the kernel's stream)."""
+    from paper_2309_15861_amd import photon as ph
+    ph.kernel_timing(True)
+    k, dfr = [], []
+    for _ in range(reps):
+        ph.run_fused(d, atm, em, seed, prec, offsets, -1, sink, tun)
+        k.append(ph.fused_kernel_ms())
+        dfr.append(ph.fused_deferred_ms())
+    ph.kernel_timing(False)
+    return float(np.mean(k)), float(np.mean(dfr))
+
+
+def alu_roofline(kernel, key, form, photons, kernel_ms, deferred_ms, tun):
+    """Roofline object of a fused kernel: algorithmic lane-slots per photon
+    over the kernel's mean launch time, against the VALU issue peak; the
+    measured VALU instruction rate and HBM bytes from the committed counters
+    when they match the current source."""
+    achieved = SLOTS_PER_PHOTON[form] * photons / (kernel_ms * 1e-3)
+    r = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+             frac=achieved / PEAK_SLOTS, traffic=None, kernel=kernel, slots_per_photon=SLOTS_PER_PHOTON[form],
+             photons_per_launch=photons, kernel_ms=kernel_ms, deferred_pass_ms=deferred_ms,
+             tuning=[tun.block, tun.chunk, tun.blocks_per_cu])
+    c = counters(key)
+    if c:
+        r["traffic"] = c["fetch_bytes"] + c["write_bytes"]
+        r["measured"] = dict(valu_lane_instr_per_photon=c["valu_per_photon"],
+                             salu_per_photon=c["salu_per_photon"],
+                             valu_issue_frac=c["valu_per_photon"] * photons / (kernel_ms * 1e-3) / PEAK_SLOTS,
+                             profiled_kernel_ms=c["avg_ns"] * 1e-6,
+                             hbm_bytes_per_photon=(c["fetch_bytes"] + c["write_bytes"]) / photons)
+    return r
+
+
+# ------------------------------------------------------- errors vs oracle --
+def photon_errors(g, ref, ok=None):
+    """Largest errors of GPU photons g against the oracle's ref, over photons
+    both call landed: landing |dr| / max(|r_land - r_emit|, 1 m), arrival
+    time (ns), relative weight, direction (rad)."""
+    import oracle.oracle as O
+    landed = (ref["status"] == O.LANDED) & (g["status"] == O.LANDED)
+    if ok is not None:
+        landed &= ok
+    if not landed.any():
+        return dict(landed=0)
+    r = ref[landed]
+    scale = np.maximum(np.hypot(r["xl"] - r["xe"], r["yl"] - r["ye"]), 1.0)
+    gx = g["x"][landed].astype(np.float64)
+    gy = g["y"][landed].astype(np.float64)
+    u = np.stack([g["ux"][landed], g["uy"][landed], g["uz"][landed]], 1).astype(np.float64)
+    ang = np.arctan2(np.linalg.norm(np.cross(u, r["ul"]), axis=1), (u * r["ul"]).sum(1))
+    return dict(landed=int(landed.sum()),
+                landing_rel=float((np.hypot(gx - r["xl"], gy - r["yl"]) / scale).max()),
+                landing_m=float(np.hypot(gx - r["xl"], gy - r["yl"]).max()),
+                time_ns=float(np.abs(g["t_ns"][landed] - r["tl"]).max()),
+                weight_rel=float((np.abs(g["weight"][landed].astype(np.float64) - r["weight"]) / r["weight"]).max()),
+                direction_rad=float(ang.max()))
+
+
+def sampled_errors(seg, a, kind, em, seed, prec, rows, tun=None, lines=None, atm=None):
+    """The fused kernel's photons of the segments `rows` (ids kept, so they
+    are the photons of the full run) through the plane sink, against the
+    oracle's: counts and statuses compared exactly, the rest by photon_errors."""
+    import torch
+
+    import oracle.oracle as O
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+    sub = W.subsample(seg, rows)
+    d = ph.DeviceSegments(sub)
+    atm = atm if atm is not None else ph.atmosphere(a)
+    counts, offsets = ph.count(d, atm, em, seed)
+    oatm = O.Atmosphere.from_dict(a)
+    ocnt = O.counts(sub, oatm, kind, seed)[0]
+    gcnt = counts.cpu().numpy().view(np.uint32)
+    total = int(offsets[-1].item())
+    plane = ph.PhotonBlock(total, prec)
+    plane.n_photons = total
+    ph.run_fused(d, atm, em, seed, prec, offsets, -1, ph.sink_plane(plane), tun)
+    torch.cuda.synchronize()
+    g = plane.numpy()
+    kw = {} if lines is None else dict(lines_nm=lines[0], line_rel=lines[1])
+    ref = O.photons_all(sub, oatm, kind, seed, O.offsets_of(ocnt), **kw)
+    out = dict(segments=len(rows), photons=total, counts_equal=bool(np.array_equal(gcnt, ocnt)),
+               status_equal=bool(len(g["status"]) == len(ref) and np.array_equal(g["status"], ref["status"])))
+    out.update(photon_errors(g, ref))
+    return out
+
+
+def every_kth(n, target, per_segment):
+    """Every k-th row so that about `target` photons are sampled."""
+    k = max(1, int(n * per_segment / max(target, 1)))
+    return np.arange(0, n, k)
+
+
+# --------------------------------------------------------------- workloads --
+def fused_form(name, seg, a, kind, em, seed, prec, sink_fn, args, tun=None, mode=0):
+    """One workload in one precision: autotuned launch shape (unless given),
+    the whole step captured in a graph and timed, the persistent kernel
+    timed alone at the same shape, the sink's results."""
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    d = ph.DeviceSegments(seg)
+    atm = ph.atmosphere(a)
+    counts, offsets = ph.count(d, atm, em, seed)
+    torch.cuda.synchronize()
+    total = int(offsets[-1].item())
+    sink, outs = sink_fn(total)
+    if tun is None:
+        tun, _ = ph.autotune(d, atm, em, seed, prec, offsets, sink, TUNING_CANDIDATES, reps=3)
+    plan = ph.Plan(d, atm, em, seed, prec, counts, offsets, sink, tun)
+    try:
+        ms = time_steps(plan.launch, args.steps, args.warmup)
+    finally:
+        plan.close()
+    res = dict(photons=total, ms_per_step=ms, photons_per_s=total / (ms * 1e-3),
+               tuning=[tun.block, tun.chunk, tun.blocks_per_cu])
+    res.update(outs())
+    kms, dms = kernel_times(d, atm, em, seed, prec, offsets, sink, tun, max(3, args.steps // 4))
+    form = "fp64" if prec == ph.FP64 else "fp32"
+    kern = f"k_fused<{'double' if prec == ph.FP64 else 'float'}, {tun.block}, {mode}>"
+    res["roofline"] = alu_roofline(kern, f"{kern} {name}", form, total, kms, dms, tun)
+    return res, d, atm, counts, offsets, tun
+
+
+def telescope_sink(tel, capacity_hint=None):
+    from paper_2309_15861_amd import photon as ph
+
+    def make(total):
+        # capacity from the photon total (hits are a few per cent of the photons)
+        hits = ph.HitBuffer(capacity_hint or max(total // 16, 1 << 16))
+        totals = ph.status_totals()
+
+        def outs():
+            tot = totals.cpu().numpy()
+            return dict(hits=hits.count(), hit_capacity=hits.capacity, hits_dropped=max(0, hits.count() - hits.capacity),
+                        status_totals=[int(x) for x in tot])
+        return ph.sink_telescopes(tel, hits, totals), outs
+    return make
+
+
+def grid_sink(g):
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+
+    def make(total):
+        gc = torch.zeros(g["nx"] * g["ny"], dtype=torch.int32, device="cuda")
+        gw = torch.zeros(g["nx"] * g["ny"], dtype=torch.int64, device="cuda")
+        totals = ph.status_totals()
+
+        def outs():
+            tot = totals.cpu().numpy()
+            return dict(on_grid=int(gc.sum().item()), grid_weight=float(gw.double().sum().item()) / 2**32,
+                        status_totals=[int(x) for x in tot])
+        return ph.sink_grid(g["x_min"], g["y_min"], g["cell"], g["nx"], g["ny"], gc, gw, totals), outs
+    return make
+
+
+def batched(args, forms):
+    """The headline workload in the requested forms, with sampled errors."""
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+    seg = W.batched_showers(seed=4)
+    a = W.default_atmosphere(absorption=True)
+    em = ph.emission_cherenkov(300.0, 600.0)
+    tel = W.telescopes_16()
+    out = dict(workload="64 showers in one persistent launch, segments log-uniform 1e3..1e6 per shower, zenith "
+                        "0..60 deg, Cherenkov 300-600 nm, absorption, 16 telescopes R=6 m on a 100 m grid",
+               segments=len(seg["x0"]))
+    for name, prec, tun in forms:
+        r, *_ = fused_form("batched", seg, a, "cherenkov", em, 4, prec, telescope_sink(tel, 1 << 23), args, tun)
+        if not args.no_errors:
+            rows = every_kth(len(seg["x0"]), 2e5, r["photons"] / len(seg["x0"]))
+            r["error_vs_oracle"] = sampled_errors(seg, a, "cherenkov", em, 4, prec, rows,
+                                                  ph.tuning(*r["tuning"]))
+        out[name] = r
+    return out
+
+
+def shower(args):
+    """The shower workload (2e5 segments) in both forms."""
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+    seg = W.shower_cherenkov()
+    a = W.default_atmosphere(absorption=True)
+    em = ph.emission_cherenkov(300.0, 600.0)
+    tel = W.telescopes_16()
+    out = dict(workload="shower-shaped Cherenkov: 2e5 segments, 1 TeV gamma profile, zenith 20 deg, 16 telescopes "
+                        "R=6 m on a 100 m grid, absorption, 300-600 nm", segments=len(seg["x0"]))
+    extra = None
+    for name, prec, tun in (("fp32", ph.FP32, ph.tuning(*SHOWER_FP32_TUNING)), ("fp64", ph.FP64, None)):
+        r, d, atm, counts, offsets, tun = fused_form("shower", seg, a, "cherenkov", em, 2, prec,
+                                                     telescope_sink(tel), args, tun)
+        if not args.no_errors:
+            rows = every_kth(len(seg["x0"]), 2e5, r["photons"] / len(seg["x0"]))
+            r["error_vs_oracle"] = sampled_errors(seg, a, "cherenkov", em, 2, prec, rows, tun)
+        out[name] = r
+        if name == "fp32":
+            extra = (seg, a, d, atm, tel, tun, r)
+    return out, extra
+
+
+def plain_block(args):
+    """The plain FP64 Cherenkov workload (1,000 segments) through the
+    materialised photon block: counts and offsets, generation into the
+    block, propagation in place (the propagated block is the observation
+    plane in slot order). The same path on the shower workload shows the
+    HBM-bound regime: algorithmic bytes per photon over the kernel times."""
+    import torch
+
+    import oracle.oracle as O
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+    a = W.default_atmosphere(absorption=False)
+    out = {}
+    for name, seg, seed, absorb in (("plain", W.plain_cherenkov(), 1, False),
+                                    ("shower_scale", W.shower_cherenkov(), 2, True)):
+        a = W.default_atmosphere(absorption=absorb)
+        d = ph.DeviceSegments(seg)
+        atm = ph.atmosphere(a)
+        em = ph.emission_cherenkov(300.0, 600.0)
+        counts, offsets = ph.count(d, atm, em, seed)
+        torch.cuda.synchronize()
+        total = int(offsets[-1].item())
+        blk = ph.PhotonBlock(total, ph.FP64)
+        blk.n_photons = total
+        c2, o2 = torch.empty_like(counts), torch.empty_like(offsets)
+
+        def step():
+            # the boundary's calls: counts and offsets, the photon block, propagation in place
+            ph.gen_cherenkov(d, atm, 300.0, 600.0, seed, ph.FP64, c2, o2)
+            ph.gen_cherenkov(d, atm, 300.0, 600.0, seed, ph.FP64, c2, o2, blk)
+            ph.propagate(blk, atm)
+        ms = time_steps(step, args.steps, args.warmup)
+        # the two photon kernels alone (each entry point is one kernel on the current stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        g_ms, p_ms = [], []
+        for _ in range(max(3, args.steps // 2)):
+            ev[0].record()
+            ph.generate(d, atm, em, seed, ph.FP64, offsets, blk)
+            ev[1].record()
+            ph.propagate(blk, atm)
+            ev[2].record()
+            torch.cuda.synchronize()
+            g_ms.append(ev[0].elapsed_time(ev[1]))
+            p_ms.append(ev[1].elapsed_time(ev[2]))
+        gms, pms = float(np.mean(g_ms)), float(np.mean(p_ms))
+        bytes_ = (BLOCK_BYTES["gen"] + BLOCK_BYTES["propagate"]) * total
+        r = dict(segments=len(seg["x0"]), photons=total, ms_per_step=ms, photons_per_s=total / (ms * 1e-3),
+                 gen_ms=gms, propagate_ms=pms,
+                 roofline=dict(bound="hbm", achieved=bytes_ / ((gms + pms) * 1e-3) / 1e9, peak=PEAK_HBM / 1e9,
+                               unit="GB/s", frac=bytes_ / ((gms + pms) * 1e-3) / PEAK_HBM,
+                               bytes_per_photon=BLOCK_BYTES["gen"] + BLOCK_BYTES["propagate"],
+                               kernels="k_gen<double> + k_propagate<double>", traffic=None))
+        cg, cp = counters(f"k_gen<double> {name}"), counters(f"k_propagate<double> {name}")
+        if cg and cp:
+            r["roofline"]["traffic"] = cg["fetch_bytes"] + cg["write_bytes"] + cp["fetch_bytes"] + cp["write_bytes"]
+        if not args.no_errors:
+            g = blk.numpy()
+            oatm = O.Atmosphere.from_dict(a)
+            off = offsets.cpu().numpy().view(np.uint64)
+            rows = np.arange(len(seg["x0"])) if name == "plain" else every_kth(len(seg["x0"]), 2e5, total / len(seg["x0"]))
+            sub = W.subsample(seg, rows)
+            ocnt = O.counts(sub, oatm, "cherenkov", seed)[0]
+            gcnt = np.diff(off)[rows].astype(np.uint32)
+            ref = O.photons_all(sub, oatm, "cherenkov", seed, O.offsets_of(ocnt))
+            slots = np.concatenate([np.arange(off[s], off[s + 1]) for s in rows]) if len(rows) else np.zeros(0, int)
+            gs = {k: v[slots] for k, v in g.items()}
+            e = dict(segments=len(rows), photons=len(slots), counts_equal=bool(np.array_equal(gcnt, ocnt)),
+                     status_equal=bool(np.array_equal(gs["status"], ref["status"])))
+            e.update(photon_errors(gs, ref))
+            r["error_vs_oracle"] = e
+        out[name] = r
+        del blk
+        torch.cuda.empty_cache()
+    out["workload"] = ("plain FP64 Cherenkov: 1000 segments 5..30 km within 5 deg of vertical, 50 MeV..1 GeV, "
+                       "plane at 2.2 km, no absorption; and the same materialised path on the 2e5-segment shower")
+    return out
+
+
+def fluorescence_grid(args):
+    """The fluorescence workload (1e5 segments, 1e8 photons) on the 64 x 64
+    ground grid of 10 m cells, FP32 and FP64."""
+    from paper_2309_15861_amd import photon as ph
+    from paper_2309_15861_amd import workloads as W
+    seg = W.fluorescence()
+    a = W.default_atmosphere(absorption=True)
+    lam, rel = W.fluorescence_lines()
+    em = ph.emission_fluor(lam, rel, W.FLUOR_YIELD_PER_MEV)
+    g = W.grid_64()
+    out = dict(workload="fluorescence: 1e5 segments 5..30 km, dE/dx 1..10 MeV/m, 10 photons/MeV, 21 lines, "
+                        "isotropic; 64 x 64 grid of 10 m cells at 2.2 km", segments=len(seg["x0"]))
+    for name, prec in (("fp32", ph.FP32), ("fp64", ph.FP64)):
+        r, *_ = fused_form("fluorescence", seg, a, "fluor", em, 3, prec, grid_sink(g), args, mode=8)
+        if not args.no_errors:
+            rows = every_kth(len(seg["x0"]), 1e6, r["photons"] / len(seg["x0"]))
+            r["error_vs_oracle"] = sampled_errors(seg, a, "fluor", em, 3, prec, rows, ph.tuning(*r["tuning"]),
+                                                  lines=(lam, rel))
+        out[name] = r
+    return out
 
 
 def angular_cut(args, d, atm, tel, seed, best, uncut):
     """The shower step with the Cherenkov angular particle cut at 6 degrees,
     to the array centre and to each telescope: emitting segments, photons and
     hits kept, and the step time against the uncut step (same launch shape)."""
-    import numpy as np
     import torch
 
     from paper_2309_15861_amd import photon as ph
     from paper_2309_15861_amd import workloads as W
-
     em0 = ph.emission_cherenkov(300.0, 600.0)
     emitting0 = int((ph.means(d, atm, em0) > 0).sum().item())
     out = dict(cut_deg=6.0, uncut=dict(emitting_segments=emitting0, photons=uncut["photons"],
@@ -156,20 +449,13 @@ def angular_cut(args, d, atm, tel, seed, best, uncut):
         hits = ph.HitBuffer(max(uncut["photons"] // 8, 1024))
         totals = ph.status_totals()
         plan = ph.Plan(d, atm, em, seed, ph.FP32, counts, offsets, ph.sink_telescopes(tel, hits, totals), best)
-        for _ in range(args.warmup):
-            plan.launch()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            plan.launch()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        try:
+            ms = time_steps(plan.launch, args.steps, args.warmup)
+        finally:
+            plan.close()
         photons = int(offsets[-1].item())
         assert int(totals.cpu().numpy()[:7].sum()) == photons
         nh = hits.count()
-        plan.close()
         out[name] = dict(emitting_segments=emitting, segments_kept_frac=emitting / max(emitting0, 1),
                          photons=photons, photons_kept_frac=photons / uncut["photons"], hits=nh,
                          hits_kept_frac=nh / max(uncut["hits"], 1), ms_per_step=ms,
@@ -185,7 +471,6 @@ def fluorescence_beaming(args, best):
 
     from paper_2309_15861_amd import photon as ph
     from paper_2309_15861_amd import workloads as W
-
     seg = W.fluorescence()
     a = W.default_atmosphere(absorption=True)
     tel = W.telescopes_16()
@@ -201,22 +486,14 @@ def fluorescence_beaming(args, best):
         hits = ph.HitBuffer(1 << 16)
         totals = ph.status_totals()
         plan = ph.Plan(d, atm, em, 3, ph.FP32, counts, offsets, ph.sink_telescopes(tel, hits, totals), best)
-        for _ in range(args.warmup):
-            plan.launch()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            plan.launch()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        try:
+            ms = time_steps(plan.launch, args.steps, args.warmup)
+        finally:
+            plan.close()
         photons = int(offsets[-1].item())
         tot = totals.cpu().numpy()
         assert int(tot[:7].sum()) == photons
-        plan.close()
-        out[name] = dict(photons=photons, hits=int(tot[ph.HIT]), ms_per_step=ms,
-                         photons_per_s=photons / (ms * 1e-3))
+        out[name] = dict(photons=photons, hits=int(tot[ph.HIT]), ms_per_step=ms, photons_per_s=photons / (ms * 1e-3))
     out["photons_kept_frac"] = out["beamed"]["photons"] / out["isotropic"]["photons"]
     out["speedup"] = out["isotropic"]["ms_per_step"] / out["beamed"]["ms_per_step"]
     return out
@@ -226,29 +503,19 @@ def radial_profile(args, d, atm, seed, best):
     """The shower step collected as the radial profiles of section 3.1
     (100 bins uniform in ln r from 1 m to 3 km about the core): step time and
     a few points of the photon density and mean arrival time."""
-    import numpy as np
     import torch
 
     from paper_2309_15861_amd import photon as ph
-    from paper_2309_15861_amd import workloads as W
-
     em = ph.emission_cherenkov(300.0, 600.0)
     prof = ph.RadialProfile(100, 1.0, 3000.0, log_bins=True, t_ref_ns=0.0)
     counts = torch.empty(d.n, dtype=torch.int32, device="cuda")
     offsets = torch.empty(d.n + 1, dtype=torch.int64, device="cuda")
     totals = ph.status_totals()
     plan = ph.Plan(d, atm, em, seed, ph.FP32, counts, offsets, ph.sink_radial(prof, totals), best)
-    for _ in range(args.warmup):
-        plan.launch()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        plan.launch()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    plan.close()
+    try:
+        ms = time_steps(plan.launch, args.steps, args.warmup)
+    finally:
+        plan.close()
     photons = int(offsets[-1].item())
     dens, mt = (x.cpu().numpy() for x in ph.radial_profile(prof))
     cnt = prof.count.cpu().numpy()
@@ -263,14 +530,14 @@ def radial_profile(args, d, atm, seed, best):
                 peak_density_r_m=float(mid[int(np.argmax(dens))]))
 
 
-def table_propagation(args, d, atm, tel, seed, best, exact_ms):
+def table_propagation(args, seg, a, d, atm, tel, seed, best, exact_ms):
     """The shower step with the straight-line propagation and tabulated
     refraction corrections of section 2 (257 x 257 nodes up to 40 km and
-    80 degrees, FP32): step time against the exact closed forms."""
+    80 degrees, FP32): step time against the exact closed forms, and the
+    method's error against the exact FP64 oracle on sampled photons."""
     import torch
 
     from paper_2309_15861_amd import photon as ph
-
     tab = ph.PropagationTable(atm)
     atm_t = tab.attach(atm)
     em = ph.emission_cherenkov(300.0, 600.0)
@@ -279,33 +546,31 @@ def table_propagation(args, d, atm, tel, seed, best, exact_ms):
     hits = ph.HitBuffer(1 << 20)
     totals = ph.status_totals()
     plan = ph.Plan(d, atm_t, em, seed, ph.FP32, counts, offsets, ph.sink_telescopes(tel, hits, totals), best)
-    for _ in range(args.warmup):
-        plan.launch()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        plan.launch()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    try:
+        ms = time_steps(plan.launch, args.steps, args.warmup)
+    finally:
+        plan.close()
     photons = int(offsets[-1].item())
-    plan.close()
-    return dict(table="257 x 257 nodes, h_obs..40 km, tan(zenith) 0..tan(80 deg); 4097 vertical nodes",
-                photons=photons, hits=hits.count(), ms_per_step=ms, photons_per_s=photons / (ms * 1e-3),
-                speedup_vs_exact=exact_ms / ms)
+    out = dict(table="257 x 257 nodes, h_obs..40 km, tan(zenith) 0..tan(80 deg); 4097 vertical nodes",
+               photons=photons, hits=hits.count(), ms_per_step=ms, photons_per_s=photons / (ms * 1e-3),
+               speedup_vs_exact=exact_ms / ms)
+    if not args.no_errors:
+        rows = every_kth(len(seg["x0"]), 2e5, photons / len(seg["x0"]))
+        out["error_vs_exact_oracle"] = sampled_errors(seg, a, "cherenkov", em, seed, ph.FP32, rows, best,
+                                                      atm=atm_t)
+    return out
 
 
 def differentiable(args):
     """The differentiable form at 1e6 segments: splatted ground density
     (128 x 128 cells of 5 m, sigma 5 m) with counts frozen at the nominal
     parameters, and its adjoint for L = sum (D - T)^2 with T the density at
-    perturbed parameters; FP32 bulk, FP64 beside it."""
+    perturbed parameters; FP32 bulk, FP64 beside it; the FP32 results'
+    relative difference from the FP64 ones."""
     import torch
 
     from paper_2309_15861_amd import photon as ph
     from paper_2309_15861_amd import workloads as W
-
     seg = W.differentiable()
     a = W.default_atmosphere(absorption=True)
     g = W.splat_grid_128()
@@ -315,33 +580,77 @@ def differentiable(args):
     out = dict(workload="1e6 shower segments, splat 128 x 128 cells of 5 m, sigma 5 m, trunc 4 sigma; "
                         "L = sum (D - T)^2, T at perturbed H, n0-1, directions")
     steps = max(2, args.steps // 4)
+    kept = {}
     for name, prec in (("fp32", ph.FP32), ("fp64", ph.FP64)):
         p = ph.SplatProblem(d, a, 5, prec, g)
         atm0 = ph.atmosphere(a)
         T = ph.splat_forward(d, p.atmosphere(H1, e1), 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, dirs=dirs1)
         D = ph.splat_forward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid)
         G = (2.0 * (D - T)).contiguous()
-        ph.splat_backward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, G)
+        grads = ph.splat_backward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, G)
         torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record()
-        for _ in range(steps):
-            ph.splat_forward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid)
-        ev[1].record()
-        for _ in range(steps):
-            grads = ph.splat_backward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, G)
-        ev[2].record()
-        torch.cuda.synchronize()
+        fwd = time_steps(lambda: ph.splat_forward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid),
+                         steps, 1)
+        bwd = time_steps(lambda: ph.splat_backward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, G),
+                         steps, 1)
         total = int(p.offsets[-1].item())
-        fwd = ev[0].elapsed_time(ev[1]) / steps
-        bwd = ev[1].elapsed_time(ev[2]) / steps
         out["segments"] = d.n
         out["photons"] = total
         out[name] = dict(forward_ms=fwd, backward_ms=bwd, forward_photons_per_s=total / (fwd * 1e-3),
                          backward_photons_per_s=total / (bwd * 1e-3), steps=steps,
                          loss=float(((D - T).double() ** 2).sum()),
                          grad_scale_height=[float(v) for v in grads[0].cpu()], grad_n0_minus_1=float(grads[1]))
+        kept[name] = (D.double().cpu().numpy(), [x.double().cpu().numpy() for x in grads])
+    D32, g32 = kept["fp32"]
+    D64, g64 = kept["fp64"]
+    gdir32 = np.stack(g32[2:5], 1)
+    gdir64 = np.stack(g64[2:5], 1)
+    out["fp32_vs_fp64"] = dict(
+        density_max_abs_over_max=float(np.abs(D32 - D64).max() / np.abs(D64).max()),
+        grad_scale_height_rel=float(np.abs(g32[0] - g64[0]).max() / np.abs(g64[0]).max()),
+        grad_n0_minus_1_rel=float(abs(g32[1] - g64[1]) / abs(g64[1])),
+        grad_direction_rel_norm=float(np.linalg.norm(gdir32 - gdir64) / np.linalg.norm(gdir64)))
     return out
+
+
+def cpu_baseline(seconds_all=12.0, seconds_one=8.0):
+    """The FP64 oracle on the host, on the headline workload: counts,
+    photon generation and quadrature propagation and the telescope test,
+    segment batches of every 53rd segment taken in order until the time
+    budget is spent; on all the threads the host share allows and on one."""
+    import oracle.oracle as O
+    from paper_2309_15861_amd import workloads as W
+    seg = W.batched_showers(seed=4)
+    a = W.default_atmosphere(absorption=True)
+    tel = W.telescopes_16()
+    oatm = O.Atmosphere.from_dict(a)
+    n_obs = oatm.index(a["h_obs"])
+    rows_all = np.arange(0, len(seg["x0"]), 53)
+    res = {}
+    for label, threads, budget in (("all", host_threads(), seconds_all), ("one", 1, seconds_one)):
+        O.set_threads(threads)
+        photons = segs = 0
+        t0 = time.perf_counter()
+        for b0 in range(0, len(rows_all), 4000):
+            sub = W.subsample(seg, rows_all[b0:b0 + 4000])
+            cnt = O.counts(sub, oatm, "cherenkov", 4)[0]
+            off = O.offsets_of(cnt)
+            phs = O.photons_all(sub, oatm, "cherenkov", 4, off)
+            O.telescopes(phs, tel, n_obs)
+            photons += int(off[-1])
+            segs += len(cnt)
+            if time.perf_counter() - t0 > budget:
+                break
+        dt = time.perf_counter() - t0
+        res[label] = dict(photons_per_s=photons / dt, threads=O.num_threads(), photons=photons, segments=segs,
+                          seconds=dt)
+    info = cpu_info()
+    return dict(value=res["all"]["photons_per_s"], unit="photons/s", cores=res["all"]["threads"], kind="oracle",
+                sample=(f"64-shower workload, every 53rd segment in batches of 4000 until the time budget: "
+                        f"{res['all']['segments']} segments ({res['all']['photons']} photons) on "
+                        f"{res['all']['threads']} threads in {res['all']['seconds']:.1f} s; counts + generation + "
+                        f"quadrature propagation + telescope test"),
+                single_thread=res["one"], cpu=info)
 
 
 def main():
@@ -350,27 +659,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true", help="skip the sampled errors against the oracle")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 form (profiling runs)")
-    ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time 64 showers of 1e3..1e6 segments in one graph-captured step")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated sections to run (profiling runs): batched32, batched64, shower, plain, "
+                         "grid, cut, table, radial, beam, adjoint")
     ap.add_argument("--tuning", default=None,
-                    help="block,chunk,blocks_per_cu of the fused kernel for both forms instead of the defaults "
-                         "(profiling runs)")
-    ap.add_argument("--fp32-tuning", default=FP32_TUNING,
-                    help="launch shape of the FP32 form: the fastest on this workload in repeated sweeps of the "
-                         "tuning candidates (a single autotuner pass is within its noise); 'auto' to autotune")
-    ap.add_argument("--cut", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time the shower step with the 6 degree Cherenkov angular particle cut")
-    ap.add_argument("--table", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time the shower step with the straight-line + correction-table propagation")
-    ap.add_argument("--radial", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time the shower step collected as radial density and arrival-time profiles")
-    ap.add_argument("--beam", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time the fluorescence step with isotropic and beamed emission")
-    ap.add_argument("--adjoint", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time the differentiable form (splat forward and adjoint, 1e6 segments)")
+                    help="block,chunk,blocks_per_cu of the headline FP32 step instead of the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -378,11 +674,9 @@ def main():
               "with one all-reduce of the small grids); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2309_15861_amd import photon as ph
-    from paper_2309_15861_amd import workloads as W
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -393,100 +687,56 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
         return
-    seed = 2
-    seg = W.shower_cherenkov()
-    a = W.default_atmosphere(absorption=True)
-    tel = W.telescopes_16()
-    d = ph.DeviceSegments(seg)
-    atm = ph.atmosphere(a)
-    em = ph.emission_cherenkov(300.0, 600.0)
-    n = d.n
-    counts = torch.empty(n, dtype=torch.int32, device="cuda")
-    offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda")
-    ph.gen_cherenkov(d, atm, 300.0, 600.0, seed, ph.FP64, counts, offsets)
-    torch.cuda.synchronize()
-    total = int(offsets[-1].item())
-    hits = ph.HitBuffer(max(total // 8, 1024))
-    totals = ph.status_totals()
-    sink = ph.sink_telescopes(tel, hits, totals)
-    stream = torch.cuda.current_stream()
-
-    results = {}
-    forms = (("fp32", ph.FP32),) if args.fp32_only else (("fp32", ph.FP32), ("fp64", ph.FP64))
-    for name, prec in forms:
-        # launch shape from the autotuner, then the whole step captured in a graph
-        if args.tuning:
-            best = ph.tuning(*(int(v) for v in args.tuning.split(",")))
-        elif prec == ph.FP32 and args.fp32_tuning != "auto":
-            best = ph.tuning(*(int(v) for v in args.fp32_tuning.split(",")))
-        else:
-            best, _ = ph.autotune(d, atm, em, seed, prec, offsets, sink, TUNING_CANDIDATES, reps=3)
-        plan = ph.Plan(d, atm, em, seed, prec, counts, offsets, sink, best)
-        for _ in range(args.warmup):
-            plan.launch()
-        torch.cuda.synchronize()
-        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        for _ in range(args.steps):
-            plan.launch()
-        end.record(stream)
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(end)
-        tot = totals.cpu().numpy()
-        assert int(tot[:7].sum()) == total, (tot, total)
-        assert hits.count() <= hits.capacity
-        nhits = hits.count()
-        plan.close()
-        # the persistent kernel alone, same shape: the library's HIP events
-        # around its launch on the stream it runs on
-        ph.kernel_timing(True)
-        kms = []
-        for _ in range(args.steps):
-            ph.run_fused(d, atm, em, seed, prec, offsets, -1, sink, best)
-            kms.append(ph.fused_kernel_ms())
-        ph.kernel_timing(False)
-        fused_ms = float(np.mean(kms))
-        results[name] = dict(ms_per_step=ms / args.steps, fused_ms=fused_ms,
-                             photons_per_s=total * args.steps / (ms * 1e-3), hits=nhits,
-                             status_totals=[int(x) for x in tot],
-                             tuning=[best.block, best.chunk, best.blocks_per_cu])
-
-    r32 = results["fp32"]
-    achieved = SLOTS_PER_PHOTON["fp32"] * total / (r32["fused_ms"] * 1e-3)
-    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
-                    frac=achieved / PEAK_SLOTS, traffic=traffic_per_launch(),
-                    kernel=f"k_fused<float, {r32['tuning'][0]}, 0>", slots_per_photon=SLOTS_PER_PHOTON["fp32"],
-                    fused_ms=r32["fused_ms"], tuning=r32["tuning"])
-    r64 = results.get("fp64", r32)
+    sections = set(args.only.split(",")) if args.only else {
+        "batched32", "batched64", "shower", "plain", "grid", "cut", "table", "radial", "beam", "adjoint"}
+    tun32 = ph.tuning(*(int(v) for v in args.tuning.split(","))) if args.tuning else None
+    forms = [f for f in (("fp32", ph.FP32, tun32), ("fp64", ph.FP64, None))
+             if ("batched32" if f[0] == "fp32" else "batched64") in sections]
+    out = {}
+    b = batched(args, forms) if forms else None
+    head = b["fp32"] if b and "fp32" in b else None
     out = {
         "metric": "photons propagated/s on 1 MI355X (FP64 vs FP32-split, batched) + % roofline",
-        "value": r32["photons_per_s"], "unit": "photons/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
+        "value": head["photons_per_s"] if head else None, "unit": "photons/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"] if head else None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "shower-shaped Cherenkov: 2e5 segments, 1 TeV gamma profile, zenith 20 deg, "
-                               "16 telescopes R=6 m on a 100 m grid, absorption, 300-600 nm",
-                   "segments": n, "photons": total, "precision": "fp32 bulk, fp64 time/path"},
-        "roofline": roofline,
-        "fp64": {"value": r64["photons_per_s"], "ms_per_step": r64["ms_per_step"], "fused_ms": r64["fused_ms"],
-                 "frac": SLOTS_PER_PHOTON["fp64"] * total / (r64["fused_ms"] * 1e-3) / PEAK_SLOTS},
-        "hits": r32["hits"],
+        "config": {"workload": b["workload"] if b else None, "segments": b["segments"] if b else None,
+                   "photons": head["photons"] if head else None,
+                   "precision": "fp32 bulk, fp64 time/path and near-horizon rays",
+                   "step": "counts + offsets + clear + fused kernel + near-horizon double pass, graph replay"},
+        "roofline": head["roofline"] if head else None,
     }
-    if args.cut:
-        out["angular_cut"] = angular_cut(args, d, atm, tel, seed, ph.tuning(*r32["tuning"]),
-                                         dict(photons=total, hits=r32["hits"], ms_per_step=r32["ms_per_step"]))
-    if args.table:
-        out["table_propagation"] = table_propagation(args, d, atm, tel, seed, ph.tuning(*r32["tuning"]),
-                                                     r32["ms_per_step"])
-    if args.radial:
-        out["radial_profile"] = radial_profile(args, d, atm, seed, ph.tuning(*r32["tuning"]))
-    if args.beam:
-        out["fluorescence_beaming"] = fluorescence_beaming(args, ph.tuning(*r32["tuning"]))
-    if args.batched:
-        out["batched"] = batched_showers(args)
-    if args.adjoint:
+    if b:
+        out["batched"] = b
+        if "fp64" in b:
+            out["fp64"] = dict(value=b["fp64"]["photons_per_s"], ms_per_step=b["fp64"]["ms_per_step"],
+                               frac=b["fp64"]["roofline"]["frac"],
+                               speedup_fp32_over_fp64=(b["fp64"]["ms_per_step"] / head["ms_per_step"]) if head else None)
+        if head and "error_vs_oracle" in head:
+            out["error_vs_oracle"] = head["error_vs_oracle"]
+    extra = None
+    if "shower" in sections or sections & {"cut", "table", "radial"}:
+        out["shower"], extra = shower(args)
+    if "plain" in sections:
+        out["plain_fp64_block"] = plain_block(args)
+    if "grid" in sections:
+        out["fluorescence_grid"] = fluorescence_grid(args)
+    if extra:
+        seg, a, d, atm, tel, tun, r32 = extra
+        if "cut" in sections:
+            out["angular_cut"] = angular_cut(args, d, atm, tel, 2, tun,
+                                             dict(photons=r32["photons"], hits=r32["hits"],
+                                                  ms_per_step=r32["ms_per_step"]))
+        if "table" in sections:
+            out["table_propagation"] = table_propagation(args, seg, a, d, atm, tel, 2, tun, r32["ms_per_step"])
+        if "radial" in sections:
+            out["radial_profile"] = radial_profile(args, d, atm, 2, tun)
+    if "beam" in sections:
+        out["fluorescence_beaming"] = fluorescence_beaming(args, ph.tuning(*SHOWER_FP32_TUNING))
+    if "adjoint" in sections:
         out["differentiable"] = differentiable(args)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(seg, a, tel, seed)
+    if not args.no_cpu_baseline and not args.only:
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
 
 

@@ -270,9 +270,10 @@ typedef struct {
   unsigned long long *radial_count, *radial_weight, *radial_wt;
 } photon_sink;
 
-/* Launch shape of the fused kernel: threads per block (64..1024, multiple
-   of 64), photons per work chunk (multiple of block, at most 16384), blocks per CU
-   (0 = as many as fit). NULL = defaults. */
+/* Launch shape of the fused kernel: threads per block (128, 256 or 512),
+   photons per work chunk (a multiple of block, at most 16384), blocks per
+   CU (0 = as many as fit). NULL = 256 threads, 4096-photon chunks, as many
+   blocks as fit. Errors: EINVAL for any other shape. */
 typedef struct {
   int32_t block;
   int32_t chunk;
@@ -283,7 +284,10 @@ typedef struct {
    returns PHOTON_ENODEV without a gfx950 device. */
 int photon_init(void);
 
-/* Version string and the message of the calling thread's last error. */
+/* Version string ("libphoton <version> (gfx950) source <hash>", the hash
+   being the first 16 hex digits of the SHA-256 of the library's source
+   files and this header) and the message of the calling thread's last
+   error. */
 const char* photon_version(void);
 const char* photon_last_error(void);
 
@@ -381,6 +385,12 @@ int photon_run_fused_noalloc(const photon_segments* seg, const photon_atmosphere
 int photon_kernel_timing(int32_t on);
 int photon_fused_kernel_ms(float* ms);
 
+/* Time of the near-horizon double pass (the scan of the per-block queues and
+   the double kernel) that followed the last timed fused kernel, in ms: the
+   interval from the end of that kernel to the end of the double pass; 0 when
+   that launch had none (FP64 form). Errors as photon_fused_kernel_ms. */
+int photon_fused_deferred_ms(float* ms);
+
 /* ---- captured steps (HIP graphs) and launch-shape tuning ------------------ */
 
 /* A plan is one whole step captured into a HIP graph: per-segment counts and
@@ -407,8 +417,9 @@ int photon_plan_destroy(photon_plan plan);
 /* Launch-shape tuning of the fused kernel: runs photon_run_fused once per
    candidate shape (after one untimed run each), `reps` timed runs per
    candidate measured with HIP events on `stream`, and returns the fastest in
-   *best with its median time in *best_ms. The sink outputs are left in an
-   unspecified state (the caller clears them). Synchronises `stream`.
+   *best with its median time in *best_ms. Every run starts from cleared
+   sink outputs (status totals, hit counter, grid, radial bins), and they are
+   left cleared. Synchronises `stream`.
    Errors: EINVAL (no candidates, reps < 1, invalid candidate), as
    photon_run_fused otherwise. */
 int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm,

@@ -1927,8 +1927,8 @@ struct DeviceState {
   int64_t splat_cells = 0;
   // kernel timing (photon_kernel_timing): events around the last fused
   // kernel launched outside a stream capture
-  bool timing = false, timed = false;
-  hipEvent_t t_ev[2] = {nullptr, nullptr};
+  bool timing = false, timed = false, timed_defer = false;
+  hipEvent_t t_ev[3] = {nullptr, nullptr, nullptr};  // before and after the kernel, after the double pass
   unsigned long long* scratch_ptr = nullptr;  // this device's address of the static scratch
 };
 std::mutex g_mu;
@@ -2215,11 +2215,16 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   if (timed) {
     if (hipEventRecord(dev->t_ev[1], st) != hipSuccess) return fail(PHOTON_EHIP, "event record failed");
     dev->timed = true;
+    dev->timed_defer = false;
   }
   if (defer) {
     hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
                        (int)grid, A.defer_cap, A.defer_pref);
     hipLaunchKernelGGL((k_fused_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A);
+    if (timed) {
+      if (hipEventRecord(dev->t_ev[2], st) != hipSuccess) return fail(PHOTON_EHIP, "event record failed");
+      dev->timed_defer = true;
+    }
   }
   return check_launch();
 }
@@ -2485,7 +2490,10 @@ struct photon_plan_s {
 // ================================================================= C ABI ==
 extern "C" {
 
-const char* photon_version(void) { return "libphoton 0.1 (gfx950)"; }
+#ifndef PHOTON_SOURCE_HASH
+#define PHOTON_SOURCE_HASH "unknown"
+#endif
+const char* photon_version(void) { return "libphoton 0.2 (gfx950) source " PHOTON_SOURCE_HASH; }
 
 const char* photon_last_error(void) { return g_err.c_str(); }
 
@@ -2599,6 +2607,22 @@ int photon_kernel_timing(int32_t on) {
   }
   dev->timing = on != 0;
   dev->timed = false;
+  dev->timed_defer = false;
+  return PHOTON_OK;
+}
+
+int photon_fused_deferred_ms(float* ms) {
+  if (!ms) return fail(PHOTON_EINVAL, "ms is NULL");
+  DeviceState* dev;
+  int rc;
+  if ((rc = current_device(&dev))) return rc;
+  if (!dev->timed) return fail(PHOTON_EINVAL, "no fused kernel timed on this device (photon_kernel_timing off?)");
+  if (!dev->timed_defer) {
+    *ms = 0.0f;
+    return PHOTON_OK;
+  }
+  if (hipEventSynchronize(dev->t_ev[2]) != hipSuccess || hipEventElapsedTime(ms, dev->t_ev[1], dev->t_ev[2]) != hipSuccess)
+    return fail(PHOTON_EHIP, "event timing failed");
   return PHOTON_OK;
 }
 
@@ -2689,13 +2713,16 @@ int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm, co
   HIP_TRY(hipEventCreate(&e1));
   float best_t = 0.0f;
   int best_i = -1;
+  // every run starts from cleared sink outputs, so that each candidate does
+  // the same work (a full hit buffer would skip the stores of later runs)
+  const ZeroList z = sink_zero_list(a.sk);
   for (int i = 0; i < n_candidates && rc == PHOTON_OK; ++i) {
-    if ((rc = enqueue_fused(a, offsets, -1, &candidates[i], dev, st))) break;
+    if ((rc = enqueue_fused(a, offsets, -1, &candidates[i], dev, st, &z))) break;
     float t[64];
     const int nr = reps < 64 ? reps : 64;
     for (int r = 0; r < nr; ++r) {
       (void)hipEventRecord(e0, st);
-      if ((rc = enqueue_fused(a, offsets, -1, &candidates[i], dev, st))) break;
+      if ((rc = enqueue_fused(a, offsets, -1, &candidates[i], dev, st, &z))) break;
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess) {
         rc = fail(PHOTON_EHIP, "hipEventSynchronize failed");
@@ -2719,6 +2746,8 @@ int photon_autotune(const photon_segments* seg, const photon_atmosphere* atm, co
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
+  launch_zero_list(z, st);
+  if ((rc = check_launch())) return rc;
   *best = candidates[best_i];
   *best_ms = best_t;
   return PHOTON_OK;

@@ -13,6 +13,8 @@ import os
 import numpy as np
 import torch
 
+from . import build as _build
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libphoton.so")
 
@@ -98,13 +100,19 @@ _lib = None
 
 
 def lib():
-    """Loads libphoton.so; raises if it has not been built."""
+    """Loads libphoton.so; raises if it has not been built, or was built from
+    other sources than the ones beside it."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
         L.photon_version.restype = C.c_char_p
+        built = L.photon_version().decode().rsplit(" ", 1)[-1]
+        want = _build.source_hash()
+        if built != want:
+            raise RuntimeError(f"{LIB_PATH} was built from sources {built}, the sources are now {want}: "
+                               "rebuild it with __graft_entry__.build()")
         L.photon_last_error.restype = C.c_char_p
         L.photon_init.restype = C.c_int
         L.photon_gen_cherenkov.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P]
@@ -124,13 +132,14 @@ def lib():
         L.photon_table_build.argtypes = [P, P, P]
         L.photon_kernel_timing.argtypes = [C.c_int32]
         L.photon_fused_kernel_ms.argtypes = [P]
+        L.photon_fused_deferred_ms.argtypes = [P]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
                   "photon_run_fused", "photon_run_fused_noalloc", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
                   "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward",
-                  "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms"):
+                  "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms", "photon_fused_deferred_ms"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -513,6 +522,14 @@ def fused_kernel_ms() -> float:
     (waits for it)."""
     ms = C.c_float(0.0)
     _check(lib().photon_fused_kernel_ms(C.byref(ms)))
+    return float(ms.value)
+
+
+def fused_deferred_ms() -> float:
+    """Time of the near-horizon double pass after the last timed fused
+    launch (0 when it had none)."""
+    ms = C.c_float(0.0)
+    _check(lib().photon_fused_deferred_ms(C.byref(ms)))
     return float(ms.value)
 
 

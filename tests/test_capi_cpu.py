@@ -34,6 +34,17 @@ def test_every_declared_symbol_is_exported(ph):
 
 def test_version(ph):
     assert "gfx950" in ph.version()
+    # the library reports the hash of the sources it was built from
+    assert ph.version().endswith(ph._build.source_hash())
+
+
+def test_stale_library_is_refused(ph, monkeypatch):
+    """A library built from other sources than the ones beside it does not
+    load: the binding raises instead of running stale kernels."""
+    monkeypatch.setattr(ph, "_lib", None)
+    monkeypatch.setattr(ph._build, "source_hash", lambda: "0000000000000000")
+    with pytest.raises(RuntimeError, match="rebuild"):
+        ph.lib()
 
 
 def _valid_atm(ph):
