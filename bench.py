@@ -387,13 +387,13 @@ def plain_block(args):
         if not args.no_errors:
             g = blk.numpy()
             oatm = O.Atmosphere.from_dict(a)
-            off = offsets.cpu().numpy().view(np.uint64)
+            off = offsets.cpu().numpy().astype(np.int64)
             rows = np.arange(len(seg["x0"])) if name == "plain" else every_kth(len(seg["x0"]), 2e5, total / len(seg["x0"]))
             sub = W.subsample(seg, rows)
             ocnt = O.counts(sub, oatm, "cherenkov", seed)[0]
             gcnt = np.diff(off)[rows].astype(np.uint32)
             ref = O.photons_all(sub, oatm, "cherenkov", seed, O.offsets_of(ocnt))
-            slots = np.concatenate([np.arange(off[s], off[s + 1]) for s in rows]) if len(rows) else np.zeros(0, int)
+            slots = np.concatenate([np.arange(off[s], off[s + 1], dtype=np.int64) for s in rows])
             gs = {k: v[slots] for k, v in g.items()}
             e = dict(segments=len(rows), photons=len(slots), counts_equal=bool(np.array_equal(gcnt, ocnt)),
                      status_equal=bool(np.array_equal(gs["status"], ref["status"])))
