@@ -32,9 +32,17 @@
  *     counter (j or chunk, index_in_shower, shower, domain); results are a
  *     pure function of (inputs, seed), independent of batching and of the
  *     order of segments.
- *   - The library allocates one small device work area per device (a few
- *     bytes of counters) on its first use on that device; photon_init()
- *     creates it up front (needed before stream capture).
+ *   - Device scratch. Eager calls of the fused, splat and adjoint forms work
+ *     in the device's own scratch, allocated on first use: a 64 KB work area
+ *     (work cursor, per-block counts), the FP32 form's near-horizon queue
+ *     (2^24 rays, 128 MB, photon_set_defer_capacity), the adjoint's partial
+ *     sums (1.1 MB) and the splat's accumulator (8 B per cell). Such calls
+ *     are ordered on the device whatever their streams: a call on another
+ *     stream than the previous one waits for it (an event recorded after
+ *     each call; not inside a stream capture). photon_init() creates the
+ *     work area up front. A captured plan owns its scratch (photon_plan_*),
+ *     and photon_run_fused_noalloc works in a static array: neither touches
+ *     the device's scratch.
  */
 #ifndef PHOTON_H
 #define PHOTON_H
@@ -71,9 +79,10 @@ extern "C" {
 #define PHOTON_INVALID 6        /* slot without a valid segment             */
 #define PHOTON_N_STATUS 8
 /* Slot 7 of the status totals is not a photon status: it counts rays near
-   the horizon that a fused FP32 run evaluated in float because its deferral
-   queue was full (2^24 rays per device, shared evenly among the kernel's
-   blocks); slots 0..6 partition the photons. */
+   the horizon that a fused FP32 run evaluated in place (in double, as the
+   photon-block path does, at a lower speed) because its deferral queue was
+   full (2^24 rays per device unless resized, shared evenly among the
+   kernel's blocks); slots 0..6 partition the photons. */
 #define PHOTON_HORIZON_FLOAT 7
 
 /* ---- sink kinds ---------------------------------------------------------- */
@@ -280,9 +289,19 @@ typedef struct {
   int32_t blocks_per_cu;
 } photon_tuning;
 
-/* Creates the per-device work area on the current device. Optional;
-   returns PHOTON_ENODEV without a gfx950 device. */
+/* Creates the per-device work area on the current device and looks up the
+   device's address of the static scratch of photon_run_fused_noalloc.
+   Optional; returns PHOTON_ENODEV without a gfx950 device. */
 int photon_init(void);
+
+/* Length of the current device's near-horizon queue of the FP32 form
+   (default 2^24 rays, 8 B each), for calls made after this one and plans
+   created after it: a block of a fused launch queues at most rays / (its
+   blocks) rays, and evaluates the rest in place, in double, at a lower
+   speed (counted in PHOTON_HORIZON_FLOAT).
+   Waits for the device to be idle and frees the current queue (it is
+   allocated again on first use). Errors: EINVAL (rays outside 1..2^28). */
+int photon_set_defer_capacity(int64_t rays);
 
 /* Version string ("libphoton <version> (gfx950) source <hash>", the hash
    being the first 16 hex digits of the SHA-256 of the library's source
@@ -346,9 +365,9 @@ int photon_collect(const photon_block* in, const photon_atmosphere* atm, const p
    offsets[n] count as INVALID). Results equal those of gen + propagate +
    collect. In the FP32 form, rays within about 6 degrees of the horizon are
    handed to a second, double kernel that regenerates them from their random
-   numbers (a per-device queue of 2^24 rays, allocated on the first such
-   call; see PHOTON_HORIZON_FLOAT). One call at a time per device: calls
-   share the device's work queue counters. */
+   numbers (the device's queue of 2^24 rays, allocated on the first such
+   call; see PHOTON_HORIZON_FLOAT). Works in the device's scratch: calls on
+   one device are ordered whatever their streams (see the conventions). */
 int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
                      const photon_emission* em, uint64_t seed, int32_t precision,
                      const uint64_t* offsets, int64_t n_photons, const photon_sink* sink,
@@ -363,8 +382,9 @@ int photon_run_fused(const photon_segments* seg, const photon_atmosphere* atm,
    address is looked up once per device (photon_init, else the first call).
    Limit: the FP32 form queues at most 2^20 / (blocks of the launch)
    near-horizon rays per block for the double pass; a block that queues more
-   finishes the excess in float and counts it in PHOTON_HORIZON_FLOAT, as
-   photon_run_fused does beyond its 2^24-ray queue. Every call on one GPU
+   evaluates the excess in place in double and counts it in
+   PHOTON_HORIZON_FLOAT, as photon_run_fused does beyond its 2^24-ray
+   queue. Every call on one GPU
    works in that GPU's one array and leaves its contents behind (the cursor
    is cleared at the start of each call): calls that overlap on one GPU, on
    any streams, race. Errors: as photon_run_fused; PHOTON_EHIP if the
@@ -399,8 +419,10 @@ int photon_fused_deferred_ms(float* ms);
    kernels, and the fused persistent kernel reading the photon total on the
    device. Replays reuse the pointers given at creation; the caller keeps those
    buffers alive and unchanged in size until photon_plan_destroy. Creation
-   validates like photon_run_fused and needs the device work area, which it
-   creates (photon_init). */
+   validates like photon_run_fused and allocates the plan's own scratch (a
+   128 KB work area and, for FP32, a near-horizon queue of the device's
+   queue length), so that plans replayed on different streams do not
+   interfere; replays of one plan must not overlap each other. */
 typedef struct photon_plan_s* photon_plan;
 
 int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm,
@@ -497,9 +519,9 @@ int photon_means(const photon_segments* seg, const photon_atmosphere* atm,
    depend on the order of the additions (a cell overflows only beyond 2^32
    in weight units); each block accumulates the whole grid in LDS when it
    fits (16384 cells on gfx950). The library keeps a per-device accumulator
-   of 8 bytes per cell, grown on the first call with a larger grid. One call
-   at a time per device. Errors: EINVAL (NULL pointers, band, atmosphere,
-   precision, grid). */
+   of 8 bytes per cell, grown on the first call with a larger grid; calls
+   are ordered on the device as the conventions say. Errors: EINVAL (NULL
+   pointers, band, atmosphere, precision, grid). */
 int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* atm,
                          double lambda_min_nm, double lambda_max_nm, uint64_t seed,
                          int32_t precision, const uint64_t* offsets, const double* mean0,
@@ -516,8 +538,9 @@ int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* at
    is regenerated from its random numbers and carried forward and back; the
    truncation edge of the splat is not differentiated. Direction gradients
    are summed with atomic adds (order varies between runs); the global ones
-   in a fixed order of per-block partial sums. One call at a time per
-   device. Errors: as photon_splat_forward. */
+   in a fixed order of per-block partial sums. Works in the device's
+   scratch (ordered as the conventions say). Errors: as
+   photon_splat_forward. */
 int photon_splat_backward(const photon_segments* seg, const photon_atmosphere* atm,
                           double lambda_min_nm, double lambda_max_nm, uint64_t seed,
                           int32_t precision, const uint64_t* offsets, const double* mean0,

@@ -1027,9 +1027,10 @@ void k_fused(FusedArgs A) {
                 if (slot < (uint64_t)A.defer_cap) {
                   A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
                 } else {
-                  // queue full: this ray is evaluated in float after all
+                  // queue full: this ray is evaluated here after all, in
+                  // double as the photon-block path does
                   p.status = PHOTON_LANDED;
-                  propagate<T, false, true>(A.atm, s_lane, p, c.layer);
+                  propagate<T>(A.atm, s_lane, p, c.layer);
                   forced = true;
                 }
               }
@@ -1913,7 +1914,13 @@ struct DeviceState {
   int cu = 0;
   size_t lds_per_block = 0;             // largest LDS allocation of one workgroup
   unsigned long long* work = nullptr;  // [0] = fused work cursor, [kDeferCounts..] per-block deferred counts
-  uint2* defer_q = nullptr;            // deferred (segment row, j), kDeferCap entries
+  uint2* defer_q = nullptr;            // deferred (segment row, j), defer_rays entries
+  int64_t defer_rays = kDeferCap;      // length of the deferral queue (photon_set_defer_capacity)
+  // calls working in this device's own scratch are ordered across streams:
+  // the event recorded after the last one, and its stream
+  hipEvent_t last_ev = nullptr;
+  hipStream_t last_st = nullptr;
+  bool last_valid = false;
   unsigned long long* defer_pref = nullptr;  // prefix sums of the per-block deferred counts
   struct OccEntry {
     const void* fn;
@@ -2124,7 +2131,7 @@ void warm_occupancy(DeviceState* dev) {
 int ensure_defer_queue(DeviceState* dev) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (dev->defer_q) return PHOTON_OK;
-  if (hipMalloc(&dev->defer_q, sizeof(uint2) * kDeferCap) != hipSuccess) {
+  if (hipMalloc(&dev->defer_q, sizeof(uint2) * dev->defer_rays) != hipSuccess) {
     dev->defer_q = nullptr;
     return fail(PHOTON_EHIP, "deferral queue allocation failed");
   }
@@ -2138,7 +2145,7 @@ int ensure_defer_queue(DeviceState* dev) {
 }
 
 // The device's own fused scratch: the work area and, for the float form, the
-// deferral queue of kDeferCap rays, both allocated on first use.
+// deferral queue (2^24 rays unless resized), both allocated on first use.
 int device_scratch(DeviceState* dev, bool defer, FusedScratch* ws) {
   int rc;
   if ((rc = ensure_work(dev))) return rc;
@@ -2147,7 +2154,83 @@ int device_scratch(DeviceState* dev, bool defer, FusedScratch* ws) {
   ws->defer_counts = dev->work + kDeferCounts;
   ws->defer_pref = dev->defer_pref;
   ws->defer_q = dev->defer_q;
-  ws->defer_rays = defer ? kDeferCap : 0;
+  ws->defer_rays = defer ? dev->defer_rays : 0;
+  return PHOTON_OK;
+}
+
+// Calls that work in the device's own scratch (work cursor, deferral queue,
+// adjoint partial sums, splat accumulator) run one after another on the
+// device whatever their streams: a call on another stream than the previous
+// one first makes its stream wait for an event recorded after that call.
+// Inside a stream capture neither the wait nor the record is made (a
+// captured graph that uses the device's scratch must not be replayed beside
+// other such calls).
+int begin_device_scratch(DeviceState* dev, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return fail(PHOTON_EHIP, "stream capture query failed");
+  if (cs != hipStreamCaptureStatusNone) return PHOTON_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev->last_valid && dev->last_st != st && hipStreamWaitEvent(st, dev->last_ev, 0) != hipSuccess)
+    return fail(PHOTON_EHIP, "hipStreamWaitEvent failed");
+  return PHOTON_OK;
+}
+
+int end_device_scratch(DeviceState* dev, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return fail(PHOTON_EHIP, "stream capture query failed");
+  if (cs != hipStreamCaptureStatusNone) return PHOTON_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!dev->last_ev && hipEventCreateWithFlags(&dev->last_ev, hipEventDisableTiming) != hipSuccess) {
+    dev->last_ev = nullptr;
+    return fail(PHOTON_EHIP, "event creation failed");
+  }
+  if (hipEventRecord(dev->last_ev, st) != hipSuccess) return fail(PHOTON_EHIP, "event record failed");
+  dev->last_st = st;
+  dev->last_valid = true;
+  return PHOTON_OK;
+}
+
+// Scratch owned by one captured plan: allocated before its capture, freed
+// with it, so that plans replayed on different streams do not share a work
+// cursor or a deferral queue.
+struct OwnedScratch {
+  unsigned long long* area = nullptr;  // cursor + per-block counts (kWorkWords), prefix sums (kWorkWords)
+  uint2* queue = nullptr;
+  int64_t rays = 0;
+  FusedScratch view() const {
+    FusedScratch w;
+    w.cursor = area;
+    w.defer_counts = area + kDeferCounts;
+    w.defer_pref = area + kWorkWords;
+    w.defer_q = queue;
+    w.defer_rays = rays;
+    return w;
+  }
+};
+
+void free_scratch(OwnedScratch* o) {
+  if (o->area) (void)hipFree(o->area);
+  if (o->queue) (void)hipFree(o->queue);
+  *o = OwnedScratch{};
+}
+
+int alloc_scratch(int64_t defer_rays, OwnedScratch* o) {
+  if (hipMalloc(&o->area, sizeof(unsigned long long) * 2 * kWorkWords) != hipSuccess) {
+    o->area = nullptr;
+    return fail(PHOTON_EHIP, "plan scratch allocation failed");
+  }
+  if (hipMemset(o->area, 0, sizeof(unsigned long long) * 2 * kWorkWords) != hipSuccess) {
+    free_scratch(o);
+    return fail(PHOTON_EHIP, "plan scratch clear failed");
+  }
+  if (defer_rays > 0) {
+    if (hipMalloc(&o->queue, sizeof(uint2) * defer_rays) != hipSuccess) {
+      o->queue = nullptr;
+      free_scratch(o);
+      return fail(PHOTON_EHIP, "plan deferral queue allocation failed");
+    }
+    o->rays = defer_rays;
+  }
   return PHOTON_OK;
 }
 
@@ -2178,8 +2261,9 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   if (scratch_in) {
     ws = *scratch_in;
   } else {
-    const int rc = device_scratch(dev, defer, &ws);
+    int rc = device_scratch(dev, defer, &ws);
     if (rc) return rc;
+    if ((rc = begin_device_scratch(dev, st))) return rc;
   }
   FusedArgs A;
   A.seg = sv;
@@ -2226,7 +2310,9 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
       dev->timed_defer = true;
     }
   }
-  return check_launch();
+  const int rc = check_launch();
+  if (rc) return rc;
+  return scratch_in ? PHOTON_OK : end_device_scratch(dev, st);
 }
 
 template <typename T>
@@ -2325,12 +2411,12 @@ int enqueue_fused(const StepArgs& a, const uint64_t* offsets, int64_t n_ph, cons
 
 // One whole step: counts + offsets, cleared outputs, fused kernel.
 int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const photon_tuning* tun,
-                 DeviceState* dev, hipStream_t st) {
+                 DeviceState* dev, hipStream_t st, const FusedScratch* ws = nullptr) {
   int rc;
   if ((rc = count_and_scan(a.sv, a.n, a.ad, a.kind, a.K, a.cut, a.g.beam, a.seed, counts, offsets, st))) return rc;
   // the sink outputs are cleared by the launch that clears the work cursor
   const ZeroList z = sink_zero_list(a.sk);
-  return enqueue_fused(a, offsets, -1, tun, dev, st, &z);
+  return enqueue_fused(a, offsets, -1, tun, dev, st, &z, ws);
 }
 
 // ------------------------------------------------------ differentiable form --
@@ -2434,6 +2520,7 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
   constexpr bool defer = sizeof(T) == 4;
   FusedScratch ws;
   if ((rc = device_scratch(dev, defer, &ws))) return rc;
+  if ((rc = begin_device_scratch(dev, st))) return rc;
   if (c.n > 0) {
     const unsigned zb = (unsigned)std::min<int64_t>(ceil_div(c.n, 256), 4096);
     hipLaunchKernelGGL(k_zero64_n, dim3(zb), dim3(256), 0, st, (unsigned long long*)gdx, c.n);
@@ -2477,7 +2564,8 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
     }
   }
   hipLaunchKernelGGL(k_adj_finalize, dim3(1), dim3(64), 0, st, (const double*)dev->adj_part, nb, c.ad, gH, geta);
-  return check_launch();
+  if ((rc = check_launch())) return rc;
+  return end_device_scratch(dev, st);
 }
 
 }  // namespace
@@ -2485,6 +2573,7 @@ int launch_adjoint(const SplatCall& c, const uint64_t* offsets, const double* me
 struct photon_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  OwnedScratch scratch;  // the plan's own work cursor and deferral queue
 };
 
 // ================================================================= C ABI ==
@@ -2649,28 +2738,38 @@ int photon_plan_create(const photon_segments* seg, const photon_atmosphere* atm,
   DeviceState* dev;
   if ((rc = current_device(&dev))) return rc;
   warm_occupancy(dev);
-  FusedScratch ws;
-  if ((rc = device_scratch(dev, precision == PHOTON_FP32, &ws))) return rc;
-  hipStream_t cs;
-  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   photon_plan_s* p = new photon_plan_s;
+  if ((rc = alloc_scratch(precision == PHOTON_FP32 ? dev->defer_rays : 0, &p->scratch))) {
+    delete p;
+    return rc;
+  }
+  const FusedScratch ws = p->scratch.view();
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    free_scratch(&p->scratch);
+    delete p;
+    return fail(PHOTON_EHIP, "capture stream creation failed");
+  }
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
     (void)hipStreamDestroy(cs);
+    free_scratch(&p->scratch);
     delete p;
     return fail(PHOTON_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
   }
-  rc = enqueue_step(a, counts, offsets, tuning, dev, cs);
+  rc = enqueue_step(a, counts, offsets, tuning, dev, cs, &ws);
   e = hipStreamEndCapture(cs, &p->graph);
   (void)hipStreamDestroy(cs);
   if (rc || e != hipSuccess) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    free_scratch(&p->scratch);
     delete p;
     return rc ? rc : fail(PHOTON_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
   }
   e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(p->graph);
+    free_scratch(&p->scratch);
     delete p;
     return fail(PHOTON_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   }
@@ -2688,7 +2787,24 @@ int photon_plan_destroy(photon_plan plan) {
   if (!plan) return PHOTON_OK;
   if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  free_scratch(&plan->scratch);
   delete plan;
+  return PHOTON_OK;
+}
+
+int photon_set_defer_capacity(int64_t rays) {
+  if (rays < 1 || rays > ((int64_t)1 << 28))
+    return fail(PHOTON_EINVAL, "deferral capacity %lld outside 1..2^28", (long long)rays);
+  DeviceState* dev;
+  int rc;
+  if ((rc = current_device(&dev))) return rc;
+  HIP_TRY(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev->defer_q) (void)hipFree(dev->defer_q);
+  if (dev->defer_pref) (void)hipFree(dev->defer_pref);
+  dev->defer_q = nullptr;
+  dev->defer_pref = nullptr;
+  dev->defer_rays = rays;
   return PHOTON_OK;
 }
 
@@ -2843,6 +2959,7 @@ int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* at
   hipStream_t st = (hipStream_t)stream;
   const int cells = c.sg.nx * c.sg.ny;
   if ((rc = ensure_splat_acc(dev, cells))) return rc;
+  if ((rc = begin_device_scratch(dev, st))) return rc;
   hipLaunchKernelGGL(k_zero64_n, dim3((unsigned)std::min<int64_t>(ceil_div(cells, 256), 4096)), dim3(256), 0, st,
                      dev->splat_acc, (int64_t)cells);
   if (status_totals) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, status_totals, PHOTON_N_STATUS);
@@ -2876,7 +2993,8 @@ int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* at
   else
     hipLaunchKernelGGL(k_splat_finish<float>, dim3(nb), dim3(256), 0, st, (const unsigned long long*)dev->splat_acc,
                        cells, c.sg.norm, (float*)density);
-  return check_launch();
+  if ((rc = check_launch())) return rc;
+  return end_device_scratch(dev, st);
 }
 
 int photon_splat_backward(const photon_segments* seg, const photon_atmosphere* atm, double lambda_min_nm,

@@ -133,13 +133,14 @@ def lib():
         L.photon_kernel_timing.argtypes = [C.c_int32]
         L.photon_fused_kernel_ms.argtypes = [P]
         L.photon_fused_deferred_ms.argtypes = [P]
+        L.photon_set_defer_capacity.argtypes = [C.c_int64]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
                   "photon_run_fused", "photon_run_fused_noalloc", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
                   "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward",
-                  "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms", "photon_fused_deferred_ms"):
+                  "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms", "photon_fused_deferred_ms", "photon_set_defer_capacity"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -523,6 +524,12 @@ def fused_kernel_ms() -> float:
     ms = C.c_float(0.0)
     _check(lib().photon_fused_kernel_ms(C.byref(ms)))
     return float(ms.value)
+
+
+def set_defer_capacity(rays: int):
+    """Length of the current device's near-horizon queue for later calls
+    (photon_set_defer_capacity)."""
+    _check(lib().photon_set_defer_capacity(int(rays)))
 
 
 def fused_deferred_ms() -> float:

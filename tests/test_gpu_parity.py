@@ -466,3 +466,29 @@ def test_fused_plane_capacity_is_checked(plain_run):
     ph.run_fused(d, atm, em, 1, ph.FP32, offsets, -1, ph.sink_plane(small))
     torch.cuda.synchronize()
     assert int((small.t["status"] == -5).sum().item()) == 0
+
+
+def test_deferral_queue_overflow_evaluated_in_place(fluor_run):
+    """With a near-horizon queue too short for any block (64 rays for the
+    whole launch), every ray the fused float kernel would hand to the double
+    pass is evaluated in place instead (in double, as the photon-block path
+    does) and counted in slot 7. Every photon still meets the FP32 bars; the
+    photons away from the horizon are bit-identical to the run with the full
+    queue."""
+    a, seg, d, atm, em, offsets, total, ref = fluor_run
+    g0, tot0 = run_fused_plane(d, atm, em, 3, ph.FP32, offsets, total)
+    assert tot0[ph.HORIZON_FLOAT] == 0
+    ph.set_defer_capacity(64)
+    try:
+        g, tot = run_fused_plane(d, atm, em, 3, ph.FP32, offsets, total)
+    finally:
+        ph.set_defer_capacity(1 << 24)
+    assert tot[:7].sum() == total
+    near = (np.abs(ref["ue"][:, 2]) < 0.1) & (ref["ue"][:, 2] < 0)
+    assert tot[ph.HORIZON_FLOAT] > 0.5 * near.sum()
+    assert np.array_equal(tot[:7], tot0[:7])
+    assert np.array_equal(g["status"], ref["status"])
+    check_propagated(g, ref, TOL32)
+    same = np.abs(ref["ue"][:, 2]) >= 0.2
+    for f in ("x", "y", "t_ns", "weight", "ux", "uy", "uz"):
+        assert np.array_equal(g[f][same], g0[f][same]), f

@@ -179,3 +179,81 @@ def test_kernel_timing(batched):
         ph.fused_kernel_ms()
     plan.close()
     ph.kernel_timing(False)
+
+
+def _fluor_set():
+    a = W.default_atmosphere(absorption=True)
+    lam, rel = W.fluorescence_lines()
+    seg = W.fluorescence(1500, seed=3)
+    d = ph.DeviceSegments(seg)
+    atm = ph.atmosphere(a)
+    em = ph.emission_fluor(lam, rel, W.FLUOR_YIELD_PER_MEV)
+    counts, offsets = ph.count(d, atm, em, 3)
+    torch.cuda.synchronize()
+    return d, atm, em, counts, offsets, int(offsets[-1].item())
+
+
+def test_two_plans_on_two_streams(batched):
+    """Plans own their work cursor and near-horizon queue: two plans (a
+    Cherenkov batch and an isotropic fluorescence set, both FP32, both with
+    near-horizon rays for the double pass of the fluorescence one) replayed
+    interleaved on two streams without synchronising give exactly the results
+    of sequential direct runs."""
+    a, seg, d, atm, em, counts, offsets, total = batched
+    tel = W.telescopes_16(radius=20.0)
+    fd, fatm, fem, fcounts, foffsets, ftotal = _fluor_set()
+    ref = []
+    for dd, aa, ee, seed, off, tt in ((d, atm, em, 4, offsets, total), (fd, fatm, fem, 3, foffsets, ftotal)):
+        h = ph.HitBuffer(tt)
+        t = ph.status_totals()
+        ph.run_fused(dd, aa, ee, seed, ph.FP32, off, tt, ph.sink_telescopes(tel, h, t))
+        torch.cuda.synchronize()
+        ref.append((hit_keys(h), t.cpu().numpy()))
+    assert ref[1][1][ph.HORIZON_FLOAT] == 0 and ref[1][1][ph.LANDED] > 0
+    outs, plans = [], []
+    for dd, aa, ee, seed, cc, off, tt in ((d, atm, em, 4, counts, offsets, total),
+                                          (fd, fatm, fem, 3, fcounts, foffsets, ftotal)):
+        h = ph.HitBuffer(tt)
+        t = ph.status_totals()
+        c2, o2 = torch.empty_like(cc), torch.empty_like(off)
+        plans.append(ph.Plan(dd, aa, ee, seed, ph.FP32, c2, o2, ph.sink_telescopes(tel, h, t)))
+        outs.append((h, t))
+    s = [torch.cuda.Stream(), torch.cuda.Stream()]
+    try:
+        torch.cuda.synchronize()
+        for rep in range(4):
+            for k in (0, 1):
+                with torch.cuda.stream(s[k]):
+                    plans[k].launch()
+            torch.cuda.synchronize()
+            for k in (0, 1):
+                assert np.array_equal(outs[k][1].cpu().numpy(), ref[k][1]), (rep, k)
+                assert np.array_equal(hit_keys(outs[k][0]), ref[k][0]), (rep, k)
+    finally:
+        for p in plans:
+            p.close()
+
+
+def test_eager_calls_on_two_streams(batched):
+    """Eager fused calls on two streams, enqueued back to back, are ordered on
+    the device (they share its work cursor): both results are exact."""
+    a, seg, d, atm, em, counts, offsets, total = batched
+    tel = W.telescopes_16(radius=20.0)
+    fd, fatm, fem, fcounts, foffsets, ftotal = _fluor_set()
+    runs = ((d, atm, em, 4, offsets, total), (fd, fatm, fem, 3, foffsets, ftotal))
+    ref = []
+    for dd, aa, ee, seed, off, tt in runs:
+        t = ph.status_totals()
+        ph.run_fused(dd, aa, ee, seed, ph.FP32, off, tt, ph.sink_status(t))
+        torch.cuda.synchronize()
+        ref.append(t.cpu().numpy())
+    s = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        tots = [ph.status_totals(), ph.status_totals()]
+        torch.cuda.synchronize()
+        for k, (dd, aa, ee, seed, off, tt) in enumerate(runs):
+            with torch.cuda.stream(s[k]):
+                ph.run_fused(dd, aa, ee, seed, ph.FP32, off, tt, ph.sink_status(tots[k]))
+        torch.cuda.synchronize()
+        for k in (0, 1):
+            assert np.array_equal(tots[k].cpu().numpy(), ref[k]), (rep, k)
