@@ -151,9 +151,15 @@ def alu_roofline(kernel, key, form, photons, kernel_ms, deferred_ms, tun):
     c = counters(key)
     if c:
         r["traffic"] = c["fetch_bytes"] + c["write_bytes"]
+        # from the committed rocprofv3 runs of this kernel and workload: executed
+        # instructions per photon, rocprofv3's VALUBusy and VALUUtilization
+        # (gfx950 can issue two VALU instructions per SIMD quad-cycle, so the
+        # busy figure can pass 100), FLOP rates against 157.3 (FP32, packed)
+        # and 78.6 TFLOP/s (FP64), and the traced mean kernel time
         r["measured"] = dict(valu_lane_instr_per_photon=c["valu_per_photon"],
-                             salu_per_photon=c["salu_per_photon"],
-                             valu_issue_frac=c["valu_per_photon"] * photons / (kernel_ms * 1e-3) / PEAK_SLOTS,
+                             salu_per_photon=c["salu_per_photon"], lds_per_photon=c.get("lds_per_photon"),
+                             valu_busy_pct=c.get("valu_busy_pct"), valu_util_pct=c.get("valu_util_pct"),
+                             fp32_tflops=c.get("fp32_tflops"), fp64_tflops=c.get("fp64_tflops"),
                              profiled_kernel_ms=c["avg_ns"] * 1e-6,
                              hbm_bytes_per_photon=(c["fetch_bytes"] + c["write_bytes"]) / photons)
     return r
@@ -667,6 +673,8 @@ def main():
                          "grid, cut, table, radial, beam, adjoint")
     ap.add_argument("--tuning", default=None,
                     help="block,chunk,blocks_per_cu of the headline FP32 step instead of the autotuner's choice")
+    ap.add_argument("--tuning64", default=None,
+                    help="block,chunk,blocks_per_cu of the headline FP64 step instead of the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -690,7 +698,8 @@ def main():
     sections = set(args.only.split(",")) if args.only else {
         "batched32", "batched64", "shower", "plain", "grid", "cut", "table", "radial", "beam", "adjoint"}
     tun32 = ph.tuning(*(int(v) for v in args.tuning.split(","))) if args.tuning else None
-    forms = [f for f in (("fp32", ph.FP32, tun32), ("fp64", ph.FP64, None))
+    tun64 = ph.tuning(*(int(v) for v in args.tuning64.split(","))) if args.tuning64 else None
+    forms = [f for f in (("fp32", ph.FP32, tun32), ("fp64", ph.FP64, tun64))
              if ("batched32" if f[0] == "fp32" else "batched64") in sections]
     out = {}
     b = batched(args, forms) if forms else None

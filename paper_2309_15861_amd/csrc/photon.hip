@@ -269,32 +269,31 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
   }
 }
 
-// In-place inclusive scan of the block totals at positions min((b+1)B, n).
+// In-place inclusive scan of the block totals at positions min((b+1)B, n),
+// one workgroup: thread t owns the run of R = ceil(nb/1024) consecutive
+// block totals starting at t R; it sums its run (independent loads, all in
+// flight together), the 1024 run sums are scanned across the workgroup, and
+// each thread rewrites its run with running sums (the second read hits L2).
 __global__ __launch_bounds__(1024) void k_scan_tops(uint64_t* __restrict__ offsets, int64_t n, int64_t nb) {
   __shared__ unsigned long long part[1024 / kWaveSize];
-  __shared__ unsigned long long carry;
-  if (threadIdx.x == 0) {
-    carry = 0;
-    offsets[0] = 0;
-  }
+  const int64_t R = (nb + 1023) / 1024;
+  const int64_t b0 = (int64_t)threadIdx.x * R;
+  const int64_t b1 = min(b0 + R, nb);
+  unsigned long long sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += offsets[min((b + 1) * kScanBlock, n)];
+  const unsigned long long incl = wave_incl_scan(sum);
+  const int w = threadIdx.x / kWaveSize;
+  if (lane_id() == kWaveSize - 1) part[w] = incl;
   __syncthreads();
-  for (int64_t base = 0; base < nb; base += 1024) {
-    const int64_t b = base + threadIdx.x;
+  unsigned long long run = incl - sum;
+  for (int k = 0; k < w; ++k) run += part[k];
+  for (int64_t b = b0; b < b1; ++b) {
     const int64_t pos = min((b + 1) * kScanBlock, n);
-    unsigned long long v = (b < nb) ? offsets[pos] : 0ull;
-    v = wave_incl_scan(v);
-    const int w = threadIdx.x / kWaveSize;
-    if (lane_id() == kWaveSize - 1) part[w] = v;
-    __syncthreads();
-    unsigned long long add = carry;
-    for (int k = 0; k < w; ++k) add += part[k];
-    if (b < nb) offsets[pos] = v + add;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = v + add;
-    __syncthreads();
+    run += offsets[pos];
+    offsets[pos] = run;
   }
+  if (threadIdx.x == 0) offsets[0] = 0;
 }
-
 __global__ __launch_bounds__(kScanBlock) void k_scan_final(const uint32_t* __restrict__ counts,
                                                            uint64_t* __restrict__ offsets, int64_t n) {
   __shared__ unsigned long long part[kScanBlock / kWaveSize];

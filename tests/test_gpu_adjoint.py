@@ -58,6 +58,53 @@ def _rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
 
 
+def fp32_cell_bound(seg, atm_d, cnt, mu, g, land_rel=1e-5, w_rel=1e-6, w_tau=6e-7):
+    """Per-cell bound on |D_fp32 - D_oracle| implied by the FP32 photon bars.
+    A photon of weight w landing within eps = land_rel max(displacement, 1 m)
+    of the oracle's point changes its contribution c = w N exp(-d^2/2 sigma^2)
+    to a cell at distance d by at most c (|d| eps + eps^2)/sigma^2 (for
+    eps < sigma/4, where the Gaussian's log changes by |d| eps/sigma^2 +
+    eps^2/(2 sigma^2), and e^x - 1 <= 2x for x <= 1/2); its weight error adds
+    c (w_rel + w_tau tau); a photon within eps of the 4-sigma window's edge
+    may add or drop a term of at most w N e^-8 (one coordinate at the edge);
+    the float Gaussian factor adds 1e-6 c, and the 64-bit fixed-point sum
+    2^-33 of weight per photon."""
+    oatm = O.Atmosphere.from_dict(atm_d)
+    c64 = np.asarray(cnt, np.int64)
+    s_list = np.repeat(np.arange(len(c64)), c64)
+    off = np.concatenate([[0], np.cumsum(c64)])
+    j_list = np.arange(off[-1]) - off[s_list]
+    ref = O.photons(seg, oatm, "cherenkov", SEED, s_list, j_list)
+    mu_now = O.counts(seg, oatm, "cherenkov", SEED)[1]
+    mu0 = np.asarray(mu)
+    ratio = np.where(mu0 > 0, mu_now / np.where(mu0 > 0, mu0, 1.0), 0.0)[s_list]
+    land = ref["status"] == O.LANDED
+    r = ref[land]
+    w = r["weight"] * ratio[land]
+    eps = land_rel * np.maximum(np.hypot(r["xl"] - r["xe"], r["yl"] - r["ye"]), 1.0)
+    sig, reach = g["sigma"], g["trunc"] * g["sigma"]
+    assert np.all(eps < sig / 4)
+    N = 1.0 / (2.0 * np.pi * sig * sig)
+    gx = g["x_min"] + (np.arange(g["nx"]) + 0.5) * g["cell"]
+    gy = g["y_min"] + (np.arange(g["ny"]) + 0.5) * g["cell"]
+    B = np.zeros((g["ny"], g["nx"]))
+    for q in range(len(r)):
+        dx = gx - r["xl"][q]
+        dy = gy - r["yl"][q]
+        ix = np.nonzero(np.abs(dx) <= reach + eps[q])[0]
+        iy = np.nonzero(np.abs(dy) <= reach + eps[q])[0]
+        if len(ix) == 0 or len(iy) == 0:
+            continue
+        DX, DY = np.meshgrid(dx[ix], dy[iy])
+        d = np.hypot(DX, DY)
+        c = w[q] * N * np.exp(-(d * d) / (2 * sig * sig))
+        b = c * ((d * eps[q] + eps[q] ** 2) / (sig * sig) + w_rel + w_tau * r["tau"][q] + 1e-6)
+        edge = (np.abs(np.abs(DX) - reach) <= eps[q]) | (np.abs(np.abs(DY) - reach) <= eps[q])
+        b = b + edge * w[q] * N * np.exp(-8.0) * 1.01
+        B[np.ix_(iy, ix)] += b + N * 2.0**-33
+    return B
+
+
 def test_frozen_counts_and_means_match_oracle(case):
     c = case
     p = _problem(c, ph.FP64)
@@ -80,6 +127,9 @@ def test_density_matches_oracle(case, prec):
         assert np.abs(D - D0).max() <= 1e-10 * np.abs(D0).max()
     else:
         assert _rel(D, D0) <= 1e-4
+        # cell by cell, within what the FP32 photon bars allow
+        B = fp32_cell_bound(c["seg"], c["atm_d"], c["cnt"], c["mu"], c["g"])
+        assert np.all(np.abs(D - D0) <= B), (np.abs(D - D0) / np.maximum(B, 1e-300)).max()
 
 
 @pytest.mark.parametrize("prec", [ph.FP64, ph.FP32])
@@ -97,6 +147,8 @@ def test_density_at_perturbed_parameters(case, prec):
         assert np.abs(D - T).max() <= 1e-10 * np.abs(T).max()
     else:
         assert _rel(D, T) <= 1e-4
+        B = fp32_cell_bound(s1, c["atm1"], c["cnt"], c["mu"], c["g"])
+        assert np.all(np.abs(D - T) <= B), (np.abs(D - T) / np.maximum(B, 1e-300)).max()
 
 
 def _gpu_vjp(c, prec, G, grid=None, atm_d=None):
@@ -308,3 +360,71 @@ def test_full_size_sampled_segments(full, prec):
     for i in range(len(rows)):
         assert np.linalg.norm(gd[rows[i]] - rd[i]) <= tol * np.linalg.norm(rd[i]) + 1e-300, (rows[i], gd[rows[i]],
                                                                                           rd[i])
+
+
+def test_full_size_fp32_against_fp64_and_differences(full):
+    """1e6 segments, L = sum (D - T)^2 with a seeded target T of the
+    density's scale and a wide window (no jumps at its edge): the FP32 adjoint
+    against the FP64 adjoint element by element (scale heights, n0 - 1 and
+    every segment's direction gradient), and the FP64 adjoint's dL/dH_0 and
+    dL/d(n0 - 1) against five-point differences of the FP64 forward."""
+    seg, d = full
+    atm = W.default_atmosphere(absorption=True)
+    g = dict(W.splat_grid_128(), trunc=10.0)
+    p64 = ph.SplatProblem(d, atm, SEED, ph.FP64, g, *BAND)
+    p32 = ph.SplatProblem(d, atm, SEED, ph.FP32, g, *BAND)
+    a0 = ph.atmosphere(atm)
+    D = ph.splat_forward(d, a0, *BAND, SEED, ph.FP64, p64.offsets, p64.mean0, p64.grid)
+    rng = np.random.Generator(np.random.PCG64(21))
+    T = torch.as_tensor(D.cpu().numpy() * rng.uniform(0.8, 1.2, size=(g["ny"], g["nx"])), device="cuda")
+
+    def loss(atm_d):
+        Dh = ph.splat_forward(d, ph.atmosphere(atm_d), *BAND, SEED, ph.FP64, p64.offsets, p64.mean0, p64.grid)
+        return float(((Dh - T) ** 2).sum())
+
+    G = (2.0 * (D - T)).contiguous()
+    g64 = ph.splat_backward(d, a0, *BAND, SEED, ph.FP64, p64.offsets, p64.mean0, p64.grid, G)
+    g32 = ph.splat_backward(d, a0, *BAND, SEED, ph.FP32, p32.offsets, p32.mean0, p32.grid, G.float().contiguous())
+    H64, e64 = g64[0].cpu().numpy(), float(g64[1].cpu())
+    H32, e32 = g32[0].cpu().numpy(), float(g32[1].cpu())
+    print(f"dL/dH fp64 {H64} fp32 {H32}; dL/d(n0-1) {e64} {e32}", flush=True)
+    for l in (0, 1, 2):
+        assert abs(H32[l] - H64[l]) <= TOL_G32 * abs(H64[l]), l
+    assert H64[3] == H32[3] == 0.0 and H64[4] == H32[4] == 0.0
+    assert abs(e32 - e64) <= TOL_G32 * abs(e64)
+    d64 = torch.stack(g64[2:5], 1).cpu().numpy()
+    d32 = torch.stack(g32[2:5], 1).cpu().numpy()
+    n64 = np.linalg.norm(d64, axis=1)
+    err = np.linalg.norm(d32 - d64, axis=1)
+    assert np.count_nonzero(n64) > 100_000
+    # a segment's gradient sums its photons' terms of both signs (moving a
+    # landing point raises the density on one side and lowers it on the
+    # other), so the float error is relative to the terms, not to their sum:
+    # the bar is 1e-3 of the segment's gradient plus 1e-3 of the rms gradient
+    rms = np.sqrt(np.mean(n64[n64 > 0] ** 2))
+    bound = TOL_G32 * (n64 + rms)
+    print(f"direction gradients: worst error / bound {(err / bound).max():.3f}, rms {rms:.3e}, "
+          f"norm-wise {np.linalg.norm(d32 - d64) / np.linalg.norm(d64):.2e}", flush=True)
+    assert np.linalg.norm(d32 - d64) <= TOL_G32 * np.linalg.norm(d64)
+    assert np.all(err <= bound)
+
+    def fd(f, h):
+        return (8.0 * (f(h) - f(-h)) - (f(2.0 * h) - f(-2.0 * h))) / (12.0 * h)
+
+    # steps: small enough that the loss is near its tangent over +-2h (at
+    # 1e-3 (n0 - 1) the differences are still 1.2% off; at 1e-4 they agree
+    # to 1e-7), large enough that the density's 2^-32 fixed-point steps stay
+    # below the change of the loss (below 1e-6 relative they reach 1e-5)
+    H0 = np.asarray(atm["scale_height"], float)
+    for l in (0, 1):
+        def fH(h, l=l):
+            Hh = H0.copy()
+            Hh[l] += h
+            return loss(dict(atm, scale_height=Hh))
+        v = fd(fH, 1e-3 * H0[l])
+        print(f"dL/dH_{l} adjoint {H64[l]} differences {v}", flush=True)
+        assert abs(H64[l] - v) <= 1e-5 * abs(v), l
+    e0 = atm["n0_minus_1"]
+    v = fd(lambda h: loss(dict(atm, n0_minus_1=e0 + h)), 1e-4 * e0)
+    print(f"dL/d(n0-1) adjoint {e64} differences {v}", flush=True)
+    assert abs(e64 - v) <= 1e-5 * abs(v)
