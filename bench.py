@@ -55,6 +55,14 @@ SLOTS_PER_PHOTON = {"fp32": 300.0, "fp64": 750.0}
 # j) and writes 76 B (all but segment, j and lambda). The propagated block is
 # the observation-plane output in slot order.
 BLOCK_BYTES = {"gen": 92.0, "propagate": 160.0}
+# The differentiable form's algorithmic slots: the forward adds, per photon
+# landing within reach of the grid, 81 cells x (the Gaussian factor's
+# multiply, the fixed-point conversion, the LDS add) = 243; the adjoint
+# regenerates and propagates each photon and sweeps its layer pieces back
+# (twice the forward's per-photon slots) and, per photon in reach, reads
+# 81 cells of dL/dD with the weight and both position derivatives
+# (5 slots each) = 405.
+SPLAT_SLOTS = {"forward": 243.0, "adjoint": 405.0}
 COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
 # launch shapes the autotuner chooses from: (block, chunk, blocks per CU; 0 = as many as fit)
 TUNING_CANDIDATES = [(256, 3072, 0), (256, 4096, 0), (256, 8192, 0), (256, 16384, 0), (512, 8192, 0),
@@ -591,7 +599,9 @@ def differentiable(args):
         p = ph.SplatProblem(d, a, 5, prec, g)
         atm0 = ph.atmosphere(a)
         T = ph.splat_forward(d, p.atmosphere(H1, e1), 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, dirs=dirs1)
-        D = ph.splat_forward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid)
+        totals = ph.status_totals()
+        D = ph.splat_forward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, totals=totals)
+        in_reach = int(totals[ph.LANDED].item())
         G = (2.0 * (D - T)).contiguous()
         grads = ph.splat_backward(d, atm0, 300.0, 600.0, 5, prec, p.offsets, p.mean0, p.grid, G)
         torch.cuda.synchronize()
@@ -602,8 +612,19 @@ def differentiable(args):
         total = int(p.offsets[-1].item())
         out["segments"] = d.n
         out["photons"] = total
+        base = SLOTS_PER_PHOTON[name]
+        fw_slots = base * total + SPLAT_SLOTS["forward"] * in_reach
+        bw_slots = 2.0 * base * total + SPLAT_SLOTS["adjoint"] * in_reach
         out[name] = dict(forward_ms=fwd, backward_ms=bwd, forward_photons_per_s=total / (fwd * 1e-3),
-                         backward_photons_per_s=total / (bwd * 1e-3), steps=steps,
+                         backward_photons_per_s=total / (bwd * 1e-3), steps=steps, photons_in_reach=in_reach,
+                         forward_roofline=dict(bound="alu", achieved=fw_slots / (fwd * 1e-3) / 1e12,
+                                               peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+                                               frac=fw_slots / (fwd * 1e-3) / PEAK_SLOTS,
+                                               slots=f"{base:g}/photon + {SPLAT_SLOTS['forward']:g}/photon in reach"),
+                         backward_roofline=dict(bound="alu", achieved=bw_slots / (bwd * 1e-3) / 1e12,
+                                                peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+                                                frac=bw_slots / (bwd * 1e-3) / PEAK_SLOTS,
+                                                slots=f"{2 * base:g}/photon + {SPLAT_SLOTS['adjoint']:g}/photon in reach"),
                          loss=float(((D - T).double() ** 2).sum()),
                          grad_scale_height=[float(v) for v in grads[0].cpu()], grad_n0_minus_1=float(grads[1]))
         kept[name] = (D.double().cpu().numpy(), [x.double().cpu().numpy() for x in grads])
@@ -616,6 +637,36 @@ def differentiable(args):
         grad_scale_height_rel=float(np.abs(g32[0] - g64[0]).max() / np.abs(g64[0]).max()),
         grad_n0_minus_1_rel=float(abs(g32[1] - g64[1]) / abs(g64[1])),
         grad_direction_rel_norm=float(np.linalg.norm(gdir32 - gdir64) / np.linalg.norm(gdir64)))
+    return out
+
+
+def peaks(args):
+    """Measured device rates (library micro-benchmarks, best of three
+    launches) beside the nominal ones the rooflines use: FP32 and FP64 FMA
+    lanes, the 32x32->64 integer multiply-add of Philox, FP32 exp2, FMA and
+    exp2 interleaved, and HBM reads of a 2 GiB buffer."""
+    import torch
+
+    from paper_2309_15861_amd import photon as ph
+    nominal = {"fp32_fma": PEAK_SLOTS, "fp64_fma": PEAK_SLOTS, "int_mad64": PEAK_SLOTS / 4,
+               "fp32_exp2": PEAK_SLOTS / 4, "fp32_fma_exp2": PEAK_SLOTS, "hbm_read": PEAK_HBM}
+    out = {}
+    small = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    big = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
+    for k, name in enumerate(ph.PEAK_KINDS):
+        work = big if name == "hbm_read" else small
+        best = None
+        for _ in range(3):
+            ops, ms = ph.peak_run(k, work, 2048)
+            rate = ops / (ms * 1e-3)
+            best = rate if best is None or rate > best else best
+        unit = "B/s" if name == "hbm_read" else "lane-op/s"
+        out[name] = dict(measured=best, nominal=nominal[name], unit=unit, frac_of_nominal=best / nominal[name])
+    del big
+    torch.cuda.empty_cache()
+    out["note"] = ("nominal: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz for full-rate VALU operations, a quarter of it "
+                   "for 32x32->64 multiplies and transcendentals, 8 TB/s HBM; the FMA+exp2 mix can exceed one "
+                   "instruction per lane-cycle because the transcendental unit issues beside the VALU")
     return out
 
 
@@ -670,7 +721,7 @@ def main():
                     help="only run a plain 512 MiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--only", default=None,
                     help="comma-separated sections to run (profiling runs): batched32, batched64, shower, plain, "
-                         "grid, cut, table, radial, beam, adjoint")
+                         "grid, cut, table, radial, beam, adjoint, peaks")
     ap.add_argument("--tuning", default=None,
                     help="block,chunk,blocks_per_cu of the headline FP32 step instead of the autotuner's choice")
     ap.add_argument("--tuning64", default=None,
@@ -696,7 +747,7 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
         return
     sections = set(args.only.split(",")) if args.only else {
-        "batched32", "batched64", "shower", "plain", "grid", "cut", "table", "radial", "beam", "adjoint"}
+        "batched32", "batched64", "shower", "plain", "grid", "cut", "table", "radial", "beam", "adjoint", "peaks"}
     tun32 = ph.tuning(*(int(v) for v in args.tuning.split(","))) if args.tuning else None
     tun64 = ph.tuning(*(int(v) for v in args.tuning64.split(","))) if args.tuning64 else None
     forms = [f for f in (("fp32", ph.FP32, tun32), ("fp64", ph.FP64, tun64))
@@ -744,6 +795,8 @@ def main():
         out["fluorescence_beaming"] = fluorescence_beaming(args, ph.tuning(*SHOWER_FP32_TUNING))
     if "adjoint" in sections:
         out["differentiable"] = differentiable(args)
+    if "peaks" in sections:
+        out["peaks"] = peaks(args)
     if not args.no_cpu_baseline and not args.only:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

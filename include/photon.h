@@ -411,6 +411,21 @@ int photon_fused_kernel_ms(float* ms);
    that launch had none (FP64 form). Errors as photon_fused_kernel_ms. */
 int photon_fused_deferred_ms(float* ms);
 
+/* Micro-benchmark of one device rate the photon kernels' rooflines use (a
+   measurement aid): kind 0 FP32 fused multiply-adds, 1 FP64 fused
+   multiply-adds, 2 32x32->64 integer multiply-adds (the Philox rounds'
+   operation), 3 FP32 exp2 on the transcendental unit, 4 FP32 FMAs and
+   exp2 interleaved one to one, 5 reads of the device buffer `work`. ALU
+   kinds run `iters` steps of eight independent chains in every thread of
+   eight 256-thread blocks per CU and write one value per thread to `work`
+   (device, at least 2 KiB per block); kind 5 reads work[64 KiB ..
+   work_bytes) once and writes one float per block at `work`. Writes the
+   lane operations (or bytes) done to *ops and the kernel time measured with
+   HIP events on `stream` to *ms; synchronises `stream`. Errors: EINVAL
+   (kind, iters outside 1..2^20, NULL pointers, work_bytes too small). */
+int photon_peak_run(int32_t kind, void* work, int64_t work_bytes, int32_t iters, double* ops, float* ms,
+                    void* stream);
+
 /* ---- captured steps (HIP graphs) and launch-shape tuning ------------------ */
 
 /* A plan is one whole step captured into a HIP graph: per-segment counts and

@@ -17,7 +17,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
 
 
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("photon.hip", "photon_device.hpp", "photon_adjoint.hpp")] + \
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("photon.hip", "photon_device.hpp", "photon_adjoint.hpp",
+                                                   "photon_peaks.hpp")] + \
     [os.path.join(ROOT, "include", "photon.h")]
 
 

@@ -30,6 +30,7 @@
 #include "photon.h"
 #include "photon_device.hpp"
 #include "photon_adjoint.hpp"
+#include "photon_peaks.hpp"
 
 using namespace ph;
 
@@ -825,8 +826,11 @@ constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8;
 
 // Float instances are built for the waves per SIMD that their LDS allows:
 // six of 256 threads (six blocks of under 26.6 KB per CU), four of 512.
+// Double instances of 256 threads for three (167 registers, some spilled:
+// 1.6% faster on the 64-shower workload than two waves without spills; four
+// spill so much that they are 1.8x slower).
 constexpr int fused_waves_per_eu(bool fp32, int mode, int bs) {
-  return (!fp32 || (mode & kMSplat)) ? 1 : (bs == 256 ? 6 : (bs >= 512 ? 4 : 1));
+  return (mode & kMSplat) ? 1 : (!fp32 ? (bs == 256 ? 3 : 1) : (bs == 256 ? 6 : (bs >= 512 ? 4 : 1)));
 }
 
 template <typename T, int BS, int MODE = 0>
@@ -1280,7 +1284,12 @@ __device__ __forceinline__ void seg_reduce_add(long long key, double v0, double 
 // into partials (summed in a fixed order by k_adj_finalize). The float form
 // queues rays near the horizon for k_splat_adjoint_deferred.
 template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
+// Built for three waves per SIMD (float) or two (double): the spills this
+// costs are cheaper than the latency two waves (one) leave exposed (FP32
+// adjoint on the 1e6-segment workload 9.05 -> 7.70 ms, FP64 18.7 -> 12.7 ms;
+// four float waves spill too much, 9.4 ms).
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) void k_splat_adjoint(
+    AdjArgs A) {
   __shared__ uint64_t s_off[kAdjWindow + 1];
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
@@ -1383,7 +1392,8 @@ __global__ __launch_bounds__(BS) void k_splat_adjoint(AdjArgs A) {
 // defer_pref) spread evenly over the threads; block b writes its sums to
 // partial row row0 + b; direction gradients are added per photon.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_splat_adjoint_deferred(AdjArgs A, int64_t row0) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) void k_splat_adjoint_deferred(
+    AdjArgs A, int64_t row0) {
   __shared__ double s_acc[kAdjWords * BS];
   __shared__ AtmLane s_lane;
   const int tid = threadIdx.x;
@@ -2697,6 +2707,72 @@ int photon_kernel_timing(int32_t on) {
   dev->timed = false;
   dev->timed_defer = false;
   return PHOTON_OK;
+}
+
+int photon_peak_run(int32_t kind, void* work, int64_t work_bytes, int32_t iters, double* ops, float* ms,
+                    void* stream) {
+  if (kind < 0 || kind > 5) return fail(PHOTON_EINVAL, "peak kind %d outside 0..5", kind);
+  if (!work || !ops || !ms) return fail(PHOTON_EINVAL, "work/ops/ms is NULL");
+  if (iters < 1 || iters > (1 << 20)) return fail(PHOTON_EINVAL, "iters %d outside 1..2^20", iters);
+  DeviceState* dev;
+  int rc;
+  if ((rc = current_device(&dev))) return rc;
+  // eight 256-thread blocks per CU: eight waves per SIMD
+  const int64_t grid = (int64_t)dev->cu * 8;
+  const int64_t threads = grid * peaks::kBlock;
+  const int64_t out_bytes = threads * 8;
+  constexpr int64_t kReadOffset = 1 << 16;
+  if (kind < 5 && work_bytes < out_bytes)
+    return fail(PHOTON_EINVAL, "work_bytes %lld below %lld", (long long)work_bytes, (long long)out_bytes);
+  if (kind == 5 && (work_bytes < kReadOffset + (1 << 20) || grid * 4 > kReadOffset))
+    return fail(PHOTON_EINVAL, "work_bytes %lld below 64 KiB + 1 MiB", (long long)work_bytes);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(PHOTON_EHIP, "event creation failed");
+  }
+  (void)hipEventRecord(e0, st);
+  switch (kind) {
+    case 0:
+      hipLaunchKernelGGL(peaks::k_fma<float>, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st, (float*)work, iters,
+                         0.999f, 1e-4f);
+      *ops = (double)threads * iters * peaks::kChains;
+      break;
+    case 1:
+      hipLaunchKernelGGL(peaks::k_fma<double>, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st, (double*)work, iters,
+                         0.999, 1e-4);
+      *ops = (double)threads * iters * peaks::kChains;
+      break;
+    case 2:
+      hipLaunchKernelGGL(peaks::k_mad64, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st, (uint64_t*)work, iters,
+                         0xD2511F53u);
+      *ops = (double)threads * iters * peaks::kChains;
+      break;
+    case 3:
+      hipLaunchKernelGGL(peaks::k_exp2, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st, (float*)work, iters);
+      *ops = (double)threads * iters * peaks::kChains;
+      break;
+    case 4:
+      hipLaunchKernelGGL(peaks::k_mix, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st, (float*)work, iters, 0.999f,
+                         1e-4f);
+      *ops = (double)threads * iters * peaks::kChains;
+      break;
+    default: {
+      const int64_t n4 = (work_bytes - kReadOffset) / 16;
+      hipLaunchKernelGGL(peaks::k_read, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st,
+                         (const float4*)((char*)work + kReadOffset), n4, (float*)work);
+      *ops = (double)n4 * 16.0;
+    }
+  }
+  (void)hipEventRecord(e1, st);
+  rc = check_launch();
+  if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+    rc = fail(PHOTON_EHIP, "event timing failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 int photon_fused_deferred_ms(float* ms) {

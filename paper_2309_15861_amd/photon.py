@@ -134,13 +134,14 @@ def lib():
         L.photon_fused_kernel_ms.argtypes = [P]
         L.photon_fused_deferred_ms.argtypes = [P]
         L.photon_set_defer_capacity.argtypes = [C.c_int64]
+        L.photon_peak_run.argtypes = [C.c_int32, P, C.c_int64, C.c_int32, P, P, P]
         L.photon_splat_forward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.photon_splat_backward.argtypes = [P, P, C.c_double, C.c_double, C.c_uint64, C.c_int32, P, P, P, P,
                                             P, P, P, P, P, P]
         for f in ("photon_gen_cherenkov", "photon_gen_fluor", "photon_propagate", "photon_collect",
                   "photon_run_fused", "photon_run_fused_noalloc", "photon_plan_create", "photon_plan_launch", "photon_plan_destroy",
                   "photon_autotune", "photon_means", "photon_splat_forward", "photon_splat_backward",
-                  "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms", "photon_fused_deferred_ms", "photon_set_defer_capacity"):
+                  "photon_count", "photon_kernel_timing", "photon_fused_kernel_ms", "photon_fused_deferred_ms", "photon_set_defer_capacity", "photon_peak_run"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -524,6 +525,19 @@ def fused_kernel_ms() -> float:
     ms = C.c_float(0.0)
     _check(lib().photon_fused_kernel_ms(C.byref(ms)))
     return float(ms.value)
+
+
+PEAK_KINDS = ("fp32_fma", "fp64_fma", "int_mad64", "fp32_exp2", "fp32_fma_exp2", "hbm_read")
+
+
+def peak_run(kind: int, work: torch.Tensor, iters: int = 4096):
+    """One micro-benchmark launch (photon_peak_run): (lane operations or
+    bytes, kernel ms)."""
+    ops = C.c_double(0.0)
+    ms = C.c_float(0.0)
+    _check(lib().photon_peak_run(int(kind), _ptr(work), work.numel() * work.element_size(), int(iters),
+                                 C.byref(ops), C.byref(ms), _stream()))
+    return ops.value, ms.value
 
 
 def set_defer_capacity(rays: int):

@@ -354,3 +354,16 @@ def test_noalloc_entry_validates_like_run_fused(ph):
         if not torch.cuda.is_available():
             assert fn(C.byref(seg), C.byref(atm), C.byref(em), 1, 1, 0x3000, -1, C.byref(sink), None,
                       None) == ph.ENODEV
+
+
+def test_peak_run_validation(ph):
+    """The micro-benchmark entry point checks kind, iterations and pointers
+    before any device work."""
+    L = ph.lib()
+    ops, ms = C.c_double(), C.c_float()
+    assert L.photon_peak_run(6, 0x1000, 1 << 20, 16, C.byref(ops), C.byref(ms), None) == ph.EINVAL
+    assert L.photon_peak_run(0, 0x1000, 1 << 20, 0, C.byref(ops), C.byref(ms), None) == ph.EINVAL
+    assert L.photon_peak_run(0, None, 1 << 20, 16, C.byref(ops), C.byref(ms), None) == ph.EINVAL
+    assert L.photon_peak_run(0, 0x1000, 1 << 20, 16, None, C.byref(ms), None) == ph.EINVAL
+    if not torch.cuda.is_available():
+        assert L.photon_peak_run(0, 0x1000, 1 << 20, 16, C.byref(ops), C.byref(ms), None) == ph.ENODEV
