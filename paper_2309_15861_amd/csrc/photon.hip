@@ -271,27 +271,39 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
 }
 
 // In-place inclusive scan of the block totals at positions min((b+1)B, n),
-// one workgroup: thread t owns the run of R = ceil(nb/1024) consecutive
-// block totals starting at t R; it sums its run (independent loads, all in
-// flight together), the 1024 run sums are scanned across the workgroup, and
-// each thread rewrites its run with running sums (the second read hits L2).
+// one workgroup, in tiles of 1024 x P totals: each thread loads its P
+// consecutive totals into registers (all loads in flight together), the
+// thread sums are scanned across the workgroup, and each thread writes its
+// running sums back; a carry links the tiles (one tile up to 8.4e6
+// segments).
 __global__ __launch_bounds__(1024) void k_scan_tops(uint64_t* __restrict__ offsets, int64_t n, int64_t nb) {
+  constexpr int P = 32;
   __shared__ unsigned long long part[1024 / kWaveSize];
-  const int64_t R = (nb + 1023) / 1024;
-  const int64_t b0 = (int64_t)threadIdx.x * R;
-  const int64_t b1 = min(b0 + R, nb);
-  unsigned long long sum = 0;
-  for (int64_t b = b0; b < b1; ++b) sum += offsets[min((b + 1) * kScanBlock, n)];
-  const unsigned long long incl = wave_incl_scan(sum);
-  const int w = threadIdx.x / kWaveSize;
-  if (lane_id() == kWaveSize - 1) part[w] = incl;
-  __syncthreads();
-  unsigned long long run = incl - sum;
-  for (int k = 0; k < w; ++k) run += part[k];
-  for (int64_t b = b0; b < b1; ++b) {
-    const int64_t pos = min((b + 1) * kScanBlock, n);
-    run += offsets[pos];
-    offsets[pos] = run;
+  unsigned long long carry = 0;
+  for (int64_t base = 0; base < nb; base += (int64_t)1024 * P) {
+    const int64_t b0 = base + (int64_t)threadIdx.x * P;
+    unsigned long long v[P];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = (b0 + k < nb) ? offsets[min((b0 + k + 1) * kScanBlock, n)] : 0ull;
+#pragma unroll
+    for (int k = 0; k < P; ++k) sum += v[k];
+    const unsigned long long incl = wave_incl_scan(sum);
+    const int w = threadIdx.x / kWaveSize;
+    if (lane_id() == kWaveSize - 1) part[w] = incl;
+    __syncthreads();
+    unsigned long long run = carry + incl - sum, tile = 0;
+    for (int k = 0; k < 1024 / kWaveSize; ++k) {
+      if (k < w) run += part[k];
+      tile += part[k];
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      run += v[k];
+      if (b0 + k < nb) offsets[min((b0 + k + 1) * kScanBlock, n)] = run;
+    }
+    carry += tile;
+    __syncthreads();  // part[] is rewritten by the next tile
   }
   if (threadIdx.x == 0) offsets[0] = 0;
 }
@@ -1126,8 +1138,10 @@ __global__ __launch_bounds__(1024) void k_defer_scan(const unsigned long long* _
 // through propagation and collection in double. The queues of all blocks
 // are taken as one list (numbered through defer_pref), spread evenly over
 // the threads.
+// Built for two waves per SIMD: the double evaluation needs more than 256
+// registers, and at one wave per SIMD its latency is exposed.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_fused_deferred(FusedArgs A) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_deferred(FusedArgs A) {
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ double s_lines[PHOTON_MAX_LINES];
   __shared__ double s_tel[PHOTON_MAX_TELESCOPES][4];

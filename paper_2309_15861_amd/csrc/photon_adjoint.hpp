@@ -68,8 +68,16 @@ __device__ __forceinline__ void gauss_start(const SplatGeom& g, double d0, T& e0
 // in weight units.
 constexpr double kSplatUnit = 4294967296.0;  // 2^32
 
+// Float: s = v 2^32 is exact, r = its nearest integer (ties to even) is a
+// float with at most 24 significant bits, and its high and low 32-bit
+// halves are exact in float too, so the 64-bit value equals the
+// round-to-nearest conversion of s, from 32-bit conversions only.
 __device__ __forceinline__ unsigned long long to_fixed(float v) {
-  return (unsigned long long)__float2ull_rn(v * (float)kSplatUnit);
+  const float r = __builtin_rintf(v * (float)kSplatUnit);
+  const float hf = __builtin_truncf(r * 0x1p-32f);
+  const uint32_t hi = (uint32_t)hf;
+  const uint32_t lo = (uint32_t)__builtin_fmaf(-hf, 0x1p32f, r);
+  return ((unsigned long long)hi << 32) | lo;
 }
 __device__ __forceinline__ unsigned long long to_fixed(double v) { return __double2ull_rn(v * kSplatUnit); }
 
