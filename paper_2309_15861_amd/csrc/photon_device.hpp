@@ -339,7 +339,27 @@ struct Fm<double> {
     g = __builtin_fma(__builtin_fma(-g, g, x), h, g);
     return x > 0.0 ? g : (x == 0.0 ? 0.0 : __builtin_nan(""));
   }
-  static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+  // log1p: below |x| = 1/8 (the layer integrals' arguments, except on rays
+  // grazing the horizon) 2 atanh(s) with s = x/(2 + x) by its odd series,
+  // 2 s (1 + s^2/3 + ... + s^16/17) (|s| < 1/15, so the next term is below
+  // 1e-20 relative); elsewhere the library routine
+  static __device__ __forceinline__ double log1p_(double x) {
+    if (__builtin_fabs(x) < 0.125) {
+      const double s = x * rcp(2.0 + x);
+      const double s2 = s * s;
+      double q = 1.0 / 17.0;
+      q = __builtin_fma(q, s2, 1.0 / 15.0);
+      q = __builtin_fma(q, s2, 1.0 / 13.0);
+      q = __builtin_fma(q, s2, 1.0 / 11.0);
+      q = __builtin_fma(q, s2, 1.0 / 9.0);
+      q = __builtin_fma(q, s2, 1.0 / 7.0);
+      q = __builtin_fma(q, s2, 1.0 / 5.0);
+      q = __builtin_fma(q, s2, 1.0 / 3.0);
+      const double s3 = s * s2;
+      return 2.0 * __builtin_fma(s3, q, s);
+    }
+    return log1p(x);
+  }
   static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
   static __device__ __forceinline__ double exp_(double x) { return exp(x); }
 };
