@@ -343,7 +343,7 @@ def shower(args):
     return out, extra
 
 
-def plain_block(args):
+def plain_block(args, which=("plain", "shower_scale")):
     """The plain FP64 Cherenkov workload (1,000 segments) through the
     materialised photon block: counts and offsets, generation into the
     block, propagation in place (the propagated block is the observation
@@ -356,8 +356,10 @@ def plain_block(args):
     from paper_2309_15861_amd import workloads as W
     a = W.default_atmosphere(absorption=False)
     out = {}
-    for name, seg, seed, absorb in (("plain", W.plain_cherenkov(), 1, False),
-                                    ("shower_scale", W.shower_cherenkov(), 2, True)):
+    cases = {"plain": (W.plain_cherenkov, 1, False), "shower_scale": (W.shower_cherenkov, 2, True)}
+    for name in which:
+        make, seed, absorb = cases[name]
+        seg = make()
         a = W.default_atmosphere(absorption=absorb)
         d = ph.DeviceSegments(seg)
         atm = ph.atmosphere(a)
@@ -721,7 +723,7 @@ def main():
                     help="only run a plain 512 MiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--only", default=None,
                     help="comma-separated sections to run (profiling runs): batched32, batched64, shower, plain, "
-                         "grid, cut, table, radial, beam, adjoint, peaks")
+                         "blockshower, grid, cut, table, radial, beam, adjoint, peaks")
     ap.add_argument("--tuning", default=None,
                     help="block,chunk,blocks_per_cu of the headline FP32 step instead of the autotuner's choice")
     ap.add_argument("--tuning64", default=None,
@@ -747,7 +749,8 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
         return
     sections = set(args.only.split(",")) if args.only else {
-        "batched32", "batched64", "shower", "plain", "grid", "cut", "table", "radial", "beam", "adjoint", "peaks"}
+        "batched32", "batched64", "shower", "plain", "blockshower", "grid", "cut", "table", "radial", "beam", "adjoint",
+        "peaks"}
     tun32 = ph.tuning(*(int(v) for v in args.tuning.split(","))) if args.tuning else None
     tun64 = ph.tuning(*(int(v) for v in args.tuning64.split(","))) if args.tuning64 else None
     forms = [f for f in (("fp32", ph.FP32, tun32), ("fp64", ph.FP64, tun64))
@@ -777,8 +780,9 @@ def main():
     extra = None
     if "shower" in sections or sections & {"cut", "table", "radial"}:
         out["shower"], extra = shower(args)
-    if "plain" in sections:
-        out["plain_fp64_block"] = plain_block(args)
+    which = tuple(k for k, sec in (("plain", "plain"), ("shower_scale", "blockshower")) if sec in sections)
+    if which:
+        out["plain_fp64_block"] = plain_block(args, which)
     if "grid" in sections:
         out["fluorescence_grid"] = fluorescence_grid(args)
     if extra:
