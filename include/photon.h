@@ -530,9 +530,10 @@ int photon_means(const photon_segments* seg, const photon_atmosphere* atm,
    float for PHOTON_FP32), overwritten. status_totals: optional device
    u64[PHOTON_N_STATUS]; landed photons with no cell in reach count as
    OFFGRID. Cells sum w exp(-d^2/(2 sigma^2)) in 64-bit fixed point (units
-   of 2^-32 of weight) before the normalisation, so the density does not
-   depend on the order of the additions (a cell overflows only beyond 2^32
-   in weight units); each block accumulates the whole grid in LDS when it
+   of 2^-32 of weight for PHOTON_FP64, 2^-24 for PHOTON_FP32) before the
+   normalisation, so the density does not depend on the order of the
+   additions (a cell overflows only beyond 2^32 or 2^40 weight units
+   respectively); each block accumulates the whole grid in LDS when it
    fits (16384 cells on gfx950). The library keeps a per-device accumulator
    of 8 bytes per cell, grown on the first call with a larger grid; calls
    are ordered on the device as the conventions say. Errors: EINVAL (NULL

@@ -21,8 +21,8 @@ namespace ph {
 
 // ----------------------------------------------------------------- splat --
 struct SplatGeom {
-  double x_min, y_min, cell;
-  double sigma, reach, norm, inv_2s2;
+  double x_min, y_min, cell, inv_cell;
+  double reach, norm, inv_2s2;  // trunc sigma, 1/(2 pi sigma^2), 1/(2 sigma^2)
   double q;  // exp(-cell^2 / sigma^2): ratio of successive Gaussian ratios
   int32_t nx, ny;
 };
@@ -30,16 +30,19 @@ struct SplatGeom {
 // Cells along one axis within reach of coordinate x: first index i0, count
 // n, offset d0 of the first centre from x. Centres and the reach test are
 // evaluated in double without contraction, so the cell set is that of any
-// IEEE evaluation of c = lo + (i + 1/2) cell, |c - x| <= reach.
-__device__ __forceinline__ void splat_axis(double lo, double cell, int nc, double reach, double x, int& i0, int& n,
-                                           double& d0) {
+// IEEE evaluation of c = lo + (i + 1/2) cell, |c - x| <= reach. The first
+// guess of the index range takes the reciprocal of the cell (inv_cell): off
+// by at most one from the quotient, which the margin of one cell and the
+// exact tests of the loops absorb.
+__device__ __forceinline__ void splat_axis(double lo, double cell, double inv_cell, int nc, double reach, double x,
+                                           int& i0, int& n, double& d0) {
 #pragma clang fp contract(off)
   i0 = 0;
   n = 0;
   d0 = 0.0;
   if (!isfinite(x)) return;
-  double fa = floor((x - reach - lo) / cell - 0.5) - 1.0;
-  double fb = floor((x + reach - lo) / cell - 0.5) + 1.0;
+  double fa = floor((x - reach - lo) * inv_cell - 0.5) - 1.0;
+  double fb = floor((x + reach - lo) * inv_cell - 0.5) + 1.0;
   fa = fmax(fa, 0.0);
   fb = fmin(fb, (double)(nc - 1));
   if (!(fa <= fb)) return;
@@ -62,24 +65,54 @@ __device__ __forceinline__ void gauss_start(const SplatGeom& g, double d0, T& e0
 }
 
 // Fixed point of the splat accumulation: every cell sums w exp(-d^2/(2 sigma^2))
-// (the density without its normalisation) in units of 2^-32 in a 64-bit
-// integer. Integer sums do not depend on the order of the additions, and
-// integer atomics are the fast ones in LDS. A cell overflows only beyond 2^32
-// in weight units.
-constexpr double kSplatUnit = 4294967296.0;  // 2^32
+// (the density without its normalisation) in a 64-bit integer, in units of
+// 2^-32 of weight in the double form and 2^-24 in the float form (the
+// float's own resolution at weight 1: a contribution below 256 then takes one
+// rounding and one 32-bit conversion). Integer sums do not depend on the
+// order of the additions, and integer atomics are the fast ones in LDS. A
+// cell overflows only beyond 2^32 (double form) or 2^40 (float form) weight
+// units.
+template <typename T>
+__host__ __device__ constexpr double splat_unit() {
+  return sizeof(T) == 4 ? 16777216.0 : 4294967296.0;  // 2^24, 2^32
+}
 
-// Float: s = v 2^32 is exact, r = its nearest integer (ties to even) is a
-// float with at most 24 significant bits, and its high and low 32-bit
+// Float, s = v splat_unit (exact): r = its nearest integer (ties to even) is
+// a float with at most 24 significant bits, and its high and low 32-bit
 // halves are exact in float too, so the 64-bit value equals the
 // round-to-nearest conversion of s, from 32-bit conversions only.
-__device__ __forceinline__ unsigned long long to_fixed(float v) {
-  const float r = __builtin_rintf(v * (float)kSplatUnit);
+__device__ __forceinline__ unsigned long long to_fixed(float s) {
+  const float r = __builtin_rintf(s);
   const float hf = __builtin_truncf(r * 0x1p-32f);
   const uint32_t hi = (uint32_t)hf;
   const uint32_t lo = (uint32_t)__builtin_fmaf(-hf, 0x1p32f, r);
   return ((unsigned long long)hi << 32) | lo;
 }
-__device__ __forceinline__ unsigned long long to_fixed(double v) { return __double2ull_rn(v * kSplatUnit); }
+__device__ __forceinline__ unsigned long long to_fixed(double s) { return __double2ull_rn(s); }
+
+// The cells of one photon, rows iy0.. of the accumulator from row (nyw rows
+// of nxw cells), wy0 its weight in fixed-point units; NARROW: every
+// contribution is below 2^32 units (one 32-bit conversion).
+template <typename T, bool NARROW>
+__device__ __forceinline__ void splat_cells(unsigned long long* row, int nx, int nxw, int nyw, T wy0, T ex0, T rx0,
+                                            T ey, T ry, T q) {
+  for (int b = 0; b < nyw; ++b) {
+    const T wy = wy0 * ey;
+    T ex = ex0, rx = rx0;
+    for (int a = 0; a < nxw; ++a) {
+      const T v = wy * ex;
+      if constexpr (NARROW)
+        atomicAdd(&row[a], (unsigned long long)(uint32_t)__builtin_rintf(v));
+      else
+        atomicAdd(&row[a], to_fixed(v));
+      ex *= rx;
+      rx *= q;
+    }
+    row += nx;
+    ey *= ry;
+    ry *= q;
+  }
+}
 
 // Adds a photon of weight w landing at (x, y) to the fixed-point
 // accumulator acc (row-major, ny rows of nx cells). Returns false when no
@@ -88,27 +121,33 @@ template <typename T>
 __device__ __forceinline__ bool splat_add(const SplatGeom& g, double x, double y, T w, unsigned long long* acc) {
   int ix0, nxw, iy0, nyw;
   double dx0, dy0;
-  splat_axis(g.x_min, g.cell, g.nx, g.reach, x, ix0, nxw, dx0);
-  splat_axis(g.y_min, g.cell, g.ny, g.reach, y, iy0, nyw, dy0);
+  splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, ix0, nxw, dx0);
+  splat_axis(g.y_min, g.cell, g.inv_cell, g.ny, g.reach, y, iy0, nyw, dy0);
   if (nxw == 0 || nyw == 0) return false;
   T ex0, rx0, ey, ry;
   gauss_start<T>(g, dx0, ex0, rx0);
   gauss_start<T>(g, dy0, ey, ry);
   const T q = (T)g.q;
   unsigned long long* row = acc + (int64_t)iy0 * g.nx + ix0;
-  for (int b = 0; b < nyw; ++b) {
-    const T wy = w * ey;
-    T ex = ex0, rx = rx0;
-    for (int a = 0; a < nxw; ++a) {
-      atomicAdd(&row[a], to_fixed(wy * ex));
-      ex *= rx;
-      rx *= q;
-    }
-    row += g.nx;
-    ey *= ry;
-    ry *= q;
-  }
+  // the Gaussian factors are at most 1: a weight below 2^32 units bounds
+  // every contribution
+  const T ws = w * (T)splat_unit<T>();
+  if (sizeof(T) == 4 && ws < (T)4294967296.0)
+    splat_cells<T, sizeof(T) == 4>(row, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, q);
+  else
+    splat_cells<T, false>(row, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, q);
   return true;
+}
+
+// Whether a photon landing at (x, y) has a cell in reach (the test of
+// splat_add, exactly).
+__device__ __forceinline__ bool splat_reach(const SplatGeom& g, double x, double y) {
+  int i0, n;
+  double d0;
+  splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, i0, n, d0);
+  if (n == 0) return false;
+  splat_axis(g.y_min, g.cell, g.inv_cell, g.ny, g.reach, y, i0, n, d0);
+  return n != 0;
 }
 
 // Seeds of one photon from the density gradient G: dL/dx, dL/dy (through
@@ -118,8 +157,8 @@ __device__ __forceinline__ bool splat_seeds(const SplatGeom& g, double x, double
                                             T& wb) {
   int ix0, nxw, iy0, nyw;
   double dx0, dy0;
-  splat_axis(g.x_min, g.cell, g.nx, g.reach, x, ix0, nxw, dx0);
-  splat_axis(g.y_min, g.cell, g.ny, g.reach, y, iy0, nyw, dy0);
+  splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, ix0, nxw, dx0);
+  splat_axis(g.y_min, g.cell, g.inv_cell, g.ny, g.reach, y, iy0, nyw, dy0);
   if (nxw == 0 || nyw == 0) return false;
   T ex0, rx0, ey, ry;
   gauss_start<T>(g, dx0, ex0, rx0);
@@ -176,6 +215,72 @@ struct SegRaw {
   double x0, y0, z0, dx, dy, dz, len, beta, zz, mu0;
   uint32_t idx, shower;
 };
+
+// Per-segment constants of the adjoint, in double, computed once per segment
+// (adj_seg_setup): the unit track direction v and 1/|d|, the cone (cos and
+// sin of its angle, cc/sc, cc/ns), the unit bisector A of the half turn and
+// 1/|b| (0 when v points straight down), the weight ratio mu/mu0 at the
+// frozen counts and its factor d ratio/d cos, and the index at the midpoint
+// (layer lc, rho_c, eta0 rho_c) with the factors its adjoint takes to H_lc and
+// to v_z. ok: the segment emits (beta n > 1, mu0 > 0, a valid record).
+struct AdjSeg {
+  double x0, y0, z0, len;
+  double vx, vy, vz, inv_dn;
+  double cc, sc, cc_sc, cc_ns;
+  double Ax, Ay, Az, inv_bn;
+  double ratio, ratio_cc;
+  double rho_c, eta_rho_c, hfac_c, vfac_c;
+  int32_t lc;
+  uint32_t idx, shower;
+  int32_t ok;
+};
+
+// The constants of segment sg (section 1.2: index at the midpoint, cone
+// angle; the half turn about the bisector of the track and the downward
+// normal), K the Frank-Tamm factor.
+__device__ __forceinline__ void adj_seg_setup(const AtmDev& a, const AtmLane& L, const SegRaw& sg, bool valid,
+                                              double K, AdjSeg& o) {
+  o.x0 = sg.x0;
+  o.y0 = sg.y0;
+  o.z0 = sg.z0;
+  o.len = sg.len;
+  o.idx = sg.idx;
+  o.shower = sg.shower;
+  const double dn = sqrt((sg.dx * sg.dx + sg.dy * sg.dy) + sg.dz * sg.dz);
+  const double vx = sg.dx / dn, vy = sg.dy / dn, vz = sg.dz / dn;
+  o.vx = vx;
+  o.vy = vy;
+  o.vz = vz;
+  o.inv_dn = 1.0 / dn;
+  const double zc = sg.z0 + (0.5 * sg.len) * vz;
+  const int lc = layer_of(a, zc);
+  const double rho_c = L.rb[lc] * exp(-(zc - L.hb[lc]) * L.invH[lc]);
+  const double ns = 1.0 + a.eta0 * rho_c;
+  const double bn = sg.beta * ns;
+  const double cc = 1.0 / bn;
+  const double sc2 = (1.0 - cc) * (1.0 + cc);
+  o.ok = valid && sc2 > 0.0 && sg.mu0 > 0.0;
+  const double sc = sqrt(fmax(sc2, 0.0));
+  const double kzl = (K * sg.zz) * sg.len;
+  o.cc = cc;
+  o.sc = sc;
+  o.cc_sc = cc / sc;
+  o.cc_ns = cc / ns;
+  o.ratio = (kzl * (1.0 - 1.0 / (bn * bn))) / sg.mu0;
+  o.ratio_cc = -2.0 * cc * kzl / sg.mu0;
+  const double bx = vx, by = vy, bz = vz - 1.0;
+  const double bnorm = sqrt((bx * bx + by * by) + bz * bz);
+  const bool rot = bnorm > 0.0;
+  o.Ax = rot ? bx / bnorm : 1.0;
+  o.Ay = rot ? by / bnorm : 0.0;
+  o.Az = rot ? bz / bnorm : 0.0;
+  o.inv_bn = rot ? 1.0 / bnorm : 0.0;
+  o.lc = lc;
+  o.rho_c = rho_c;
+  o.eta_rho_c = a.eta0 * rho_c;
+  o.hfac_c = (zc - L.hb[lc]) * L.invH[lc] * L.invH[lc];
+  o.vfac_c = -0.5 * sg.len * L.invH[lc];
+}
 
 // Closed-form layer piece with its partial derivatives. Variables of the
 // formulas: C2 = 1 - S^2, eps_a / eps_b (n - 1 at the bottom / top), H, dh,
@@ -300,37 +405,21 @@ constexpr int kAdjNone = 0, kAdjDone = 1, kAdjDeferred = 2;
 // within about 6 degrees of the horizontal (C^2 <= 0.01), which the double
 // form finishes; with FORCE_FLOAT it evaluates them in float.
 template <typename T, typename Gt, bool FORCE_FLOAT = false>
-__device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& sg, uint32_t j, uint32_t k0,
-                              uint32_t k1, double K, double inv_l1, double inv_dl, const SplatGeom& g, const Gt* G,
-                              AdjAcc acc, double dd[3]) {
+__device__ __forceinline__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const AdjSeg& sg, uint32_t j,
+                                              uint32_t k0, uint32_t k1, double inv_l1, double inv_dl,
+                                              const SplatGeom& g, const Gt* G, AdjAcc acc, double dd[3]) {
   using F = Fm<T>;
   dd[0] = dd[1] = dd[2] = 0.0;
-  // segment (double): unit direction, index at the midpoint, cone, bisector
-  const double dn = sqrt((sg.dx * sg.dx + sg.dy * sg.dy) + sg.dz * sg.dz);
-  const double vx = sg.dx / dn, vy = sg.dy / dn, vz = sg.dz / dn;
-  const double zc = sg.z0 + (0.5 * sg.len) * vz;
-  const int lc = layer_of(a, zc);
-  const double rho_c = L.rb[lc] * exp(-(zc - L.hb[lc]) * L.invH[lc]);
-  const double ns = 1.0 + a.eta0 * rho_c;
-  const double bn = sg.beta * ns;
-  const double cc = 1.0 / bn;
-  const double sc2 = (1.0 - cc) * (1.0 + cc);
-  if (!(sc2 > 0.0) || !(sg.mu0 > 0.0)) return kAdjNone;
-  const double sc = sqrt(sc2);
-  const double kzl = (K * sg.zz) * sg.len;
-  const double ratio = (kzl * (1.0 - 1.0 / (bn * bn))) / sg.mu0;
-  const double bx = vx, by = vy, bz = vz - 1.0;
-  const double bnorm = sqrt((bx * bx + by * by) + bz * bz);
-  const bool rot = bnorm > 0.0;
-  const double Axd = rot ? bx / bnorm : 1.0, Ayd = rot ? by / bnorm : 0.0, Azd = rot ? bz / bnorm : 0.0;
+  if (!sg.ok) return kAdjNone;
+  const double vx = sg.vx, vy = sg.vy, vz = sg.vz;
 
   // photon j (section 1.2.1): cone vector, M_Rod p = 2 (A.p) A - p
   const U4 r = philox(j, sg.idx, sg.shower, kDomCher, k0, k1);
   const T u0 = u01<T>(r.w[0]), u1 = u01<T>(r.w[1]), u2 = u01<T>(r.w[2]);
   T sp, cp;
   cone_sincos(u1, &sp, &cp);
-  const T tsc = (T)sc, tcc = (T)cc;
-  const T Ax = (T)Axd, Ay = (T)Ayd, Az = (T)Azd;
+  const T tsc = (T)sg.sc, tcc = (T)sg.cc;
+  const T Ax = (T)sg.Ax, Ay = (T)sg.Ay, Az = (T)sg.Az;
   const T px = cp * tsc, py = sp * tsc, pz = -tcc;
   const T ap = Ax * px + Ay * py + Az * pz;
   T ux = (T)2 * ap * Ax - px, uy = (T)2 * ap * Ay - py, uz = (T)2 * ap * Az - pz;
@@ -396,13 +485,13 @@ __device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& s
   const double disp = (double)ne * g0;
   const double xl = xe + (double)ux * disp, yl = ye + (double)uy * disp;
   const T w = F::exp_(-kabs * col);
-  const T W = (T)ratio * w;
+  const T W = (T)sg.ratio * w;
 
   // seeds from the density gradient
   T xb, yb, Wb;
   if (!splat_seeds<T, Gt>(g, xl, yl, W, G, xb, yb, Wb)) return kAdjNone;
   const T ratio_b = Wb * w;
-  const T col_b = -kabs * w * (T)ratio * Wb;
+  const T col_b = -kabs * w * (T)sg.ratio * Wb;
   const T g0t = (T)g0;
   const T g0_b = (xb * ux + yb * uy) * ne;
   T ne_b = (xb * ux + yb * uy) * g0t;
@@ -479,29 +568,29 @@ __device__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const SegRaw& s
   const T Au = Ax * ux_b + Ay * uy_b + Az * uz_b;
   const T Axb = (T)2 * (Au * px + ap * ux_b), Ayb = (T)2 * (Au * py + ap * uy_b), Azb = (T)2 * (Au * pz + ap * uz_b);
   const T pxb = (T)2 * Au * Ax - ux_b, pyb = (T)2 * Au * Ay - uy_b, pzb = (T)2 * Au * Az - uz_b;
-  if (rot) {
+  if (sg.inv_bn > 0.0) {
     // A = b/|b|, b = v - (0, 0, 1)
-    const double AdA = Axd * (double)Axb + Ayd * (double)Ayb + Azd * (double)Azb;
-    vxb += ((double)Axb - Axd * AdA) / bnorm;
-    vyb += ((double)Ayb - Ayd * AdA) / bnorm;
-    vzb += ((double)Azb - Azd * AdA) / bnorm;
+    const double AdA = sg.Ax * (double)Axb + sg.Ay * (double)Ayb + sg.Az * (double)Azb;
+    vxb += ((double)Axb - sg.Ax * AdA) * sg.inv_bn;
+    vyb += ((double)Ayb - sg.Ay * AdA) * sg.inv_bn;
+    vzb += ((double)Azb - sg.Az * AdA) * sg.inv_bn;
   }
   // p = (cos c sin Tc, sin c sin Tc, -cos Tc); the weight ratio ~ 1 - cos^2 Tc
   const double scb = (double)(pxb * cp + pyb * sp);
-  double ccb = -(double)pzb - scb * cc / sc;
-  ccb += (double)ratio_b * (-2.0 * cc * kzl / sg.mu0);
+  double ccb = -(double)pzb - scb * sg.cc_sc;
+  ccb += (double)ratio_b * sg.ratio_cc;
   // cos Tc = 1/(beta ns), ns = 1 + eta0 rho_c, rho_c = rb[lc] exp(-(zc - hb[lc])/H[lc])
-  const double nsb = -ccb * cc / ns;
-  acc.eta(nsb * rho_c);
-  const double t = nsb * a.eta0 * rho_c;
-  acc.lnrb(lc, t);
-  acc.H(lc, t * (zc - L.hb[lc]) * L.invH[lc] * L.invH[lc]);
-  vzb += 0.5 * sg.len * (-t * L.invH[lc]);
+  const double nsb = -ccb * sg.cc_ns;
+  acc.eta(nsb * sg.rho_c);
+  const double t = nsb * sg.eta_rho_c;
+  acc.lnrb(sg.lc, t);
+  acc.H(sg.lc, t * sg.hfac_c);
+  vzb += t * sg.vfac_c;
   // v = d/|d|
   const double vdot = vx * vxb + vy * vyb + vz * vzb;
-  dd[0] = (vxb - vx * vdot) / dn;
-  dd[1] = (vyb - vy * vdot) / dn;
-  dd[2] = (vzb - vz * vdot) / dn;
+  dd[0] = (vxb - vx * vdot) * sg.inv_dn;
+  dd[1] = (vyb - vy * vdot) * sg.inv_dn;
+  dd[2] = (vzb - vz * vdot) * sg.inv_dn;
   return kAdjDone;
 }
 

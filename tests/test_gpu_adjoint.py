@@ -67,8 +67,8 @@ def fp32_cell_bound(seg, atm_d, cnt, mu, g, land_rel=1e-5, w_rel=1e-6, w_tau=6e-
     eps^2/(2 sigma^2), and e^x - 1 <= 2x for x <= 1/2); its weight error adds
     c (w_rel + w_tau tau); a photon within eps of the 4-sigma window's edge
     may add or drop a term of at most w N e^-8 (one coordinate at the edge);
-    the float Gaussian factor adds 1e-6 c, and the 64-bit fixed-point sum
-    2^-33 of weight per photon."""
+    the float Gaussian factor adds 1e-6 c, and the float form's fixed-point
+    sum (units of 2^-24 of weight) 2^-25 per photon and cell."""
     oatm = O.Atmosphere.from_dict(atm_d)
     c64 = np.asarray(cnt, np.int64)
     s_list = np.repeat(np.arange(len(c64)), c64)
@@ -101,7 +101,7 @@ def fp32_cell_bound(seg, atm_d, cnt, mu, g, land_rel=1e-5, w_rel=1e-6, w_tau=6e-
         b = c * ((d * eps[q] + eps[q] ** 2) / (sig * sig) + w_rel + w_tau * r["tau"][q] + 1e-6)
         edge = (np.abs(np.abs(DX) - reach) <= eps[q]) | (np.abs(np.abs(DY) - reach) <= eps[q])
         b = b + edge * w[q] * N * np.exp(-8.0) * 1.01
-        B[np.ix_(iy, ix)] += b + N * 2.0**-33
+        B[np.ix_(iy, ix)] += b + N * 2.0**-25
     return B
 
 
