@@ -534,7 +534,10 @@ int photon_means(const photon_segments* seg, const photon_atmosphere* atm,
    normalisation, so the density does not depend on the order of the
    additions (a cell overflows only beyond 2^32 or 2^40 weight units
    respectively); each block accumulates the whole grid in LDS when it
-   fits (16384 cells on gfx950). The library keeps a per-device accumulator
+   fits (on gfx950 up to about 37,000 cells in 32-bit words with carries
+   into the global grid for PHOTON_FP32, 17,600 cells in 64-bit words for
+   PHOTON_FP64; larger grids add to the global grid directly). The library
+   keeps a per-device accumulator
    of 8 bytes per cell, grown on the first call with a larger grid; calls
    are ordered on the device as the conventions say. Errors: EINVAL (NULL
    pointers, band, atmosphere, precision, grid). */

@@ -793,6 +793,10 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
 
 // ------------------------------------------------------------ fused kernel --
 constexpr int kWindow = 128;        // segments staged in LDS per piece of a work chunk
+constexpr int kWindowSplat32 = 96;  // the same for the float splat (two blocks and their grids per CU)
+// the float splat's launch: 768-thread blocks, two per CU (six waves per
+// SIMD), 6144-photon chunks
+constexpr int kSplatBs32 = 768, kSplatChunk32 = 6144;
 constexpr int kAdjSegWin = 64;      // segments staged in LDS per piece of a chunk of the adjoint
 constexpr int kMaxChunk = 16384;     // photons per work chunk (the slot map's size)
 constexpr int kMaxChunkSplat = 8192;
@@ -842,48 +846,9 @@ constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8;
 // 1.6% faster on the 64-shower workload than two waves without spills; four
 // spill so much that they are 1.8x slower).
 constexpr int fused_waves_per_eu(bool fp32, int mode, int bs) {
-  return (mode & kMSplat) ? 1 : (!fp32 ? (bs == 256 ? 3 : 1) : (bs == 256 ? 6 : (bs >= 512 ? 4 : 1)));
-}
-
-// A float photon into the splat accumulator: the block's LDS grid, else the
-// global one (one call per address space).
-__device__ __forceinline__ void splat_to(const SinkDev& sk, float x, float y, float w, unsigned long long* lds_acc) {
-  if (lds_acc)
-    (void)splat_add<float>(sk.sg, (double)x, (double)y, w, lds_acc);
-  else
-    (void)splat_add<float>(sk.sg, (double)x, (double)y, w, sk.splat_acc);
-}
-
-// The wave's queue of float photons in reach of the splat grid (q: LDS, x, y
-// and w of 64 entries), n entries long: the lanes of mask m (pend) append
-// their photon, and whenever 64 are queued every lane splats one, so the
-// 81-cell loops run on full waves. Returns the new length (below 64).
-__device__ __forceinline__ int splat_queue_add(const SinkDev& sk, float* q, int n, unsigned long long m, bool pend,
-                                               float x, float y, float w, unsigned long long* lds_acc) {
-  const int cnt = __popcll(m);
-  const int slot = n + (int)lanes_below(m);
-  if (pend && slot < kWaveSize) {
-    q[slot] = x;
-    q[kWaveSize + slot] = y;
-    q[2 * kWaveSize + slot] = w;
-  }
-  if (n + cnt < kWaveSize) return n + cnt;
-  // the lanes read what others of the wave wrote (a wave's LDS operations
-  // complete in order; the fence keeps the compiler from moving them)
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  const int l = lane_id();
-  const float qx = q[l], qy = q[kWaveSize + l], qw = q[2 * kWaveSize + l];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  if (pend && slot >= kWaveSize) {
-    const int k = slot - kWaveSize;
-    q[k] = x;
-    q[kWaveSize + k] = y;
-    q[2 * kWaveSize + k] = w;
-  }
-  splat_to(sk, qx, qy, qw, lds_acc);
-  return n + cnt - kWaveSize;
+  // the float splat: two blocks per CU
+  return (mode & kMSplat) ? (fp32 ? bs / 128 : 1)
+                          : (!fp32 ? (bs == 256 ? 3 : 1) : (bs == 256 ? 6 : (bs >= 512 ? 4 : 1)));
 }
 
 template <typename T, int BS, int MODE = 0>
@@ -893,7 +858,10 @@ void k_fused(FusedArgs A) {
   constexpr bool RADIAL = (MODE & kMRadial) != 0;
   constexpr bool TABLE = (MODE & kMTable) != 0;
   constexpr bool CHER = (MODE & kMFluo) == 0;
-  constexpr int kWin = kWindow;
+  // float SPLAT: the block's grid in 32-bit LDS cells with carries into the
+  // global grid, small enough for two blocks per CU
+  constexpr bool SPLAT32 = SPLAT && sizeof(T) == 4;
+  constexpr int kWin = SPLAT32 ? kWindowSplat32 : kWindow;
   // telescope tables only where a telescope sink can occur
   constexpr int kTel = (SPLAT || RADIAL) ? 1 : PHOTON_MAX_TELESCOPES;
   constexpr int kCand = (SPLAT || RADIAL) ? 1 : kCandCells * kCandCells;
@@ -919,10 +887,9 @@ void k_fused(FusedArgs A) {
   __shared__ uint32_t s_pre[kMapWords];
   __shared__ uint16_t s_slot[kWin];
   extern __shared__ unsigned long long s_splat[];  // dynamic: the block's fixed-point grid (SPLAT)
-  // float SPLAT: each wave's queue of photons in reach (splat_queue_add)
-  constexpr bool SPLAT_Q = SPLAT && sizeof(T) == 4;
-  __shared__ float s_pq[SPLAT_Q ? (BS / kWaveSize) * 3 * kWaveSize : 1];
-  int pq_n = 0;
+  // SPLAT: the waves share out each piece dynamically (photons in reach cost more)
+  constexpr bool DYN = SPLAT;
+  __shared__ unsigned int s_grab;
   constexpr bool kDefer = sizeof(T) == 4;
   const bool stage_hits = !SPLAT && !RADIAL && A.sk.kind == PHOTON_SINK_TELESCOPES;
   // the block's LDS accumulator: the splat grid, or the radial bins
@@ -934,8 +901,12 @@ void k_fused(FusedArgs A) {
     s_dcount = 0u;
     if constexpr (!SPLAT && !RADIAL) s_hs.get()->n = 0u;
   }
-  if (lds_acc)
-    for (int k = tid; k < n_cells; k += BS) lds_acc[k] = 0ull;
+  if (lds_acc) {
+    if constexpr (SPLAT32)
+      for (int k = tid; k < n_cells; k += BS) reinterpret_cast<uint32_t*>(lds_acc)[k] = 0u;
+    else
+      for (int k = tid; k < n_cells; k += BS) lds_acc[k] = 0ull;
+  }
   if (tid < PHOTON_MAX_LINES) {
     s_thr[tid] = A.g.thr[tid];
     s_lines[tid] = (T)A.g.line_nm[tid];
@@ -1003,6 +974,7 @@ void k_fused(FusedArgs A) {
         }
         if (tid == 0) s_off[W] = offsets[lo + W];
       }
+      if (DYN && tid == 0) s_grab = 0u;
       __syncthreads();
       // the piece ends where the first segment beyond the window starts
       uint64_t ce = win ? min(v1, (uint64_t)s_off[W]) : v1;
@@ -1041,13 +1013,22 @@ void k_fused(FusedArgs A) {
         }
         __syncthreads();
       }
-      // every lane runs the same number of iterations (the status ballots)
-      for (uint64_t qb = cs; qb < ce; qb += BS) {
-        const uint64_t q = qb + tid;
+      // every lane of a wave runs the same number of iterations (the status
+      // ballots); DYN: the waves take 64-photon groups of the piece from an
+      // LDS counter, so that a wave slowed by its photons (splats) takes fewer
+      for (uint32_t ng = 0;; ++ng) {
+        uint64_t qb;
+        if constexpr (DYN) {
+          unsigned int g0 = 0u;
+          if (lane_id() == 0) g0 = atomicAdd(&s_grab, (unsigned int)kWaveSize);
+          qb = cs + (uint64_t)__shfl(g0, 0, kWaveSize);
+        } else {
+          qb = cs + (uint64_t)ng * BS;
+        }
+        if (qb >= ce) break;
+        const uint64_t q = qb + (DYN ? (uint64_t)lane_id() : (uint64_t)tid);
         int st_out = -1;
         bool forced = false;
-        bool pend = false;  // SPLAT_Q: the photon joins the wave's queue
-        float px = 0.0f, py = 0.0f, pw = 0.0f;
         if (q < ce) {
           SegConst<T> c;
           uint64_t off_s;
@@ -1099,17 +1080,14 @@ void k_fused(FusedArgs A) {
             }
           }
           if (!kDefer || p.status != kDeferred) {
-            if constexpr (SPLAT_Q) {
+            if constexpr (SPLAT32) {
               st_out = p.status;
               if (st_out == PHOTON_LANDED) {
-                if (splat_reach(A.sk.sg, (double)p.x, (double)p.y)) {
-                  pend = true;
-                  px = (float)p.x;
-                  py = (float)p.y;
-                  pw = (float)p.w;
-                } else {
-                  st_out = PHOTON_OFFGRID;
-                }
+                const bool in = lds_acc ? splat_add32(A.sk.sg, (double)p.x, (double)p.y, (float)p.w,
+                                                      reinterpret_cast<uint32_t*>(lds_acc), A.sk.splat_acc)
+                                        : splat_add<float>(A.sk.sg, (double)p.x, (double)p.y, (float)p.w,
+                                                           A.sk.splat_acc);
+                if (!in) st_out = PHOTON_OFFGRID;
               }
             } else {
               st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, q,
@@ -1119,9 +1097,10 @@ void k_fused(FusedArgs A) {
         }
         pk += status_inc(st_out);
         if (kDefer && forced) pk += status_inc(PHOTON_HORIZON_FLOAT);
-        if constexpr (SPLAT_Q) {
-          const unsigned long long m = __ballot(pend);
-          if (m) pq_n = splat_queue_add(A.sk, s_pq + wave * 3 * kWaveSize, pq_n, m, pend, px, py, pw, lds_acc);
+        if (DYN && (ng & 63u) == 63u) {
+          // a lane's 8-bit counters hold 64 photons' increments
+          flush_lane_status(pk, s_stat);
+          pk = 0;
         }
       }
       // the per-lane 8-bit counters stay below 256 increments per piece
@@ -1139,18 +1118,14 @@ void k_fused(FusedArgs A) {
     const uint64_t nd = s_dcount;
     A.defer_counts[blockIdx.x] = nd < (uint64_t)A.defer_cap ? nd : (uint64_t)A.defer_cap;
   }
-  if constexpr (SPLAT_Q) {
-    // what is left in the wave's queue
-    if (pq_n > 0) {
-      const float* pq = s_pq + (tid / kWaveSize) * 3 * kWaveSize;
-      const int l = lane_id();
-      if (l < pq_n) splat_to(A.sk, pq[l], pq[kWaveSize + l], pq[2 * kWaveSize + l], lds_acc);
-    }
-    __syncthreads();
-  }
   if (lds_acc) {
     // the block's accumulator into the global one (the loop above ends with a barrier)
-    if constexpr (SPLAT) {
+    if constexpr (SPLAT32) {
+      for (int k = tid; k < n_cells; k += BS) {
+        const uint32_t v = reinterpret_cast<const uint32_t*>(lds_acc)[k];
+        if (v) atomicAdd(&A.sk.splat_acc[k], (unsigned long long)v);
+      }
+    } else if constexpr (SPLAT) {
       for (int k = tid; k < n_cells; k += BS) {
         const unsigned long long v = lds_acc[k];
         if (v) atomicAdd(&A.sk.splat_acc[k], v);
@@ -1386,6 +1361,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     AdjArgs A) {
   __shared__ uint64_t s_off[kAdjSegWin + 1];
   __shared__ AdjSeg s_seg[kAdjSegWin];
+  __shared__ unsigned int s_grab;
   __shared__ unsigned long long s_c0;
   __shared__ int64_t s_lo, s_hi;
   __shared__ double s_acc[kAdjWords * BS];  // lane-private sums: word k of thread t at k * BS + t
@@ -1430,13 +1406,20 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         if (offsets[lo + t + 1] > offsets[lo + t])
           adj_seg_setup(A.atm, s_lane, load_seg_raw(A, lo + t), seg_ok(A.seg, lo + t), A.K, s_seg[t]);
       }
+      if (tid == 0) s_grab = 0u;
       __syncthreads();
       // the piece ends where the first segment beyond the window starts (for
       // offsets that do not increase, the rest of the chunk is one piece)
       uint64_t ce = min(v1, (uint64_t)s_off[W]);
       if (!(ce > cs)) ce = v1;
-      for (uint64_t qb = cs; qb < ce; qb += BS) {
-        const uint64_t q = qb + tid;
+      // the waves take 64-photon groups of the piece from an LDS counter (a
+      // wave slowed by photons in reach takes fewer)
+      for (;;) {
+        unsigned int g0 = 0u;
+        if (lane_id() == 0) g0 = atomicAdd(&s_grab, (unsigned int)kWaveSize);
+        const uint64_t qb = cs + (uint64_t)__shfl(g0, 0, kWaveSize);
+        if (qb >= ce) break;
+        const uint64_t q = qb + (uint64_t)lane_id();
         long long key = -1 - (long long)lane_id();
         double dd[3] = {0.0, 0.0, 0.0};
         if (q < ce) {
@@ -2212,6 +2195,8 @@ int occupancy_of(DeviceState* dev, const void* fn, int bs, size_t dyn) {
 // The fused kernel instance of a mode.
 template <typename T, int BS>
 const void* fused_instance(int mode) {
+  // the float splat's own block size carries the splat instance only
+  if constexpr (BS != 128 && BS != 256 && BS != 512) return (const void*)k_fused<T, BS, kMSplat>;
   switch (mode) {
     case kMSplat: return (const void*)k_fused<T, BS, kMSplat>;
     case kMRadial: return (const void*)k_fused<T, BS, kMRadial>;
@@ -2526,7 +2511,7 @@ int enqueue_step(const StepArgs& a, uint32_t* counts, uint64_t* offsets, const p
 }
 
 // ------------------------------------------------------ differentiable form --
-constexpr int64_t kAdjChunk = 2048;
+constexpr int64_t kAdjChunk = 4096;
 
 int prep_splat_grid(const photon_splat_grid* gr, SplatGeom* g) {
   if (!gr) return fail(PHOTON_EINVAL, "splat grid is NULL");
@@ -3143,19 +3128,23 @@ int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* at
     sk.sg = c.sg;
     sk.splat_acc = dev->splat_acc;
     sk.mu0 = mean0;
-    // each block accumulates the whole grid in LDS when it fits beside the kernel's own LDS
-    const size_t lds = (size_t)cells * sizeof(unsigned long long);
+    // each block accumulates the whole grid in LDS when it fits beside the
+    // kernel's own LDS: 32-bit cells in the float form (splat_add32; two
+    // 768-thread blocks per CU for a 128 x 128 grid), 64-bit cells in the
+    // double form (one 512-thread block per CU)
+    const size_t lds = (size_t)cells * (precision == PHOTON_FP32 ? sizeof(uint32_t) : sizeof(unsigned long long));
     hipFuncAttributes fa;
-    const void* kf = precision == PHOTON_FP32 ? reinterpret_cast<const void*>(&k_fused<float, 1024, kMSplat>)
+    const void* kf = precision == PHOTON_FP32 ? reinterpret_cast<const void*>(&k_fused<float, kSplatBs32, kMSplat>)
                                               : reinterpret_cast<const void*>(&k_fused<double, 512, kMSplat>);
     const bool fits = hipFuncGetAttributes(&fa, kf) == hipSuccess && fa.sharedSizeBytes + lds <= dev->lds_per_block;
     sk.splat_lds = fits ? 1 : 0;
-    // 8192-photon chunks: with one block per CU (the grid fills its LDS) the
-    // block's serial set-up of a chunk (work cursor, segment search, window)
-    // is hidden by no other block, so fewer, larger chunks pay (1e6-segment
-    // workload, 4096 -> 8192: FP32 4.39 -> 3.85 ms, FP64 7.02 -> 6.55 ms)
+    // large chunks: a block's serial set-up of a chunk (work cursor, segment
+    // search, window) is hidden by few or no other blocks (1e6-segment
+    // workload, FP64 4096 -> 8192 photons: 7.02 -> 6.55 ms; FP32 3072 -> 6144:
+    // 3.86 -> 3.52 ms)
     if (precision == PHOTON_FP32)
-      rc = fits ? launch_fused_bs<float, 1024, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 8192, 0, sk, dev, st, lds)
+      rc = fits ? launch_fused_bs<float, kSplatBs32, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, kSplatChunk32, 0, sk,
+                                                           dev, st, lds)
                 : launch_fused_bs<float, 256, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 4096, 0, sk, dev, st);
     else
       rc = fits ? launch_fused_bs<double, 512, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, 8192, 0, sk, dev, st, lds)

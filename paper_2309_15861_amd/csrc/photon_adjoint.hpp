@@ -139,6 +139,59 @@ __device__ __forceinline__ bool splat_add(const SplatGeom& g, double x, double y
   return true;
 }
 
+// The float form's block accumulator in LDS with 32-bit cells (units of
+// 2^-24 of weight, as splat_add): the adds return the old value, and a wrap
+// past 2^32 carries 2^32 into the global 64-bit cell (gacc), so that the
+// global cell plus the LDS cell is the exact 64-bit sum. NARROW: every
+// contribution is below 2^32 units; otherwise each one's high word goes to
+// the global cell directly.
+template <bool NARROW>
+__device__ __forceinline__ void splat_cells32(uint32_t* row, unsigned long long* grow, int nx, int nxw, int nyw,
+                                              float wy0, float ex0, float rx0, float ey, float ry, float q) {
+  for (int b = 0; b < nyw; ++b) {
+    const float wy = wy0 * ey;
+    float ex = ex0, rx = rx0;
+    for (int a = 0; a < nxw; ++a) {
+      const float v = wy * ex;
+      uint32_t lo;
+      if constexpr (NARROW) {
+        lo = (uint32_t)__builtin_rintf(v);
+      } else {
+        const unsigned long long f = to_fixed(v);
+        lo = (uint32_t)f;
+        if (f >> 32) atomicAdd(&grow[a], f & 0xffffffff00000000ull);
+      }
+      const uint32_t old = atomicAdd(&row[a], lo);
+      if (old > 0xffffffffu - lo) atomicAdd(&grow[a], 1ull << 32);
+      ex *= rx;
+      rx *= q;
+    }
+    row += nx;
+    grow += nx;
+    ey *= ry;
+    ry *= q;
+  }
+}
+
+__device__ __forceinline__ bool splat_add32(const SplatGeom& g, double x, double y, float w, uint32_t* acc,
+                                            unsigned long long* gacc) {
+  int ix0, nxw, iy0, nyw;
+  double dx0, dy0;
+  splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, ix0, nxw, dx0);
+  splat_axis(g.y_min, g.cell, g.inv_cell, g.ny, g.reach, y, iy0, nyw, dy0);
+  if (nxw == 0 || nyw == 0) return false;
+  float ex0, rx0, ey, ry;
+  gauss_start<float>(g, dx0, ex0, rx0);
+  gauss_start<float>(g, dy0, ey, ry);
+  const int64_t base = (int64_t)iy0 * g.nx + ix0;
+  const float ws = w * (float)splat_unit<float>();
+  if (ws < 4294967296.0f)
+    splat_cells32<true>(acc + base, gacc + base, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, (float)g.q);
+  else
+    splat_cells32<false>(acc + base, gacc + base, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, (float)g.q);
+  return true;
+}
+
 // Whether a photon landing at (x, y) has a cell in reach (the test of
 // splat_add, exactly).
 __device__ __forceinline__ bool splat_reach(const SplatGeom& g, double x, double y) {

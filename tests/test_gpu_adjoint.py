@@ -160,6 +160,33 @@ def _gpu_vjp(c, prec, G, grid=None, atm_d=None):
     return gH.cpu().numpy(), float(ge.cpu()), gd
 
 
+@pytest.mark.parametrize("k", [200.0, 1.0e4])
+def test_fp32_fixed_point_carries(case, k):
+    """Frozen means divided by k multiply every photon's weight by k. At
+    k = 200 (weights below 256) each cell of the float form's 32-bit LDS grid
+    takes one conversion, and the cell sums pass 2^32 units: the densest cell
+    holds more than 256 weight units per 3072 photons, so any split of the
+    photons into chunks of at least that size wraps a cell in some block and
+    carries into the global grid. At k = 1e4 single contributions pass 2^32
+    units (their high words go to the global grid directly). The float
+    density must still match the double one (whose 64-bit cells never wrap)
+    to the FP32 bar."""
+    c = case
+    p32, p64 = _problem(c, ph.FP32), _problem(c, ph.FP64)
+    N = 1.0 / (2.0 * np.pi * c["g"]["sigma"] ** 2)
+    atm = ph.atmosphere(c["atm_d"])
+    D = {}
+    for prec, p in ((ph.FP32, p32), (ph.FP64, p64)):
+        m0 = (p.mean0 / k).contiguous()
+        D[prec] = ph.splat_forward(c["d"], atm, *BAND, SEED, prec, p.offsets, m0, p.grid).double().cpu().numpy()
+    photons = int(c["cnt"].sum())
+    if k == 200.0:
+        assert D[ph.FP64].max() / N > 256.0 * (photons / 3072.0 + 1.0)
+    assert np.abs(D[ph.FP64] - k * c["D0"]).max() <= 1e-10 * k * np.abs(c["D0"]).max()
+    assert _rel(D[ph.FP32], D[ph.FP64]) <= 1e-4
+    assert np.abs(D[ph.FP32] - D[ph.FP64]).max() <= 1e-4 * np.abs(D[ph.FP64]).max()
+
+
 def test_adjoint_fp64_matches_reference(case):
     c = case
     gH, ge, gd = _gpu_vjp(c, ph.FP64, c["G"])
