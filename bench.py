@@ -42,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9          # VALU lane-slots/s: CUs x SIMDs x lanes x clock
 PEAK_HBM = 8.0e12                          # B/s
+PEAK_LDS_BYTES = 256 * 128 * 2.4e9         # B/s of LDS: CUs x 128 B per clock x clock
 # Algorithmic VALU issue slots per photon (quarter-rate operations count 4):
 # Philox4x32-10 (10 rounds of two 32x32->64 multiplies and two 3-way xors,
 # ~100-120), uniforms (~8), cone/rotation/translation/wavelength (~30),
@@ -646,12 +647,14 @@ def peaks(args):
     """Measured device rates (library micro-benchmarks, best of three
     launches) beside the nominal ones the rooflines use: FP32 and FP64 FMA
     lanes, the 32x32->64 integer multiply-add of Philox, FP32 exp2, FMA and
-    exp2 interleaved, and HBM reads of a 2 GiB buffer."""
+    exp2 interleaved, HBM reads of a 2 GiB buffer, and the splat's LDS
+    integer adds (32-bit returning, 64-bit)."""
     import torch
 
     from paper_2309_15861_amd import photon as ph
     nominal = {"fp32_fma": PEAK_SLOTS, "fp64_fma": PEAK_SLOTS, "int_mad64": PEAK_SLOTS / 4,
-               "fp32_exp2": PEAK_SLOTS / 4, "fp32_fma_exp2": PEAK_SLOTS, "hbm_read": PEAK_HBM}
+               "fp32_exp2": PEAK_SLOTS / 4, "fp32_fma_exp2": PEAK_SLOTS, "hbm_read": PEAK_HBM,
+               "lds_add32_rtn": PEAK_LDS_BYTES / 4, "lds_add64": PEAK_LDS_BYTES / 8}
     out = {}
     small = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
     big = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
@@ -667,8 +670,9 @@ def peaks(args):
     del big
     torch.cuda.empty_cache()
     out["note"] = ("nominal: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz for full-rate VALU operations, a quarter of it "
-                   "for 32x32->64 multiplies and transcendentals, 8 TB/s HBM; the FMA+exp2 mix can exceed one "
-                   "instruction per lane-cycle because the transcendental unit issues beside the VALU")
+                   "for 32x32->64 multiplies and transcendentals, 8 TB/s HBM, 128 B per clock per CU of LDS for "
+                   "the LDS adds; the FMA+exp2 mix can exceed one instruction per lane-cycle because the "
+                   "transcendental unit issues beside the VALU")
     return out
 
 

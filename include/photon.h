@@ -415,10 +415,13 @@ int photon_fused_deferred_ms(float* ms);
    measurement aid): kind 0 FP32 fused multiply-adds, 1 FP64 fused
    multiply-adds, 2 32x32->64 integer multiply-adds (the Philox rounds'
    operation), 3 FP32 exp2 on the transcendental unit, 4 FP32 FMAs and
-   exp2 interleaved one to one, 5 reads of the device buffer `work`. ALU
-   kinds run `iters` steps of eight independent chains in every thread of
-   eight 256-thread blocks per CU and write one value per thread to `work`
-   (device, at least 2 KiB per block); kind 5 reads work[64 KiB ..
+   exp2 interleaved one to one, 5 reads of the device buffer `work`, 6 LDS
+   32-bit integer adds returning the old value (the float splat's cell
+   update), 7 LDS 64-bit integer adds (the double splat's), each wave's lanes
+   on consecutive words. ALU and LDS kinds run `iters` steps of eight
+   independent chains in every thread of eight 256-thread blocks per CU and
+   write one value per thread to `work` (device, at least 2 KiB per block);
+   kind 5 reads work[64 KiB ..
    work_bytes) once and writes one float per block at `work`. Writes the
    lane operations (or bytes) done to *ops and the kernel time measured with
    HIP events on `stream` to *ms; synchronises `stream`. Errors: EINVAL

@@ -887,8 +887,16 @@ void k_fused(FusedArgs A) {
   __shared__ uint32_t s_pre[kMapWords];
   __shared__ uint16_t s_slot[kWin];
   extern __shared__ unsigned long long s_splat[];  // dynamic: the block's fixed-point grid (SPLAT)
-  // SPLAT: the waves share out each piece dynamically (photons in reach cost more)
-  constexpr bool DYN = SPLAT;
+  // SPLAT: the waves share out each piece dynamically (photons in reach cost
+  // more); double fluorescence (REFILL): lanes whose photon leaves upwards
+  // take another photon of the piece before the propagation (fluorescence
+  // step 5.66 -> 5.50 ms; in the float form the extra registers spill and
+  // the step is 15% slower)
+  constexpr bool REFILL = !CHER && sizeof(T) == 8;
+  constexpr bool DYN = SPLAT || REFILL;
+  // not for the plane sink, which writes a record of every photon
+  const bool refill = REFILL && A.sk.kind != PHOTON_SINK_PLANE;
+  constexpr bool LATE = (sizeof(T) == 4 && CHER && !SPLAT) || REFILL;
   __shared__ unsigned int s_grab;
   constexpr bool kDefer = sizeof(T) == 4;
   const bool stage_hits = !SPLAT && !RADIAL && A.sk.kind == PHOTON_SINK_TELESCOPES;
@@ -1026,17 +1034,16 @@ void k_fused(FusedArgs A) {
           qb = cs + (uint64_t)ng * BS;
         }
         if (qb >= ce) break;
-        const uint64_t q = qb + (DYN ? (uint64_t)lane_id() : (uint64_t)tid);
+        const uint64_t q0 = qb + (DYN ? (uint64_t)lane_id() : (uint64_t)tid);
         int st_out = -1;
         bool forced = false;
-        if (q < ce) {
-          SegConst<T> c;
+        // photon qq of the piece: its segment (from the window's slot map, or
+        // looked up in global memory) and the photon itself
+        auto fetch = [&](uint64_t qq, SegConst<T>& c, int64_t& s, uint32_t& j, T& wsc, Photon<T>& p) {
           uint64_t off_s;
-          int64_t s;
-          T wsc = (T)1;
           if (win) {
-            // starts at or before q, counted from the map
-            const uint64_t i = q - cs;
+            // starts at or before qq, counted from the map
+            const uint64_t i = qq - cs;
             const int a = s_slot[s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull))];
             c = s_seg[a];
             if constexpr (SPLAT) wsc = s_wsc[a];
@@ -1046,14 +1053,16 @@ void k_fused(FusedArgs A) {
             asm volatile("" : "+v"(off_s));
             s = lo + a;
           } else {
-            s = lane_upper_index(offsets, n_seg, q);
+            s = lane_upper_index(offsets, n_seg, qq);
             seg_const<T>(A.seg, s, A.atm, cher, A.g.beam, c);
             if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
             off_s = offsets[s];
           }
-          const uint32_t j = (uint32_t)(q - off_s);
-          Photon<T> p;
+          j = (uint32_t)(qq - off_s);
           generate_kind<T, CHER>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
+        };
+        // its propagation and sink
+        auto finish = [&](const SegConst<T>& c, int64_t s, uint32_t j, T wsc, Photon<T>& p, uint64_t qq) {
           propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p, c.layer);
           if constexpr (SPLAT) p.w *= wsc;
           if (kDefer) {
@@ -1090,8 +1099,128 @@ void k_fused(FusedArgs A) {
                 if (!in) st_out = PHOTON_OFFGRID;
               }
             } else {
-              st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, q,
+              st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, qq,
                                                      stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
+            }
+          }
+        };
+        // Two arrangements of the same work, chosen by measurement: the
+        // photon's state declared outside the lane's test and the two steps
+        // as the calls above (LATE) make the float Cherenkov forms faster
+        // (64-shower FP32 kernel 22.9 -> 21.3 ms) and the double ones and
+        // the float splat slower (85.3 -> 92.0 ms; 3.39 -> 3.53 ms), which
+        // keep the steps written out inside the test (the same statements as
+        // fetch and finish); the refill needs LATE.
+        if constexpr (LATE) {
+          uint64_t q = q0;
+          bool have = q < ce;
+          SegConst<T> c;
+          int64_t s = 0;
+          uint32_t j = 0;
+          T wsc = (T)1;
+          Photon<T> p;
+          if constexpr (REFILL) {
+            // a photon that leaves upwards or starts below h_obs ends after
+            // its generation (the status propagate would give it), and its
+            // lane takes another photon of the piece (one more round), so that
+            // fewer lanes idle in the propagation (one inlined generation)
+            bool need = have;
+            const int rounds = refill ? 2 : 1;
+#pragma unroll 1
+            for (int r = 0;;) {
+              if (need) fetch(q, c, s, j, wsc, p);
+              if (++r == rounds) break;
+              const bool gone = have && p.status == PHOTON_LANDED && (!(p.uz < (T)0) || p.z < A.atm.hobs);
+              const unsigned long long m = __ballot(gone);
+              if (!m) break;
+              if (gone) pk += status_inc(!(p.uz < (T)0) ? PHOTON_UP : PHOTON_BELOW);
+              unsigned int g1 = 0u;
+              if (lane_id() == 0) g1 = atomicAdd(&s_grab, (unsigned int)__popcll(m));
+              g1 = (unsigned int)__shfl((int)g1, 0, kWaveSize);
+              need = false;
+              if (gone) {
+                q = cs + (uint64_t)g1 + lanes_below(m);
+                have = q < ce;
+                need = have;
+              }
+            }
+          }
+          if (have) {
+            if constexpr (!REFILL) fetch(q, c, s, j, wsc, p);
+            finish(c, s, j, wsc, p, q);
+          }
+        } else {
+          if (q0 < ce) {
+            SegConst<T> c;
+            int64_t s;
+            uint32_t j;
+            T wsc = (T)1;
+            Photon<T> p;
+            {
+              const uint64_t qq = q0;
+              uint64_t off_s;
+              if (win) {
+                // starts at or before qq, counted from the map
+                const uint64_t i = qq - cs;
+                const int a = s_slot[s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull))];
+                c = s_seg[a];
+                if constexpr (SPLAT) wsc = s_wsc[a];
+                off_s = s_off[a];
+                // keeps the LDS load and the global one below apart (merged,
+                // they would become one generic load through a selected pointer)
+                asm volatile("" : "+v"(off_s));
+                s = lo + a;
+              } else {
+                s = lane_upper_index(offsets, n_seg, qq);
+                seg_const<T>(A.seg, s, A.atm, cher, A.g.beam, c);
+                if constexpr (SPLAT) wsc = splat_wscale<T>(A, s);
+                off_s = offsets[s];
+              }
+              j = (uint32_t)(qq - off_s);
+              generate_kind<T, CHER>(c, j, A.g, A.k0, A.k1, s_thr, s_lines, p);
+            }
+            {
+              const uint64_t qq = q0;
+              propagate<T, kDefer, false, TABLE>(A.atm, s_lane, p, c.layer);
+              if constexpr (SPLAT) p.w *= wsc;
+              if (kDefer) {
+                const bool defer = p.status == kDeferred;
+                const unsigned long long m = __ballot(defer);
+                if (m) {
+                  // the block's own queue: one LDS atomic per wave
+                  const int leader = __ffsll((long long)m) - 1;
+                  unsigned int base = 0;
+                  if (lane_id() == leader) base = atomicAdd(&s_dcount, (unsigned int)__popcll(m));
+                  base = lane_value(base, leader);
+                  if (defer) {
+                    const uint64_t slot = (uint64_t)base + lanes_below(m);
+                    if (slot < (uint64_t)A.defer_cap) {
+                      A.defer_q[(uint64_t)blockIdx.x * (uint64_t)A.defer_cap + slot] = make_uint2((uint32_t)s, j);
+                    } else {
+                      // queue full: this ray is evaluated here after all, in
+                      // double as the photon-block path does
+                      p.status = PHOTON_LANDED;
+                      propagate<T>(A.atm, s_lane, p, c.layer);
+                      forced = true;
+                    }
+                  }
+                }
+              }
+              if (!kDefer || p.status != kDeferred) {
+                if constexpr (SPLAT32) {
+                  st_out = p.status;
+                  if (st_out == PHOTON_LANDED) {
+                    const bool in = lds_acc ? splat_add32(A.sk.sg, (double)p.x, (double)p.y, (float)p.w,
+                                                          reinterpret_cast<uint32_t*>(lds_acc), A.sk.splat_acc)
+                                            : splat_add<float>(A.sk.sg, (double)p.x, (double)p.y, (float)p.w,
+                                                               A.sk.splat_acc);
+                    if (!in) st_out = PHOTON_OFFGRID;
+                  }
+                } else {
+                  st_out = sink_photon<T, SPLAT, RADIAL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, qq,
+                                                         stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
+                }
+              }
             }
           }
         }
@@ -2196,17 +2325,20 @@ int occupancy_of(DeviceState* dev, const void* fn, int bs, size_t dyn) {
 template <typename T, int BS>
 const void* fused_instance(int mode) {
   // the float splat's own block size carries the splat instance only
-  if constexpr (BS != 128 && BS != 256 && BS != 512) return (const void*)k_fused<T, BS, kMSplat>;
-  switch (mode) {
-    case kMSplat: return (const void*)k_fused<T, BS, kMSplat>;
-    case kMRadial: return (const void*)k_fused<T, BS, kMRadial>;
-    case kMTable: return (const void*)k_fused<T, BS, kMTable>;
-    case kMRadial | kMTable: return (const void*)k_fused<T, BS, kMRadial | kMTable>;
-    case kMFluo: return (const void*)k_fused<T, BS, kMFluo>;
-    case kMFluo | kMRadial: return (const void*)k_fused<T, BS, kMFluo | kMRadial>;
-    case kMFluo | kMTable: return (const void*)k_fused<T, BS, kMFluo | kMTable>;
-    case kMFluo | kMRadial | kMTable: return (const void*)k_fused<T, BS, kMFluo | kMRadial | kMTable>;
-    default: return (const void*)k_fused<T, BS, 0>;
+  if constexpr (BS != 128 && BS != 256 && BS != 512) {
+    return (const void*)k_fused<T, BS, kMSplat>;
+  } else {
+    switch (mode) {
+      case kMSplat: return (const void*)k_fused<T, BS, kMSplat>;
+      case kMRadial: return (const void*)k_fused<T, BS, kMRadial>;
+      case kMTable: return (const void*)k_fused<T, BS, kMTable>;
+      case kMRadial | kMTable: return (const void*)k_fused<T, BS, kMRadial | kMTable>;
+      case kMFluo: return (const void*)k_fused<T, BS, kMFluo>;
+      case kMFluo | kMRadial: return (const void*)k_fused<T, BS, kMFluo | kMRadial>;
+      case kMFluo | kMTable: return (const void*)k_fused<T, BS, kMFluo | kMTable>;
+      case kMFluo | kMRadial | kMTable: return (const void*)k_fused<T, BS, kMFluo | kMRadial | kMTable>;
+      default: return (const void*)k_fused<T, BS, 0>;
+    }
   }
 }
 
@@ -2793,7 +2925,7 @@ int photon_kernel_timing(int32_t on) {
 
 int photon_peak_run(int32_t kind, void* work, int64_t work_bytes, int32_t iters, double* ops, float* ms,
                     void* stream) {
-  if (kind < 0 || kind > 5) return fail(PHOTON_EINVAL, "peak kind %d outside 0..5", kind);
+  if (kind < 0 || kind > 7) return fail(PHOTON_EINVAL, "peak kind %d outside 0..7", kind);
   if (!work || !ops || !ms) return fail(PHOTON_EINVAL, "work/ops/ms is NULL");
   if (iters < 1 || iters > (1 << 20)) return fail(PHOTON_EINVAL, "iters %d outside 1..2^20", iters);
   DeviceState* dev;
@@ -2804,7 +2936,7 @@ int photon_peak_run(int32_t kind, void* work, int64_t work_bytes, int32_t iters,
   const int64_t threads = grid * peaks::kBlock;
   const int64_t out_bytes = threads * 8;
   constexpr int64_t kReadOffset = 1 << 16;
-  if (kind < 5 && work_bytes < out_bytes)
+  if (kind != 5 && work_bytes < out_bytes)
     return fail(PHOTON_EINVAL, "work_bytes %lld below %lld", (long long)work_bytes, (long long)out_bytes);
   if (kind == 5 && (work_bytes < kReadOffset + (1 << 20) || grid * 4 > kReadOffset))
     return fail(PHOTON_EINVAL, "work_bytes %lld below 64 KiB + 1 MiB", (long long)work_bytes);
@@ -2839,6 +2971,16 @@ int photon_peak_run(int32_t kind, void* work, int64_t work_bytes, int32_t iters,
     case 4:
       hipLaunchKernelGGL(peaks::k_mix, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st, (float*)work, iters, 0.999f,
                          1e-4f);
+      *ops = (double)threads * iters * peaks::kChains;
+      break;
+    case 6:
+      hipLaunchKernelGGL(peaks::k_lds_add32, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st, (uint32_t*)work,
+                         iters);
+      *ops = (double)threads * iters * peaks::kChains;
+      break;
+    case 7:
+      hipLaunchKernelGGL(peaks::k_lds_add64, dim3((unsigned)grid), dim3(peaks::kBlock), 0, st,
+                         (unsigned long long*)work, iters);
       *ops = (double)threads * iters * peaks::kChains;
       break;
     default: {

@@ -1,9 +1,10 @@
 // Micro-benchmarks of the device rates that bound the photon kernels: FP32
 // and FP64 fused multiply-adds, the 32x32->64 integer multiply-add of the
 // Philox rounds, the FP32 transcendental unit (exp2), FMAs and exp2
-// interleaved (the two can issue side by side), and HBM reads. A measurement
-// aid for the rooflines (their nominal peaks come from unit counts and
-// clock); nothing on the photon path uses them.
+// interleaved (the two can issue side by side), HBM reads, and the LDS
+// integer adds of the splat (32-bit returning the old value, 64-bit without).
+// A measurement aid for the rooflines (their nominal peaks come from unit
+// counts and clock); nothing on the photon path uses them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -108,6 +109,40 @@ __global__ __launch_bounds__(kBlock) void k_read(const float4* __restrict__ in, 
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) out[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// LDS integer adds in the splat's pattern along a row: the lanes of a wave
+// add to consecutive words (no two lanes of a wave on one bank beyond what
+// the word size implies), eight chains per thread. 32-bit: the float splat's
+// cell update, which returns the old value (summed, so the adds stay live).
+constexpr int kLdsWords32 = 4096;  // 16 KB per block
+__global__ __launch_bounds__(kBlock) void k_lds_add32(uint32_t* __restrict__ out, int iters) {
+  __shared__ uint32_t s[kLdsWords32];
+  for (int k = threadIdx.x; k < kLdsWords32; k += kBlock) s[k] = 0u;
+  __syncthreads();
+  uint32_t acc = 0u;
+  for (int i = 0; i < iters; ++i) {
+    const int base = (int)threadIdx.x + (i & 1) * (kLdsWords32 / 2);
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) acc += atomicAdd(&s[(base + k * kBlock) & (kLdsWords32 - 1)], 1u + k);
+  }
+  __syncthreads();
+  out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = acc + s[threadIdx.x];
+}
+
+// 64-bit adds without a returned value: the double splat's cell update.
+constexpr int kLdsWords64 = 2048;  // 16 KB per block
+__global__ __launch_bounds__(kBlock) void k_lds_add64(unsigned long long* __restrict__ out, int iters) {
+  __shared__ unsigned long long s[kLdsWords64];
+  for (int k = threadIdx.x; k < kLdsWords64; k += kBlock) s[k] = 0ull;
+  __syncthreads();
+  for (int i = 0; i < iters; ++i) {
+    const int base = (int)threadIdx.x + (i & 1) * (kLdsWords64 / 2);
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) atomicAdd(&s[(base + k * kBlock) & (kLdsWords64 - 1)], 1ull + k);
+  }
+  __syncthreads();
+  out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s[threadIdx.x];
 }
 
 }  // namespace peaks

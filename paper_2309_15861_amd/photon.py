@@ -527,7 +527,8 @@ def fused_kernel_ms() -> float:
     return float(ms.value)
 
 
-PEAK_KINDS = ("fp32_fma", "fp64_fma", "int_mad64", "fp32_exp2", "fp32_fma_exp2", "hbm_read")
+PEAK_KINDS = ("fp32_fma", "fp64_fma", "int_mad64", "fp32_exp2", "fp32_fma_exp2", "hbm_read", "lds_add32_rtn",
+              "lds_add64")
 
 
 def peak_run(kind: int, work: torch.Tensor, iters: int = 4096):

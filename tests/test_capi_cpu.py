@@ -361,7 +361,8 @@ def test_peak_run_validation(ph):
     before any device work."""
     L = ph.lib()
     ops, ms = C.c_double(), C.c_float()
-    assert L.photon_peak_run(6, 0x1000, 1 << 20, 16, C.byref(ops), C.byref(ms), None) == ph.EINVAL
+    assert L.photon_peak_run(8, 0x1000, 1 << 20, 16, C.byref(ops), C.byref(ms), None) == ph.EINVAL
+    assert L.photon_peak_run(-1, 0x1000, 1 << 20, 16, C.byref(ops), C.byref(ms), None) == ph.EINVAL
     assert L.photon_peak_run(0, 0x1000, 1 << 20, 0, C.byref(ops), C.byref(ms), None) == ph.EINVAL
     assert L.photon_peak_run(0, None, 1 << 20, 16, C.byref(ops), C.byref(ms), None) == ph.EINVAL
     assert L.photon_peak_run(0, 0x1000, 1 << 20, 16, None, C.byref(ms), None) == ph.EINVAL
