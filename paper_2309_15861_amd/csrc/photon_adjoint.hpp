@@ -90,6 +90,12 @@ __device__ __forceinline__ unsigned long long to_fixed(float s) {
 }
 __device__ __forceinline__ unsigned long long to_fixed(double s) { return __double2ull_rn(s); }
 
+// Rows of at most kSplatCols cells (a 4-sigma window of cells no narrower
+// than sigma) take unrolled rows: the column factors e_a come once per photon
+// from the same recurrence (the same products, so the same values), and each
+// cell costs a multiply, a conversion and the LDS add at an immediate offset.
+constexpr int kSplatCols = 9;
+
 // The cells of one photon, rows iy0.. of the accumulator from row (nyw rows
 // of nxw cells), wy0 its weight in fixed-point units; NARROW: every
 // contribution is below 2^32 units (one 32-bit conversion).
@@ -107,6 +113,38 @@ __device__ __forceinline__ void splat_cells(unsigned long long* row, int nx, int
         atomicAdd(&row[a], to_fixed(v));
       ex *= rx;
       rx *= q;
+    }
+    row += nx;
+    ey *= ry;
+    ry *= q;
+  }
+}
+
+// The same in unrolled rows of at most kSplatCols cells.
+template <typename T, bool NARROW>
+__device__ __forceinline__ void splat_cells_rows(unsigned long long* row, int nx, int nxw, int nyw, T wy0, T ex0,
+                                                 T rx0, T ey, T ry, T q) {
+  T ea[kSplatCols];
+  {
+    T ex = ex0, rx = rx0;
+#pragma unroll
+    for (int a = 0; a < kSplatCols; ++a) {
+      ea[a] = ex;
+      ex *= rx;
+      rx *= q;
+    }
+  }
+  for (int b = 0; b < nyw; ++b) {
+    const T wy = wy0 * ey;
+#pragma unroll
+    for (int a = 0; a < kSplatCols; ++a) {
+      if (a < nxw) {
+        const T v = wy * ea[a];
+        if constexpr (NARROW)
+          atomicAdd(&row[a], (unsigned long long)(uint32_t)__builtin_rintf(v));
+        else
+          atomicAdd(&row[a], to_fixed(v));
+      }
     }
     row += nx;
     ey *= ry;
@@ -132,10 +170,17 @@ __device__ __forceinline__ bool splat_add(const SplatGeom& g, double x, double y
   // the Gaussian factors are at most 1: a weight below 2^32 units bounds
   // every contribution
   const T ws = w * (T)splat_unit<T>();
-  if (sizeof(T) == 4 && ws < (T)4294967296.0)
+  const bool narrow = sizeof(T) == 4 && ws < (T)4294967296.0;
+  if (nxw <= kSplatCols) {
+    if (narrow)
+      splat_cells_rows<T, sizeof(T) == 4>(row, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, q);
+    else
+      splat_cells_rows<T, false>(row, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, q);
+  } else if (narrow) {
     splat_cells<T, sizeof(T) == 4>(row, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, q);
-  else
+  } else {
     splat_cells<T, false>(row, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, q);
+  }
   return true;
 }
 
@@ -173,6 +218,36 @@ __device__ __forceinline__ void splat_cells32(uint32_t* row, unsigned long long*
   }
 }
 
+__device__ __forceinline__ void splat_cells32_rows(uint32_t* row, unsigned long long* grow, int nx, int nxw, int nyw,
+                                                   float wy0, float ex0, float rx0, float ey, float ry, float q) {
+  float ea[kSplatCols];
+  {
+    float ex = ex0, rx = rx0;
+#pragma unroll
+    for (int a = 0; a < kSplatCols; ++a) {
+      ea[a] = ex;
+      ex *= rx;
+      rx *= q;
+    }
+  }
+  for (int b = 0; b < nyw; ++b) {
+    const float wy = wy0 * ey;
+#pragma unroll
+    for (int a = 0; a < kSplatCols; ++a) {
+      if (a < nxw) {
+        const uint32_t lo = (uint32_t)__builtin_rintf(wy * ea[a]);
+        const uint32_t old = atomicAdd(&row[a], lo);
+        uint32_t sum;
+        if (__builtin_add_overflow(old, lo, &sum)) atomicAdd(&grow[a], 1ull << 32);
+      }
+    }
+    row += nx;
+    grow += nx;
+    ey *= ry;
+    ry *= q;
+  }
+}
+
 __device__ __forceinline__ bool splat_add32(const SplatGeom& g, double x, double y, float w, uint32_t* acc,
                                             unsigned long long* gacc) {
   int ix0, nxw, iy0, nyw;
@@ -185,7 +260,9 @@ __device__ __forceinline__ bool splat_add32(const SplatGeom& g, double x, double
   gauss_start<float>(g, dy0, ey, ry);
   const int64_t base = (int64_t)iy0 * g.nx + ix0;
   const float ws = w * (float)splat_unit<float>();
-  if (ws < 4294967296.0f)
+  if (ws < 4294967296.0f && nxw <= kSplatCols)
+    splat_cells32_rows(acc + base, gacc + base, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, (float)g.q);
+  else if (ws < 4294967296.0f)
     splat_cells32<true>(acc + base, gacc + base, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, (float)g.q);
   else
     splat_cells32<false>(acc + base, gacc + base, g.nx, nxw, nyw, ws, ex0, rx0, ey, ry, (float)g.q);
@@ -220,24 +297,59 @@ __device__ __forceinline__ bool splat_seeds(const SplatGeom& g, double x, double
   T s0 = (T)0, sx = (T)0, sy = (T)0;
   const Gt* row = G + (int64_t)iy0 * g.nx + ix0;
   T dy = (T)dy0;
-  for (int b = 0; b < nyw; ++b) {
-    T ex = ex0, rx = rx0, dx = (T)dx0;
-    T r0 = (T)0, r1 = (T)0;
-    for (int a = 0; a < nxw; ++a) {
-      const T v = (T)row[a] * ex;
-      r0 += v;
-      r1 += v * dx;
-      ex *= rx;
-      rx *= q;
-      dx += cell;
+  if (nxw <= kSplatCols) {
+    // unrolled rows (as splat_cells32_rows): the column factors and offsets
+    // from the same recurrences, the same sums in the same order
+    T ea[kSplatCols], da[kSplatCols];
+    {
+      T ex = ex0, rx = rx0, dx = (T)dx0;
+#pragma unroll
+      for (int a = 0; a < kSplatCols; ++a) {
+        ea[a] = ex;
+        da[a] = dx;
+        ex *= rx;
+        rx *= q;
+        dx += cell;
+      }
     }
-    s0 += ey * r0;
-    sx += ey * r1;
-    sy += ey * dy * r0;
-    row += g.nx;
-    ey *= ry;
-    ry *= q;
-    dy += cell;
+    for (int b = 0; b < nyw; ++b) {
+      T r0 = (T)0, r1 = (T)0;
+#pragma unroll
+      for (int a = 0; a < kSplatCols; ++a) {
+        if (a < nxw) {
+          const T v = (T)row[a] * ea[a];
+          r0 += v;
+          r1 += v * da[a];
+        }
+      }
+      s0 += ey * r0;
+      sx += ey * r1;
+      sy += ey * dy * r0;
+      row += g.nx;
+      ey *= ry;
+      ry *= q;
+      dy += cell;
+    }
+  } else {
+    for (int b = 0; b < nyw; ++b) {
+      T ex = ex0, rx = rx0, dx = (T)dx0;
+      T r0 = (T)0, r1 = (T)0;
+      for (int a = 0; a < nxw; ++a) {
+        const T v = (T)row[a] * ex;
+        r0 += v;
+        r1 += v * dx;
+        ex *= rx;
+        rx *= q;
+        dx += cell;
+      }
+      s0 += ey * r0;
+      sx += ey * r1;
+      sy += ey * dy * r0;
+      row += g.nx;
+      ey *= ry;
+      ry *= q;
+      dy += cell;
+    }
   }
   const T n = (T)g.norm, is2 = (T)(2.0 * g.inv_2s2);  // 1/sigma^2
   wb = n * s0;
