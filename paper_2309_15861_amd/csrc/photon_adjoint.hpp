@@ -55,6 +55,19 @@ __device__ __forceinline__ void splat_axis(double lo, double cell, double inv_ce
   d0 = (lo + ((double)a + 0.5) * cell) - x;
 }
 
+// A cheap first test that a photon landing at (x, y) may have a cell in
+// reach: false only when x or y lies more than 1 m outside the grid grown by
+// the reach (the margin is far above the float rounding of coordinates below
+// 1e6 m and of the bounds; farther out the distance alone decides), and for
+// non-finite coordinates. splat_axis's exact tests decide the rest, so the
+// cell sets do not change.
+template <typename C>
+__device__ __forceinline__ bool splat_near(const SplatGeom& g, C x, C y) {
+  const C x0 = (C)(g.x_min - g.reach - 1.0), x1 = (C)(g.x_min + g.nx * g.cell + g.reach + 1.0);
+  const C y0 = (C)(g.y_min - g.reach - 1.0), y1 = (C)(g.y_min + g.ny * g.cell + g.reach + 1.0);
+  return x >= x0 && x <= x1 && y >= y0 && y <= y1;
+}
+
 // Gaussian factors along one axis, e_k = exp(-(d0 + k cell)^2 / (2 sigma^2)),
 // by the recurrence e_{k+1} = e_k r_k, r_{k+1} = r_k q (two exponentials per
 // axis instead of one per cell).
@@ -157,6 +170,7 @@ __device__ __forceinline__ void splat_cells_rows(unsigned long long* row, int nx
 // cell is within reach.
 template <typename T>
 __device__ __forceinline__ bool splat_add(const SplatGeom& g, double x, double y, T w, unsigned long long* acc) {
+  if (!splat_near<T>(g, (T)x, (T)y)) return false;
   int ix0, nxw, iy0, nyw;
   double dx0, dy0;
   splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, ix0, nxw, dx0);
@@ -250,6 +264,7 @@ __device__ __forceinline__ void splat_cells32_rows(uint32_t* row, unsigned long 
 
 __device__ __forceinline__ bool splat_add32(const SplatGeom& g, double x, double y, float w, uint32_t* acc,
                                             unsigned long long* gacc) {
+  if (!splat_near<float>(g, (float)x, (float)y)) return false;
   int ix0, nxw, iy0, nyw;
   double dx0, dy0;
   splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, ix0, nxw, dx0);
@@ -272,6 +287,7 @@ __device__ __forceinline__ bool splat_add32(const SplatGeom& g, double x, double
 // Whether a photon landing at (x, y) has a cell in reach (the test of
 // splat_add, exactly).
 __device__ __forceinline__ bool splat_reach(const SplatGeom& g, double x, double y) {
+  if (!splat_near<double>(g, x, y)) return false;
   int i0, n;
   double d0;
   splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, i0, n, d0);
@@ -285,6 +301,7 @@ __device__ __forceinline__ bool splat_reach(const SplatGeom& g, double x, double
 template <typename T, typename Gt>
 __device__ __forceinline__ bool splat_seeds(const SplatGeom& g, double x, double y, T w, const Gt* G, T& xb, T& yb,
                                             T& wb) {
+  if (!splat_near<double>(g, x, y)) return false;
   int ix0, nxw, iy0, nyw;
   double dx0, dy0;
   splat_axis(g.x_min, g.cell, g.inv_cell, g.nx, g.reach, x, ix0, nxw, dx0);
