@@ -363,7 +363,7 @@ int photon_collect(const photon_block* in, const photon_atmosphere* atm, const p
    number of photon slots to process: offsets[n], or -1 to have the kernel
    read offsets[n] on the device (no host round trip; slots beyond
    offsets[n] count as INVALID). Results equal those of gen + propagate +
-   collect. In the FP32 form, rays within about 6 degrees of the horizon are
+   collect. In the FP32 form, rays within about 3 degrees of the horizon are
    handed to a second, double kernel that regenerates them from their random
    numbers (the device's queue of 2^24 rays, allocated on the first such
    call; see PHOTON_HORIZON_FLOAT). Works in the device's scratch: calls on

@@ -584,7 +584,7 @@ constexpr int kAdjNone = 0, kAdjDone = 1, kAdjDeferred = 2;
 // returns the segment-direction adjoint in dd (kAdjDone), or kAdjNone when
 // the photon contributes nothing (not landed, outside every cell's reach, or
 // its segment below threshold). The float form returns kAdjDeferred for rays
-// within about 6 degrees of the horizontal (C^2 <= 0.01), which the double
+// within about 3 degrees of the horizontal (C^2 <= 0.0025), which the double
 // form finishes; with FORCE_FLOAT it evaluates them in float.
 template <typename T, typename Gt, bool FORCE_FLOAT = false>
 __device__ __forceinline__ int adjoint_photon(const AtmDev& a, const AtmLane& L, const AdjSeg& sg, uint32_t j,
