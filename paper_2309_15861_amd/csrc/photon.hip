@@ -795,11 +795,13 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
 constexpr int kWindow = 128;        // segments staged in LDS per piece of a work chunk
 constexpr int kWindowSplat32 = 96;  // the same for the float splat (two blocks and their grids per CU)
 // the float splat's launch: 768-thread blocks, two per CU (six waves per
-// SIMD), 6144-photon chunks
-constexpr int kSplatBs32 = 768, kSplatChunk32 = 6144;
+// SIMD), chunks of eleven blocks' worth (about 70 segments, within the
+// 96-segment window)
+constexpr int kSplatBs32 = 768, kSplatChunk32 = 8448;
 constexpr int kAdjSegWin = 64;      // segments staged in LDS per piece of a chunk of the adjoint
 constexpr int kMaxChunk = 16384;     // photons per work chunk (the slot map's size)
-constexpr int kMaxChunkSplat = 8192;
+constexpr int kMaxChunkSplat = 9216;
+static_assert(kSplatChunk32 <= kMaxChunkSplat && 8192 <= kMaxChunkSplat, "splat chunks fit the slot map");
 
 // Everything the fused kernels take, as one kernel argument.
 struct FusedArgs {
@@ -842,13 +844,14 @@ constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8;
 
 // Float instances are built for the waves per SIMD that their LDS allows:
 // six of 256 threads (six blocks of under 26.6 KB per CU), four of 512.
-// Double instances of 256 threads for three (167 registers, some spilled:
-// 1.6% faster on the 64-shower workload than two waves without spills; four
-// spill so much that they are 1.8x slower).
+// Double instances of 256 threads for two waves per SIMD (256 registers, no
+// spills), that is two blocks per CU: one block's chunk set-up and barrier
+// waits overlap the other's work (64-shower FP64 kernel 85.4 ms in 512-thread
+// blocks, one per CU, 73.3 ms; three waves spill, 101 ms).
 constexpr int fused_waves_per_eu(bool fp32, int mode, int bs) {
   // the float splat: two blocks per CU
   return (mode & kMSplat) ? (fp32 ? bs / 128 : 1)
-                          : (!fp32 ? (bs == 256 ? 3 : 1) : (bs == 256 ? 6 : (bs >= 512 ? 4 : 1)));
+                          : (!fp32 ? (bs == 256 ? 2 : 1) : (bs == 256 ? 6 : (bs >= 512 ? 4 : 1)));
 }
 
 template <typename T, int BS, int MODE = 0>
@@ -2468,6 +2471,9 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   const bool table = !SPLAT && atm.tcorr != nullptr;
   const int mode = SPLAT ? kMSplat
                          : ((radial ? kMRadial : 0) | (table ? kMTable : 0) | (g.kind == PHOTON_FLUORESCENCE ? kMFluo : 0));
+  // the slot map of a chunk's piece holds kMaxChunk (splat: kMaxChunkSplat) photons
+  if (chunk < 1 || chunk > (SPLAT ? kMaxChunkSplat : kMaxChunk))
+    return fail(PHOTON_EINVAL, "fused chunk %lld outside 1..%d", (long long)chunk, SPLAT ? kMaxChunkSplat : kMaxChunk);
   const void* kfn = fused_instance<T, BS>(mode);
   // the radial bins live in dynamic LDS: count, weight and w t per bin
   if (radial) dyn_lds = (size_t)3 * sizeof(unsigned long long) * (size_t)sk.n_bins;
@@ -3282,8 +3288,8 @@ int photon_splat_forward(const photon_segments* seg, const photon_atmosphere* at
     sk.splat_lds = fits ? 1 : 0;
     // large chunks: a block's serial set-up of a chunk (work cursor, segment
     // search, window) is hidden by few or no other blocks (1e6-segment
-    // workload, FP64 4096 -> 8192 photons: 7.02 -> 6.55 ms; FP32 3072 -> 6144:
-    // 3.86 -> 3.52 ms)
+    // workload, FP64 4096 -> 8192 photons: 7.02 -> 6.55 ms; FP32 3072 -> 6144
+    // -> 8448: 3.86 -> 3.52 -> ... -> 3.05 -> 2.84 ms)
     if (precision == PHOTON_FP32)
       rc = fits ? launch_fused_bs<float, kSplatBs32, true>(c.sv, c.n, c.ad, c.g, seed, offsets, -1, kSplatChunk32, 0, sk,
                                                            dev, st, lds)
