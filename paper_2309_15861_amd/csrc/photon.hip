@@ -385,26 +385,79 @@ __device__ __forceinline__ void generate_kind(const SegConst<T>& c, uint32_t j, 
     gen_fluor<T>(c, j, k0, k1, thr, lines, g.n_lines, g.beam.on != 0, p);
 }
 
+// Photons [256 b, 256 b + 256) of the block: their segments are found once
+// per block (a wave-parallel search for the first and the last) and, when
+// they are at most kGenWin, staged in LDS with their constants, so that each
+// photon looks its segment up among a few LDS offsets instead of searching
+// the offsets in global memory and recomputing the segment's constants.
+constexpr int kGenWin = 64;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gen(SegView seg, int64_t n_seg, AtmDev atm, GenParams g, uint32_t k0,
                                              uint32_t k1, const uint64_t* __restrict__ offsets, int64_t n_ph,
                                              BlockView<T> out) {
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ T s_lines[PHOTON_MAX_LINES];
-  if (threadIdx.x < PHOTON_MAX_LINES) {
-    s_thr[threadIdx.x] = g.thr[threadIdx.x];
-    s_lines[threadIdx.x] = (T)g.line_nm[threadIdx.x];
+  __shared__ SegConst<T> s_seg[kGenWin];
+  __shared__ uint64_t s_off[kGenWin + 1];
+  __shared__ int64_t s_lo, s_hi;
+  const int tid = threadIdx.x;
+  if (tid < PHOTON_MAX_LINES) {
+    s_thr[tid] = g.thr[tid];
+    s_lines[tid] = (T)g.line_nm[tid];
+  }
+  const uint64_t total = offsets[n_seg];
+  const int64_t q0 = (int64_t)blockIdx.x * blockDim.x;
+  // the block's valid photons [q0, qe)
+  const int64_t qe = min(min(q0 + (int64_t)blockDim.x, n_ph), (int64_t)total);
+  const int wave = tid / kWaveSize;
+  if (qe > q0) {
+    if (wave == 0) {
+      const int64_t sl = wave_upper_index(offsets, n_seg, (uint64_t)q0);
+      if (lane_id() == 0) s_lo = sl;
+    } else if (wave == 1) {
+      const int64_t sh = wave_upper_index(offsets, n_seg, (uint64_t)(qe - 1));
+      if (lane_id() == 0) s_hi = sh;
+    }
   }
   __syncthreads();
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // both ends in [0, n_seg) for offsets from the count call; the clamps keep
+  // every index in bounds for any offsets array
+  const int64_t lo = qe > q0 ? min(s_lo, n_seg - 1) : 0;
+  const int64_t W = qe > q0 ? min(s_hi, n_seg - 1) - lo + 1 : 0;
+  const bool win = W >= 1 && W <= kGenWin;
+  const bool cher = g.kind == PHOTON_CHERENKOV;
+  if (win) {
+    for (int t = tid; t < W; t += blockDim.x) seg_const<T>(seg, lo + t, atm, cher, g.beam, s_seg[t]);
+    for (int t = tid; t <= W; t += blockDim.x) s_off[t] = offsets[lo + t];
+  }
+  __syncthreads();
+  const int64_t q = q0 + tid;
   if (q >= n_ph) return;
   Photon<T> p;
   uint32_t s32 = 0xffffffffu, j = 0;
-  if ((uint64_t)q < offsets[n_seg]) {
-    const int64_t s = lane_upper_index(offsets, n_seg, (uint64_t)q);
+  if ((uint64_t)q < total) {
+    int64_t s;
+    uint64_t off_s;
     SegConst<T> c;
-    seg_const<T>(seg, s, atm, g.kind == PHOTON_CHERENKOV, g.beam, c);
-    j = (uint32_t)((uint64_t)q - offsets[s]);
+    int a = 0;
+    if (win) {
+      int b = (int)W;  // s_off[a] <= q < s_off[b]
+      while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (s_off[mid] <= (uint64_t)q) a = mid; else b = mid;
+      }
+      s = lo + a;
+      c = s_seg[a];
+      off_s = s_off[a];
+      // keeps the LDS load and the global one below apart
+      asm volatile("" : "+v"(off_s));
+    } else {
+      s = lane_upper_index(offsets, n_seg, (uint64_t)q);
+      seg_const<T>(seg, s, atm, cher, g.beam, c);
+      off_s = offsets[s];
+    }
+    j = (uint32_t)((uint64_t)q - off_s);
     generate<T>(c, j, g, k0, k1, s_thr, s_lines, p);
     s32 = (uint32_t)s;
   } else {
@@ -427,7 +480,9 @@ __global__ __launch_bounds__(256) void k_gen(SegView seg, int64_t n_seg, AtmDev 
 }
 
 // ------------------------------------------------------------- propagation --
-template <typename T>
+// TABLE: the straight line with tabulated corrections (atm.tcorr set); a
+// separate instance, so that the exact path carries none of its registers.
+template <typename T, bool TABLE>
 __global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, int64_t n_ph) {
   __shared__ AtmLane s_lane;
   atm_lane_fill(atm, &s_lane);
@@ -447,10 +502,7 @@ __global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, i
   p.path = b.path[q];
   p.status = b.status[q];
   p.uzd = (double)p.uz;
-  if (atm.tcorr)
-    propagate<T, false, false, true>(atm, s_lane, p);
-  else
-    propagate<T>(atm, s_lane, p);
+  propagate<T, false, false, TABLE>(atm, s_lane, p);
   b.x[q] = p.x;
   b.y[q] = p.y;
   b.z[q] = p.z;
@@ -2297,8 +2349,12 @@ int launch_propagate(photon_block* b, const AtmDev& atm, hipStream_t st) {
   int rc = prep_block<T>(b, &bv, true);
   if (rc) return rc;
   if (b->n_photons == 0) return PHOTON_OK;
-  hipLaunchKernelGGL(k_propagate<T>, dim3((unsigned)ceil_div(b->n_photons, 256)), dim3(256), 0, st, atm, bv,
-                     b->n_photons);
+  if (atm.tcorr)
+    hipLaunchKernelGGL((k_propagate<T, true>), dim3((unsigned)ceil_div(b->n_photons, 256)), dim3(256), 0, st, atm,
+                       bv, b->n_photons);
+  else
+    hipLaunchKernelGGL((k_propagate<T, false>), dim3((unsigned)ceil_div(b->n_photons, 256)), dim3(256), 0, st, atm,
+                       bv, b->n_photons);
   return check_launch();
 }
 
