@@ -397,8 +397,8 @@ def plain_block(args, which=("plain", "shower_scale")):
                  roofline=dict(bound="hbm", achieved=bytes_ / ((gms + pms) * 1e-3) / 1e9, peak=PEAK_HBM / 1e9,
                                unit="GB/s", frac=bytes_ / ((gms + pms) * 1e-3) / PEAK_HBM,
                                bytes_per_photon=BLOCK_BYTES["gen"] + BLOCK_BYTES["propagate"],
-                               kernels="k_gen<double> + k_propagate<double>", traffic=None))
-        cg, cp = counters(f"k_gen<double> {name}"), counters(f"k_propagate<double> {name}")
+                               kernels="k_gen<double> + k_propagate<double, false>", traffic=None))
+        cg, cp = counters(f"k_gen<double> {name}"), counters(f"k_propagate<double, false> {name}")
         if cg and cp:
             r["roofline"]["traffic"] = cg["fetch_bytes"] + cg["write_bytes"] + cp["fetch_bytes"] + cp["write_bytes"]
         if not args.no_errors:
