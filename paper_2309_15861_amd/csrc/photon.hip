@@ -943,15 +943,9 @@ void k_fused(FusedArgs A) {
   __shared__ uint16_t s_slot[kWin];
   extern __shared__ unsigned long long s_splat[];  // dynamic: the block's fixed-point grid (SPLAT)
   // SPLAT: the waves share out each piece dynamically (photons in reach cost
-  // more); double fluorescence (REFILL): lanes whose photon leaves upwards
-  // take another photon of the piece before the propagation (fluorescence
-  // step 5.66 -> 5.50 ms; in the float form the extra registers spill and
-  // the step is 15% slower)
-  constexpr bool REFILL = !CHER && sizeof(T) == 8;
-  constexpr bool DYN = SPLAT || REFILL;
-  // not for the plane sink, which writes a record of every photon
-  const bool refill = REFILL && A.sk.kind != PHOTON_SINK_PLANE;
-  constexpr bool LATE = (sizeof(T) == 4 && CHER && !SPLAT) || REFILL;
+  // more)
+  constexpr bool DYN = SPLAT;
+  constexpr bool LATE = sizeof(T) == 4 && CHER && !SPLAT;
   __shared__ unsigned int s_grab;
   constexpr bool kDefer = sizeof(T) == 4;
   const bool stage_hits = !SPLAT && !RADIAL && A.sk.kind == PHOTON_SINK_TELESCOPES;
@@ -1165,7 +1159,7 @@ void k_fused(FusedArgs A) {
         // (64-shower FP32 kernel 22.9 -> 21.3 ms) and the double ones and
         // the float splat slower (85.3 -> 92.0 ms; 3.39 -> 3.53 ms), which
         // keep the steps written out inside the test (the same statements as
-        // fetch and finish); the refill needs LATE.
+        // fetch and finish).
         if constexpr (LATE) {
           uint64_t q = q0;
           bool have = q < ce;
@@ -1174,34 +1168,8 @@ void k_fused(FusedArgs A) {
           uint32_t j = 0;
           T wsc = (T)1;
           Photon<T> p;
-          if constexpr (REFILL) {
-            // a photon that leaves upwards or starts below h_obs ends after
-            // its generation (the status propagate would give it), and its
-            // lane takes another photon of the piece (one more round), so that
-            // fewer lanes idle in the propagation (one inlined generation)
-            bool need = have;
-            const int rounds = refill ? 2 : 1;
-#pragma unroll 1
-            for (int r = 0;;) {
-              if (need) fetch(q, c, s, j, wsc, p);
-              if (++r == rounds) break;
-              const bool gone = have && p.status == PHOTON_LANDED && (!(p.uz < (T)0) || p.z < A.atm.hobs);
-              const unsigned long long m = __ballot(gone);
-              if (!m) break;
-              if (gone) pk += status_inc(!(p.uz < (T)0) ? PHOTON_UP : PHOTON_BELOW);
-              unsigned int g1 = 0u;
-              if (lane_id() == 0) g1 = atomicAdd(&s_grab, (unsigned int)__popcll(m));
-              g1 = (unsigned int)__shfl((int)g1, 0, kWaveSize);
-              need = false;
-              if (gone) {
-                q = cs + (uint64_t)g1 + lanes_below(m);
-                have = q < ce;
-                need = have;
-              }
-            }
-          }
           if (have) {
-            if constexpr (!REFILL) fetch(q, c, s, j, wsc, p);
+            fetch(q, c, s, j, wsc, p);
             finish(c, s, j, wsc, p, q);
           }
         } else {
