@@ -213,11 +213,11 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
                                                       uint32_t* __restrict__ counts,
                                                       uint64_t* __restrict__ offsets) {
   __shared__ unsigned long long part[kScanBlock / kWaveSize];
-  __shared__ double rk[kPoissonKmax + 1];
+  __shared__ __align__(16) double rk[kPoissonKmax];
   __shared__ double s_mc[kScanBlock], s_p0[kScanBlock];
   __shared__ uint32_t s_start[kScanBlock], s_cnt[kScanBlock], s_idx[kScanBlock], s_sh[kScanBlock];
   const int tid = threadIdx.x;
-  for (int k = tid; k <= (int)kPoissonKmax; k += kScanBlock) rk[k] = 1.0 / (double)k;
+  for (int k = tid; k < (int)kPoissonKmax; k += kScanBlock) rk[k] = 1.0 / (double)(k + 1);
   const int64_t i = (int64_t)blockIdx.x * kScanBlock + tid;
   uint32_t m = 0;
   double mc = 0.0, p0 = 0.0;

@@ -294,17 +294,29 @@ __device__ __forceinline__ uint32_t poisson_chunks(double mu) {
   return (mu <= kPoissonChunk) ? 1u : (uint32_t)ceil(mu / kPoissonChunk);
 }
 
-// One chunk: the smallest k with F(k) >= u for Poisson(mc), p0 = exp(-mc).
+// One chunk: the smallest k with F(k) >= u for Poisson(mc), p0 = exp(-mc),
+// capped at kPoissonKmax; rk[k] = 1/(k+1), 16-byte aligned. The terms are
+// taken four at a time: the products and sums are the ones of the step-by-step
+// recurrence in the same order, and F never decreases, so one test of the
+// fourth sum decides whether all four steps are taken (one table read and one
+// loop test per four steps), and the result is the same.
 __device__ __forceinline__ uint32_t poisson_chunk(double u, double mc, double p0, const double* rk) {
 #pragma clang fp contract(off)
-  uint32_t k = 0;
+  static_assert(kPoissonKmax % 4u == 0u, "the cap is a multiple of the step group");
   double p = p0, F = p0;
-  while (u > F && k < kPoissonKmax) {
-    k += 1;
-    p = (p * mc) * rk[k];
-    F = F + p;
+  if (!(u > F)) return 0u;
+  for (uint32_t k = 0; k < kPoissonKmax; k += 4u) {
+    const double2 r01 = *reinterpret_cast<const double2*>(rk + k);
+    const double2 r23 = *reinterpret_cast<const double2*>(rk + k + 2);
+    const double p1 = (p * mc) * r01.x, F1 = F + p1;
+    const double p2 = (p1 * mc) * r01.y, F2 = F1 + p2;
+    const double p3 = (p2 * mc) * r23.x, F3 = F2 + p3;
+    const double p4 = (p3 * mc) * r23.y, F4 = F3 + p4;
+    if (!(u > F4)) return k + (!(u > F1) ? 1u : !(u > F2) ? 2u : !(u > F3) ? 3u : 4u);
+    p = p4;
+    F = F4;
   }
-  return k;
+  return kPoissonKmax;
 }
 
 // Precision-specific primitives: the float path uses the hardware
