@@ -947,6 +947,15 @@ void k_fused(FusedArgs A) {
   constexpr bool DYN = SPLAT;
   constexpr bool LATE = sizeof(T) == 4 && CHER && !SPLAT;
   __shared__ unsigned int s_grab;
+  // Isotropic fluorescence into a sink that records nothing for photons that
+  // never land (grid, telescopes, radial bins): half the photons go up and
+  // would leave their lanes idle beside the propagation of the others. Each
+  // wave first draws its photons' direction words, whose top bit fixes the
+  // sign of u_z, counts the up-going ones and passes the others on, 64 at a
+  // time, through a ring of piece positions in LDS.
+  constexpr bool FILT = !CHER && !SPLAT;
+  constexpr int kRing = 2 * kWaveSize;
+  const bool filt = FILT && !A.g.beam.on && A.sk.kind != PHOTON_SINK_PLANE;
   constexpr bool kDefer = sizeof(T) == 4;
   const bool stage_hits = !SPLAT && !RADIAL && A.sk.kind == PHOTON_SINK_TELESCOPES;
   // the block's LDS accumulator: the splat grid, or the radial bins
@@ -1070,6 +1079,10 @@ void k_fused(FusedArgs A) {
         }
         __syncthreads();
       }
+      // filtered fluorescence: the wave's ring (head, length) and the next
+      // block group of the piece whose directions are drawn; all wave-uniform
+      uint32_t r_head = 0u, r_len = 0u, n_up = 0u;
+      uint64_t q_draw = cs;
       // every lane of a wave runs the same number of iterations (the status
       // ballots); DYN: the waves take 64-photon groups of the piece from an
       // LDS counter, so that a wave slowed by its photons (splats) takes fewer
@@ -1082,8 +1095,47 @@ void k_fused(FusedArgs A) {
         } else {
           qb = cs + (uint64_t)ng * BS;
         }
+        uint64_t q_ring = 0;  // filtered fluorescence: the lane's photon from the ring, ce for none
+        if constexpr (FILT) {
+          if (filt) {
+            __shared__ uint16_t s_ring[BS / kWaveSize][kRing];
+            // draw directions group by group (the wave's slice of each block
+            // group, as in the plain schedule) until the ring holds 64 photons
+            while (r_len < (uint32_t)kWaveSize && q_draw < ce) {
+              const uint64_t q = q_draw + (uint64_t)tid;
+              const bool valid = q < ce;
+              bool down = valid;
+              if (valid && win) {
+                const uint64_t i = q - cs;
+                const int a = s_slot[s_pre[i >> 6] + (uint32_t)__popcll(s_bits[i >> 6] & ((2ull << (i & 63)) - 1ull))];
+                const U4 r = philox((uint32_t)(q - s_off[a]), s_seg[a].idx, s_seg[a].shower, kDomFluo, A.k0, A.k1);
+                down = (r.w[1] >> 31) != 0u;  // u_z = -(w1 - 2^31 + 1/2) 2^-31 < 0
+              }
+              const unsigned long long m = __ballot(down);
+              n_up += (uint32_t)__popcll(__ballot(valid)) - (uint32_t)__popcll(m);
+              if (down) s_ring[wave][(r_head + r_len + lanes_below(m)) & (kRing - 1)] = (uint16_t)(q - cs);
+              r_len += (uint32_t)__popcll(m);
+              q_draw += BS;
+            }
+            qb = r_len ? cs : ce;  // an empty ring ends the piece
+            if (r_len) {
+              // the lanes' ring writes before the reads of other lanes' entries
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+              const uint32_t take = min(r_len, (uint32_t)kWaveSize);
+              q_ring = (uint32_t)lane_id() < take ? cs + s_ring[wave][(r_head + (uint32_t)lane_id()) & (kRing - 1)] : ce;
+              // the reads before the next round's writes
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+              r_head += take;
+              r_len -= take;
+            }
+          }
+        }
         if (qb >= ce) break;
-        const uint64_t q0 = qb + (DYN ? (uint64_t)lane_id() : (uint64_t)tid);
+        const uint64_t q0 = (FILT && filt) ? q_ring : qb + (DYN ? (uint64_t)lane_id() : (uint64_t)tid);
         int st_out = -1;
         bool forced = false;
         // photon qq of the piece: its segment (from the window's slot map, or
@@ -1258,6 +1310,7 @@ void k_fused(FusedArgs A) {
       // the per-lane 8-bit counters stay below 256 increments per piece
       flush_lane_status(pk, s_stat);
       pk = 0;
+      if (FILT && n_up && lane_id() == 0) atomicAdd(&s_stat[PHOTON_UP], (unsigned long long)n_up);
       cs = ce;
       __syncthreads();  // the window is refilled for the next piece
     }

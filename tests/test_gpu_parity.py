@@ -492,3 +492,53 @@ def test_deferral_queue_overflow_evaluated_in_place(fluor_run):
     same = np.abs(ref["ue"][:, 2]) >= 0.2
     for f in ("x", "y", "t_ns", "weight", "ux", "uy", "uz"):
         assert np.array_equal(g[f][same], g0[f][same]), f
+
+
+def test_fused_fluorescence_sinks_every_launch_shape(fluor_run):
+    """Isotropic fluorescence into the sinks that record nothing for photons
+    that never land (grid, telescopes): the fused kernel counts the up-going
+    photons from their direction words and propagates only the others. Every
+    block size, chunk size and occupancy gives the oracle's up-going count,
+    its grid within the landing tolerance and, in FP64, its hit set."""
+    a, seg, d, atm, em, offsets, total, ref = fluor_run
+    oatm = O.Atmosphere.from_dict(a)
+    g = dict(x_min=-2000.0, y_min=-2000.0, cell=50.0, nx=80, ny=80)
+    n_up = int((ref["status"] == O.UP).sum())
+    assert 0.4 * total < n_up < 0.6 * total
+    tel = W.telescopes_16(radius=45.0)
+    tid, _ = O.telescopes(ref, tel, oatm.index(a["h_obs"]))
+    off = offsets.cpu().numpy().view(np.uint64)
+    s_of = np.repeat(np.arange(len(seg["x0"])), np.diff(off).astype(np.int64))
+    j_of = np.arange(total) - off[s_of].astype(np.int64)
+    hit = tid >= 0
+    key_ref = np.sort((s_of[hit].astype(np.int64) << 32) | j_of[hit])
+    print(f"{int(hit.sum())} oracle hits, {n_up} up-going of {total}", flush=True)
+    assert hit.sum() > 10
+    for prec in (ph.FP64, ph.FP32):
+        tol = TOL64 if prec == ph.FP64 else TOL32
+        bounds = grid_bounds(ref, g, tol["land"], tol["w"] + tol["w_tau"] * ref["tau"])
+        for block, chunk, bpc in ((128, 128, 1), (256, 4096, 0), (512, 512 * 31, 2), (256, 16384, 0)):
+            tun = ph.tuning(block, chunk, bpc)
+            gc = torch.zeros(g["nx"] * g["ny"], dtype=torch.int32, device="cuda")
+            gw = torch.zeros(g["nx"] * g["ny"], dtype=torch.int64, device="cuda")
+            totals = ph.status_totals()
+            ph.run_fused(d, atm, em, 3, prec, offsets, total,
+                         ph.sink_grid(g["x_min"], g["y_min"], g["cell"], g["nx"], g["ny"], gc, gw, totals), tun)
+            torch.cuda.synchronize()
+            check_grid(gc.cpu().numpy(), gw.cpu().numpy(), bounds)
+            tot = totals.cpu().numpy()
+            assert tot.sum() == total and tot[ph.UP] == n_up, (prec, block, chunk)
+            hits = ph.HitBuffer(total)
+            totals = ph.status_totals()
+            ph.run_fused(d, atm, em, 3, prec, offsets, total, ph.sink_telescopes(tel, hits, totals), tun)
+            torch.cuda.synchronize()
+            tot = totals.cpu().numpy()
+            assert tot.sum() == total and tot[ph.UP] == n_up, (prec, block, chunk)
+            h = hits.numpy()
+            key = np.sort((h["segment"].astype(np.int64) << 32) | h["j"].astype(np.int64))
+            assert len(np.unique(key)) == len(key)
+            if prec == ph.FP64:
+                assert np.array_equal(key, key_ref), (block, chunk)
+            else:
+                # float landing points within the tolerance of a sphere's rim may fall either way
+                assert abs(len(key) - len(key_ref)) <= max(2, len(key_ref) // 1000), (block, chunk)
