@@ -202,6 +202,26 @@ __device__ __forceinline__ int64_t lane_upper_index(const uint64_t* off, int64_t
 }
 
 // ------------------------------------------------------------- count+scan --
+// Mean of segment i (i < n) and its Poisson chunking: m chunks of mean mc,
+// p0 = exp(-mc); the segment's random-stream ids. Zero chunks beyond n.
+template <int KIND>
+__device__ __forceinline__ void count_setup(const SegView& seg, int64_t n, int64_t i, const AtmDev& atm, double K,
+                                            const CutDev& cut, const BeamDev& beam, uint32_t& m, double& mc,
+                                            double& p0, uint32_t& idx, uint32_t& sh) {
+  if (i < n) {
+#pragma clang fp contract(off)
+    const double mu = (KIND == PHOTON_CHERENKOV) ? (passes_cut(seg, i, cut) ? mean_cherenkov(seg, i, atm, K) : 0.0)
+                                                 : beamed_mean(seg, i, beam, mean_fluor(seg, i, K));
+    m = poisson_chunks(mu);
+    if (m) {
+      mc = mu / (double)m;
+      p0 = exp_fixed(-mc);
+    }
+    idx = seg_idx(seg, i);
+    sh = seg_shower(seg, i);
+  }
+}
+
 // Counts: lane i computes the mean of segment i and its number of Poisson
 // chunks; each wave then spreads the (segment, chunk) draws of its 64
 // segments over its lanes, so that lanes do not idle while one segment with
@@ -222,18 +242,7 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
   uint32_t m = 0;
   double mc = 0.0, p0 = 0.0;
   uint32_t idx = 0, sh = 0;
-  if (i < n) {
-#pragma clang fp contract(off)
-    const double mu = (KIND == PHOTON_CHERENKOV) ? (passes_cut(seg, i, cut) ? mean_cherenkov(seg, i, atm, K) : 0.0)
-                                                 : beamed_mean(seg, i, beam, mean_fluor(seg, i, K));
-    m = poisson_chunks(mu);
-    if (m) {
-      mc = mu / (double)m;
-      p0 = exp_fixed(-mc);
-    }
-    idx = seg_idx(seg, i);
-    sh = seg_shower(seg, i);
-  }
+  count_setup<KIND>(seg, n, i, atm, K, cut, beam, m, mc, p0, idx, sh);
   const unsigned long long incl = wave_incl_scan((unsigned long long)m);
   const uint32_t total = (uint32_t)__shfl(incl, kWaveSize - 1, kWaveSize);
   s_start[tid] = (uint32_t)(incl - m);
@@ -265,6 +274,77 @@ __global__ __launch_bounds__(kScanBlock) void k_count(SegView seg, int64_t n, At
   if (tid == 0) {
     unsigned long long t = 0;
     for (int w = 0; w < kScanBlock / kWaveSize; ++w) t += part[w];
+    const int64_t pos = min((int64_t)(blockIdx.x + 1) * kScanBlock, n);
+    offsets[pos] = t;
+  }
+}
+
+// The same counts for inputs of few segments (kCountWideMaxBlocks blocks or
+// fewer): the draws of a block's kScanBlock segments are spread over all
+// kCountWide threads of the block instead of over the 64 lanes of each
+// segment's wave. A Poisson search is a chain of dependent multiplies and adds,
+// and a small input at one wave per 64 segments leaves a few waves per SIMD to
+// hide its latency; four times the waves per segment do.
+constexpr int kCountWide = 1024;
+constexpr int64_t kCountWideMaxBlocks = 2048;
+template <int KIND>
+__global__ __launch_bounds__(kCountWide) void k_count_wide(SegView seg, int64_t n, AtmDev atm, double K,
+                                                           uint32_t k0, uint32_t k1, CutDev cut, BeamDev beam,
+                                                           uint32_t* __restrict__ counts,
+                                                           uint64_t* __restrict__ offsets) {
+  constexpr int kW = kScanBlock / kWaveSize;  // the waves holding one segment per lane
+  __shared__ unsigned long long part[kW];
+  __shared__ uint32_t s_wt[kW];
+  __shared__ __align__(16) double rk[kPoissonKmax];
+  __shared__ double s_mc[kScanBlock], s_p0[kScanBlock];
+  __shared__ uint32_t s_start[kScanBlock], s_cnt[kScanBlock], s_idx[kScanBlock], s_sh[kScanBlock];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < (int)kPoissonKmax; k += kCountWide) rk[k] = 1.0 / (double)(k + 1);
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + tid;
+  if (tid < kScanBlock) {
+    uint32_t m = 0;
+    double mc = 0.0, p0 = 0.0;
+    uint32_t idx = 0, sh = 0;
+    count_setup<KIND>(seg, n, i, atm, K, cut, beam, m, mc, p0, idx, sh);
+    const unsigned long long incl = wave_incl_scan((unsigned long long)m);
+    if (lane_id() == kWaveSize - 1) s_wt[tid / kWaveSize] = (uint32_t)incl;
+    s_start[tid] = (uint32_t)(incl - m);  // within the wave; the waves before are added below
+    s_mc[tid] = mc;
+    s_p0[tid] = p0;
+    s_cnt[tid] = 0u;
+    s_idx[tid] = idx;
+    s_sh[tid] = sh;
+  }
+  __syncthreads();
+  uint32_t total = 0, before = 0;
+  for (int w = 0; w < kW; ++w) {
+    if (w < tid / kWaveSize) before += s_wt[w];
+    total += s_wt[w];
+  }
+  if (tid < kScanBlock) s_start[tid] += before;
+  __syncthreads();
+  for (uint32_t t = (uint32_t)tid; t < total; t += kCountWide) {
+    // the segment L of item t: the last L with start[L] <= t
+    int lo = 0, hi = kScanBlock;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_start[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t c = t - s_start[lo];
+    const double u = u01d(philox(c, s_idx[lo], s_sh[lo], kDomCount, k0, k1).w[0]);
+    atomicAdd(&s_cnt[lo], poisson_chunk(u, s_mc[lo], s_p0[lo], rk));
+  }
+  __syncthreads();
+  if (tid < kScanBlock) {
+    const uint32_t cnt = s_cnt[tid];
+    if (i < n) counts[i] = cnt;
+    const unsigned long long s = wave_sum((unsigned long long)cnt);
+    if (lane_id() == 0) part[tid / kWaveSize] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kW; ++w) t += part[w];
     const int64_t pos = min((int64_t)(blockIdx.x + 1) * kScanBlock, n);
     offsets[pos] = t;
   }
@@ -2310,12 +2390,20 @@ int count_and_scan(const SegView& sv, int64_t n, const AtmDev& atm, int kind, do
     return check_launch();
   }
   const int64_t nb = ceil_div(n, kScanBlock);
-  if (kind == PHOTON_CHERENKOV)
+  if (nb <= kCountWideMaxBlocks) {
+    if (kind == PHOTON_CHERENKOV)
+      hipLaunchKernelGGL(k_count_wide<PHOTON_CHERENKOV>, dim3((unsigned)nb), dim3(kCountWide), 0, st, sv, n, atm, K,
+                         k0, k1, cut, beam, counts, offsets);
+    else
+      hipLaunchKernelGGL(k_count_wide<PHOTON_FLUORESCENCE>, dim3((unsigned)nb), dim3(kCountWide), 0, st, sv, n, atm,
+                         K, k0, k1, cut, beam, counts, offsets);
+  } else if (kind == PHOTON_CHERENKOV) {
     hipLaunchKernelGGL(k_count<PHOTON_CHERENKOV>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0, k1,
                        cut, beam, counts, offsets);
-  else
+  } else {
     hipLaunchKernelGGL(k_count<PHOTON_FLUORESCENCE>, dim3((unsigned)nb), dim3(kScanBlock), 0, st, sv, n, atm, K, k0,
                        k1, cut, beam, counts, offsets);
+  }
   hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(1024), 0, st, offsets, n, nb);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanBlock), 0, st, (const uint32_t*)counts, offsets, n);
   return check_launch();
