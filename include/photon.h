@@ -214,9 +214,11 @@ typedef struct {
    written to one memory block and processed downstream), structure of
    arrays with `capacity` slots (device pointers). Slot q holds photon j of
    segment `segment[q]`, with q = offsets[segment] + j. Horizontal position,
-   direction, wavelength and weight are double (PHOTON_FP64) or float
-   (PHOTON_FP32); the height z, the time and the path length are double in
-   both. After generation: emission point,
+   the horizontal direction components, wavelength and weight are double
+   (PHOTON_FP64) or float (PHOTON_FP32); the vertical direction component,
+   the height z, the time and the path length are double in both (near the
+   horizon the zenith cosine sets the slant path and must keep its double
+   digits from generation to propagation). After generation: emission point,
    time and direction, path 0, weight 1, status LANDED (or INVALID). After
    propagation: landing point (z = h_obs), arrival time, arrival direction,
    geometric path length, transmission weight exp(-tau) and status. */
@@ -224,7 +226,9 @@ typedef struct {
   int64_t capacity;
   int64_t n_photons;                  /* slots in use = offsets[n]          */
   int32_t precision;
-  void *x, *y, *ux, *uy, *uz, *wavelength_nm, *weight;
+  void *x, *y, *ux, *uy;
+  double *uz;
+  void *wavelength_nm, *weight;
   double *z, *t_ns, *path_m;
   uint32_t *segment, *j;
   int32_t *status;
@@ -252,7 +256,8 @@ typedef struct {
    `cell` from (x_min, y_min), half-open; grid_count[iy*nx+ix] counts landed
    photons, grid_weight the sum of their weights in units of 2^-32. PLANE:
    every photon's final state is written at its slot q = offsets[s] + j of
-   `plane` (arrays of the run's precision, capacity >= number of photons;
+   `plane` (a photon block of the run's precision, its vertical direction
+   in double; capacity >= number of photons;
    slots beyond the capacity are not written), as photon_propagate leaves a
    photon block. RADIAL (the profiles of section 3.1): a landed photon at
    distance r = |(x, y) - (core_x, core_y)| from the core falls in bin

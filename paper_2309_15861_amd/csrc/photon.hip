@@ -73,8 +73,8 @@ constexpr int kWaveSize = 64;
 // ------------------------------------------------------------------ views --
 template <typename T>
 struct BlockView {
-  T *x, *y, *ux, *uy, *uz, *lam, *w;
-  double *z, *t, *path;
+  T *x, *y, *ux, *uy, *lam, *w;
+  double *uz, *z, *t, *path;  // uz in double: the zenith cosine near the horizon
   uint32_t *seg, *j;
   int32_t* status;
 };
@@ -117,8 +117,8 @@ struct SinkDev {
   unsigned long long* grid_weight;
   // PLANE: every photon written at its slot (arrays of the run's precision)
   int64_t plane_capacity;
-  void *px, *py, *pux, *puy, *puz, *plam, *pw;
-  double *pz, *pt, *ppath;
+  void *px, *py, *pux, *puy, *plam, *pw;
+  double *puz, *pz, *pt, *ppath;  // the vertical direction in double, as in the photon block
   uint32_t *pseg, *pj;
   int32_t* pstatus;
   // SPLAT (differentiable form): fixed-point accumulator of the whole grid
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256) void k_gen(SegView seg, int64_t n_seg, AtmDev 
   out.z[q] = p.z;
   out.ux[q] = p.ux;
   out.uy[q] = p.uy;
-  out.uz[q] = p.uz;
+  out.uz[q] = p.uzd;
   out.lam[q] = p.lambda;
   out.w[q] = p.w;
   out.t[q] = p.t;
@@ -575,20 +575,22 @@ __global__ __launch_bounds__(256) void k_propagate(AtmDev atm, BlockView<T> b, i
   p.z = b.z[q];
   p.ux = b.ux[q];
   p.uy = b.uy[q];
-  p.uz = b.uz[q];
+  p.uzd = b.uz[q];
+  p.uz = (T)p.uzd;
   p.lambda = b.lam[q];
   p.w = b.w[q];
   p.t = b.t[q];
   p.path = b.path[q];
   p.status = b.status[q];
-  p.uzd = (double)p.uz;
   propagate<T, false, false, TABLE>(atm, s_lane, p);
   b.x[q] = p.x;
   b.y[q] = p.y;
   b.z[q] = p.z;
   b.ux[q] = p.ux;
   b.uy[q] = p.uy;
-  b.uz[q] = p.uz;
+  // the arrival direction is in the working precision; photons that did not
+  // land keep their emitted component
+  b.uz[q] = p.status == PHOTON_LANDED ? (double)p.uz : p.uzd;
   b.w[q] = p.w;
   b.t[q] = p.t;
   b.path[q] = p.path;
@@ -770,7 +772,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
       sk.pz[slot_q] = p.z;
       ((T*)sk.pux)[slot_q] = p.ux;
       ((T*)sk.puy)[slot_q] = p.uy;
-      ((T*)sk.puz)[slot_q] = p.uz;
+      sk.puz[slot_q] = p.status == PHOTON_LANDED ? (double)p.uz : p.uzd;
       ((T*)sk.plam)[slot_q] = p.lambda;
       ((T*)sk.pw)[slot_q] = p.w;
       sk.pt[slot_q] = p.t;
@@ -906,7 +908,8 @@ __global__ __launch_bounds__(256) void k_collect(BlockView<T> b, int64_t n_ph, S
     p.z = b.z[q];
     p.ux = b.ux[q];
     p.uy = b.uy[q];
-    p.uz = b.uz[q];
+    p.uzd = b.uz[q];
+    p.uz = (T)p.uzd;
     p.lambda = b.lam[q];
     p.w = b.w[q];
     p.t = b.t[q];
@@ -1527,6 +1530,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) void k_
     pf.ux = (float)p.ux;
     pf.uy = (float)p.uy;
     pf.uz = (float)p.uz;
+    pf.uzd = p.uzd;
     pf.lambda = (float)p.lambda;
     pf.w = (float)p.w;
     pf.z = p.z;
@@ -2124,8 +2128,9 @@ int prep_block(const photon_block* b, BlockView<T>* v, bool need_cap) {
     for (int k = 0; k < 13; ++k)
       if (!req[k]) return fail(PHOTON_EINVAL, "photon block array %d is NULL", k);
   }
-  *v = BlockView<T>{(T*)b->x, (T*)b->y, (T*)b->ux, (T*)b->uy, (T*)b->uz, (T*)b->wavelength_nm, (T*)b->weight,
-                    b->z, b->t_ns, b->path_m, b->segment, b->j, b->status};
+  *v = BlockView<T>{(T*)b->x,      (T*)b->y, (T*)b->ux, (T*)b->uy, (T*)b->wavelength_nm, (T*)b->weight,
+                    b->uz,          b->z,     b->t_ns,   b->path_m, b->segment,           b->j,
+                    b->status};
   return PHOTON_OK;
 }
 

@@ -240,7 +240,7 @@ class DeviceSegments:
 class PhotonBlock:
     """The common photon block (structure of arrays) on the GPU."""
 
-    REAL = ("x", "y", "ux", "uy", "uz", "wavelength_nm", "weight")
+    REAL = ("x", "y", "ux", "uy", "wavelength_nm", "weight")
 
     def __init__(self, capacity: int, precision: int, device="cuda"):
         dt = torch.float64 if precision == FP64 else torch.float32
@@ -249,6 +249,7 @@ class PhotonBlock:
         self.n_photons = 0
         n = max(self.capacity, 1)
         self.t = {f: torch.empty(n, dtype=dt, device=device) for f in self.REAL}
+        self.t["uz"] = torch.empty(n, dtype=torch.float64, device=device)   # double in both precisions
         self.t["z"] = torch.empty(n, dtype=torch.float64, device=device)
         self.t["t_ns"] = torch.empty(n, dtype=torch.float64, device=device)
         self.t["path_m"] = torch.empty(n, dtype=torch.float64, device=device)

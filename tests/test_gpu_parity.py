@@ -8,12 +8,11 @@ Tolerances:
              weight 1e-12 relative, direction 1e-12 rad, emission
              point/time/direction/wavelength 1e-12 relative
   FP32 path: landing 1e-5 (same metric), time 0.1 ns, weight 1e-6 +
-             3e-7 x optical depth (the float optical depth's relative
-             error), direction 1e-6 rad for every photon of the fused kernel (rays
-             near the horizon are finished in double); the unfused block
-             stores float directions, whose 6e-8 relative precision limits
-             slant-path times below |cos(zenith)| = 0.2: landing 1e-5 and
-             time 3e-7 x travel time there
+             6e-7 x optical depth (the float optical depth's relative
+             error), direction 1e-6 rad, for every photon of the fused
+             kernel and of the unfused block (rays near the horizon are
+             finished in double; the block keeps the vertical direction
+             component in double, as the fused kernel does in registers)
 Counts are compared for equality on every segment: both sides evaluate the
 mean and the Poisson search in the same fixed order of IEEE double
 operations, exp included (a specified method on each side), so no decision
@@ -31,8 +30,6 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = dict(land=1e-9, t=1e-6, t_rel=2e-11, w=1e-12, w_tau=0.0, dir=1e-12)
 TOL32 = dict(land=1e-5, t=0.1, t_rel=0.0, w=1e-6, w_tau=6e-7, dir=1e-6)
-TOL32_HORIZON = dict(land=1e-5, t=0.1, t_rel=3e-7, w=1e-6, w_tau=6e-7, dir=1e-6)
-HORIZON_COS = 0.2
 
 
 def gpu_counts(seg, a, em, seed):
@@ -84,6 +81,8 @@ def check_propagated(g, ref, tol, mask=None):
     assert np.all(dt <= bound), f"time error {dt.max():.3e} ns (worst excess {(dt - bound).max():.3e})"
     dw = (np.abs(g["weight"].astype(np.float64) - ref["weight"]) / ref["weight"])[landed]
     wb = tol["w"] + tol["w_tau"] * ref["tau"][landed]
+    print(f"weight bar {tol['w']:.0e} + {tol['w_tau']:.0e} tau: largest tau {ref['tau'][landed].max():.2f}, "
+          f"bar {wb.max():.2e}, largest error {dw.max():.2e}", flush=True)
     assert np.all(dw <= wb), f"weight error {dw.max():.3e} (worst excess {(dw - wb).max():.3e})"
     da = direction_error(g, ref)[landed]
     assert da.max() <= tol["dir"], f"direction error {da.max():.3e} rad"
@@ -250,9 +249,7 @@ def test_fluorescence_fp32_split(fluor_run):
     # statuses may differ only for photons emitted within float rounding of horizontal
     diff = g["status"] != ref["status"]
     assert np.all(np.abs(ref["ue"][diff, 2]) < 1e-6)
-    steep = np.abs(ref["ue"][:, 2]) >= HORIZON_COS
-    check_propagated(g, ref, TOL32, mask=~diff & steep)
-    check_propagated(g, ref, TOL32_HORIZON, mask=~diff & ~steep)
+    check_propagated(g, ref, TOL32, mask=~diff)
 
 
 # ------------------------------------------------------------------- sinks --
