@@ -772,7 +772,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
       sk.pz[slot_q] = p.z;
       ((T*)sk.pux)[slot_q] = p.ux;
       ((T*)sk.puy)[slot_q] = p.uy;
-      sk.puz[slot_q] = p.status == PHOTON_LANDED ? (double)p.uz : p.uzd;
+      sk.puz[slot_q] = (double)p.uz;
       ((T*)sk.plam)[slot_q] = p.lambda;
       ((T*)sk.pw)[slot_q] = p.w;
       sk.pt[slot_q] = p.t;
