@@ -1471,6 +1471,8 @@ __global__ __launch_bounds__(1024) void k_defer_scan(const unsigned long long* _
   }
 }
 
+constexpr int kDeferOther = 0, kDeferSplat = 1, kDeferRadial = 2;
+
 // Double pass over the near-horizon rays queued by the float kernel: each is
 // regenerated in double from its counter-based random numbers and carried
 // through propagation and collection in double. The queues of all blocks
@@ -1478,7 +1480,10 @@ __global__ __launch_bounds__(1024) void k_defer_scan(const unsigned long long* _
 // the threads.
 // Built for two waves per SIMD: the double evaluation needs more than 256
 // registers, and at one wave per SIMD its latency is exposed.
-template <int BS>
+// SINK: the sink class of the run (kDeferSplat, kDeferRadial, or
+// kDeferOther for the plane, telescopes and grid), one instance each, so
+// that each carries only its own sink's registers.
+template <int BS, int SINK>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_deferred(FusedArgs A) {
   __shared__ uint64_t s_thr[PHOTON_MAX_LINES];
   __shared__ double s_lines[PHOTON_MAX_LINES];
@@ -1521,7 +1526,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) void k_
     Photon<double> p;
     generate<double>(c, e.y, A.g, A.k0, A.k1, s_thr, s_lines, p);
     propagate<double>(A.atm, s_lane, p);
-    const bool splat = A.sk.kind == kSinkSplat;
+    constexpr bool splat = SINK == kDeferSplat;
     if (splat) p.w *= splat_wscale<double>(A, s);
     // collected in the run's precision (float)
     Photon<float> pf;
@@ -1538,10 +1543,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2))) void k_
     pf.path = p.path;
     pf.status = p.status;
     int st;
-    if (splat)
+    if constexpr (SINK == kDeferSplat)
       st = sink_photon<float, true>(A.sk, s_tel, s_telf, n_over_c, pf, (uint32_t)s, e.y, true, 0, nullptr,
                                     nullptr, s_cand);
-    else if (A.sk.kind == PHOTON_SINK_RADIAL)
+    else if constexpr (SINK == kDeferRadial)
       st = sink_photon<float, false, true>(A.sk, s_tel, s_telf, n_over_c, pf, (uint32_t)s, e.y, true, 0,
                                            nullptr, nullptr, s_cand);
     else
@@ -2703,7 +2708,12 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   if (defer) {
     hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(1024), 0, st, (const unsigned long long*)A.defer_counts,
                        (int)grid, A.defer_cap, A.defer_pref);
-    hipLaunchKernelGGL((k_fused_deferred<256>), dim3((unsigned)grid), dim3(256), 0, st, A);
+    if (A.sk.kind == kSinkSplat)
+      hipLaunchKernelGGL((k_fused_deferred<256, kDeferSplat>), dim3((unsigned)grid), dim3(256), 0, st, A);
+    else if (A.sk.kind == PHOTON_SINK_RADIAL)
+      hipLaunchKernelGGL((k_fused_deferred<256, kDeferRadial>), dim3((unsigned)grid), dim3(256), 0, st, A);
+    else
+      hipLaunchKernelGGL((k_fused_deferred<256, kDeferOther>), dim3((unsigned)grid), dim3(256), 0, st, A);
     if (timed) {
       if (hipEventRecord(dev->t_ev[2], st) != hipSuccess) return fail(PHOTON_EHIP, "event record failed");
       dev->timed_defer = true;
