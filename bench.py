@@ -236,10 +236,12 @@ def every_kth(n, target, per_segment):
 
 
 # --------------------------------------------------------------- workloads --
-def fused_form(name, seg, a, kind, em, seed, prec, sink_fn, args, tun=None, mode=0):
+def fused_form(name, seg, a, kind, em, seed, prec, sink_fn, args, tun=None, mode=16):
     """One workload in one precision: autotuned launch shape (unless given),
     the whole step captured in a graph and timed, the persistent kernel
-    timed alone at the same shape, the sink's results."""
+    timed alone at the same shape, the sink's results. mode: the fused
+    kernel instance's template mode (16: Cherenkov into telescopes, 8:
+    fluorescence into the grid)."""
     import torch
 
     from paper_2309_15861_amd import photon as ph
