@@ -240,7 +240,7 @@ def fused_form(name, seg, a, kind, em, seed, prec, sink_fn, args, tun=None, mode
     """One workload in one precision: autotuned launch shape (unless given),
     the whole step captured in a graph and timed, the persistent kernel
     timed alone at the same shape, the sink's results. mode: the fused
-    kernel instance's template mode (16: Cherenkov into telescopes, 8:
+    kernel instance's template mode (16: Cherenkov into telescopes, 40:
     fluorescence into the grid)."""
     import torch
 
@@ -439,7 +439,7 @@ def fluorescence_grid(args):
     out = dict(workload="fluorescence: 1e5 segments 5..30 km, dE/dx 1..10 MeV/m, 10 photons/MeV, 21 lines, "
                         "isotropic; 64 x 64 grid of 10 m cells at 2.2 km", segments=len(seg["x0"]))
     for name, prec in (("fp32", ph.FP32), ("fp64", ph.FP64)):
-        r, *_ = fused_form("fluorescence", seg, a, "fluor", em, 3, prec, grid_sink(g), args, mode=8)
+        r, *_ = fused_form("fluorescence", seg, a, "fluor", em, 3, prec, grid_sink(g), args, mode=40)
         if not args.no_errors:
             rows = every_kth(len(seg["x0"]), 1e6, r["photons"] / len(seg["x0"]))
             r["error_vs_oracle"] = sampled_errors(seg, a, "fluor", em, 3, prec, rows, ph.tuning(*r["tuning"]),

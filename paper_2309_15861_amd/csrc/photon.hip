@@ -731,7 +731,7 @@ struct HitStageLds<true> {
 // carry none of their code). lds_acc: the block's LDS accumulator (the
 // splat grid, or the radial bins as count, weight, w t), or NULL to add to
 // the global arrays directly.
-template <typename T, bool SPLAT = false, bool RADIAL = false, bool TEL_ONLY = false>
+template <typename T, bool SPLAT = false, bool RADIAL = false, bool TEL_ONLY = false, bool GRID_ONLY = false>
 __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel)[4], const float (*telf)[4],
                                            double n_over_c, Photon<T>& p,
                                            uint32_t seg_row, uint32_t j, bool active, uint64_t slot_q,
@@ -765,7 +765,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
         st = PHOTON_OFFGRID;
       }
     }
-  } else if (!TEL_ONLY && sk.kind == PHOTON_SINK_PLANE) {
+  } else if (!TEL_ONLY && !GRID_ONLY && sk.kind == PHOTON_SINK_PLANE) {
     if (active && slot_q < (uint64_t)sk.plane_capacity) {
       ((T*)sk.px)[slot_q] = p.x;
       ((T*)sk.py)[slot_q] = p.y;
@@ -781,7 +781,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
       sk.pj[slot_q] = j;
       sk.pstatus[slot_q] = p.status;
     }
-  } else if (TEL_ONLY || sk.kind == PHOTON_SINK_TELESCOPES) {
+  } else if (!GRID_ONLY && (TEL_ONLY || sk.kind == PHOTON_SINK_TELESCOPES)) {
     int k = -1;
     T s_hit = (T)0;
     if (active && st == PHOTON_LANDED) {
@@ -862,7 +862,7 @@ __device__ __forceinline__ int sink_photon(const SinkDev& sk, const double (*tel
         }
       }
     }
-  } else if (!TEL_ONLY && sk.kind == PHOTON_SINK_GRID) {
+  } else if (GRID_ONLY || (!TEL_ONLY && sk.kind == PHOTON_SINK_GRID)) {
     if (active && st == PHOTON_LANDED) {
       const double fx = floor(((double)p.x - sk.x_min) / sk.cell);
       const double fy = floor(((double)p.y - sk.y_min) / sk.cell);
@@ -975,7 +975,7 @@ __device__ __forceinline__ T splat_wscale(const FusedArgs& A, int64_t s) {
 // Kernel instances (MODE bits): the sink of the differentiable form, the
 // radial profile sink, the correction-table propagation, fluorescence
 // emission (else Cherenkov). Each carries only its own code.
-constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8, kMTel = 16;
+constexpr int kMSplat = 1, kMRadial = 2, kMTable = 4, kMFluo = 8, kMTel = 16, kMGrid = 32;
 
 // Float instances are built for the waves per SIMD that their LDS allows:
 // six of 256 threads (six blocks of under 26.6 KB per CU), four of 512.
@@ -998,6 +998,7 @@ void k_fused(FusedArgs A) {
   constexpr bool CHER = (MODE & kMFluo) == 0;
   // the telescope sink only (its instance carries no plane or grid code)
   constexpr bool TEL = (MODE & kMTel) != 0;
+  constexpr bool GRIDS = (MODE & kMGrid) != 0;  // the grid sink only
   // float SPLAT: the block's grid in 32-bit LDS cells with carries into the
   // global grid, small enough for two blocks per CU
   constexpr bool SPLAT32 = SPLAT && sizeof(T) == 4;
@@ -1285,7 +1286,7 @@ void k_fused(FusedArgs A) {
                 if (!in) st_out = PHOTON_OFFGRID;
               }
             } else {
-              st_out = sink_photon<T, SPLAT, RADIAL, TEL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, qq,
+              st_out = sink_photon<T, SPLAT, RADIAL, TEL, GRIDS>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, qq,
                                                      stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
             }
           }
@@ -1377,7 +1378,7 @@ void k_fused(FusedArgs A) {
                     if (!in) st_out = PHOTON_OFFGRID;
                   }
                 } else {
-                  st_out = sink_photon<T, SPLAT, RADIAL, TEL>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, qq,
+                  st_out = sink_photon<T, SPLAT, RADIAL, TEL, GRIDS>(A.sk, s_tel, s_telf, n_over_c, p, (uint32_t)s, j, true, qq,
                                                          stage_hits ? s_hs.get() : nullptr, lds_acc, s_cand);
                 }
               }
@@ -2521,6 +2522,10 @@ const void* fused_instance(int mode) {
       case kMTel | kMTable: return (const void*)k_fused<T, BS, kMTel | kMTable>;
       case kMTel | kMFluo: return (const void*)k_fused<T, BS, kMTel | kMFluo>;
       case kMTel | kMFluo | kMTable: return (const void*)k_fused<T, BS, kMTel | kMFluo | kMTable>;
+      case kMGrid: return (const void*)k_fused<T, BS, kMGrid>;
+      case kMGrid | kMTable: return (const void*)k_fused<T, BS, kMGrid | kMTable>;
+      case kMGrid | kMFluo: return (const void*)k_fused<T, BS, kMGrid | kMFluo>;
+      case kMGrid | kMFluo | kMTable: return (const void*)k_fused<T, BS, kMGrid | kMFluo | kMTable>;
       default: return (const void*)k_fused<T, BS, 0>;
     }
   }
@@ -2655,9 +2660,11 @@ int launch_fused_bs(const SegView& sv, int64_t n, const AtmDev& atm, const GenPa
   const bool radial = !SPLAT && sk.kind == PHOTON_SINK_RADIAL;
   const bool table = !SPLAT && atm.tcorr != nullptr;
   const bool tel = !SPLAT && sk.kind == PHOTON_SINK_TELESCOPES;
+  const bool grid_only = !SPLAT && sk.kind == PHOTON_SINK_GRID;
   const int mode = SPLAT ? kMSplat
                          : ((radial ? kMRadial : 0) | (table ? kMTable : 0) |
-                            (g.kind == PHOTON_FLUORESCENCE ? kMFluo : 0) | (tel ? kMTel : 0));
+                            (g.kind == PHOTON_FLUORESCENCE ? kMFluo : 0) | (tel ? kMTel : 0) |
+                            (grid_only ? kMGrid : 0));
   // the slot map of a chunk's piece holds kMaxChunk (splat: kMaxChunkSplat) photons
   if (chunk < 1 || chunk > (SPLAT ? kMaxChunkSplat : kMaxChunk))
     return fail(PHOTON_EINVAL, "fused chunk %lld outside 1..%d", (long long)chunk, SPLAT ? kMaxChunkSplat : kMaxChunk);
